@@ -1,0 +1,252 @@
+"""Seeded synthetic inputs for the DDM Helmholtz solver and its oracle.
+
+This module generates problem data only -- media k(x)^2, sources f and the
+scalar problem parameters -- and holds none of the method's arithmetic (no
+operator, cut-off, transfer or solve).  Both the CPU oracle (tests) and the HIP
+library (tests, bench) are fed from here.
+
+Grid convention (shared problem definition): per axis the physical interval
+[0, L] has M cells of size h = L / M; the global unknowns are the nodes
+g = -n_pml+1 ... M+n_pml-1 (x_g = g h), i.e. M + 2 n_pml - 1 of them, the
+outer n_pml-1 on each side lying in the PML; arrays are C-ordered
+[rhs][z][y][x].
+
+The paper (Sec. 4) uses analytic sources (a Gaussian of unit mass and an
+approximate delta shot) and constant or layered media whose velocity profile is
+only shown in a figure; the layered media below are synthetic stand-ins.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+BASE_SEED = 180704180
+
+
+def sigma0_for_reflection(R: float, k_ref: float, delta: float) -> float:
+    """PML strength for a quadratic profile sigma0 (t/delta)^2 and stretch
+    alpha = 1 + i sigma: a normally incident wave crosses the layer twice and
+    is damped by exp(-2 k sigma0 delta / 3); solve that for R."""
+    return 3.0 * math.log(1.0 / R) / (2.0 * k_ref * delta)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    dim: int
+    M: Tuple[int, ...]
+    L: float
+    omega: float
+    n_pml: int
+    n_ov: int
+    N: Tuple[int, ...]
+    sigma0: float
+    k2: np.ndarray            # global unknown grid, float64
+    f: np.ndarray             # [nrhs, *grid], complex128
+    c_min: float = 1.0
+    c_max: float = 1.0
+    notes: str = ""
+
+    @property
+    def h(self) -> float:
+        return self.L / self.M[0]
+
+    @property
+    def nrhs(self) -> int:
+        return self.f.shape[0]
+
+    @property
+    def grid_shape(self) -> Tuple[int, ...]:
+        return tuple(m + 2 * self.n_pml - 1 for m in reversed(self.M))
+
+    def describe(self) -> dict:
+        return dict(name=self.name, dim=self.dim, M=list(self.M), N=list(self.N), n_pml=self.n_pml,
+                    n_ov=self.n_ov, omega_over_2pi=self.omega / (2 * math.pi), sigma0=self.sigma0,
+                    nrhs=self.nrhs, c_min=self.c_min, c_max=self.c_max)
+
+
+def node_coords(M: int, n_pml: int, h: float) -> np.ndarray:
+    g = np.arange(-n_pml + 1, M + n_pml, dtype=np.float64)
+    return g * h
+
+
+def _mesh(dim: int, M: Sequence[int], n_pml: int, h: float):
+    axes = [node_coords(M[d], n_pml, h) for d in range(dim)]
+    # C order [z][y][x]: reverse the axis list for meshgrid(indexing="ij")
+    grids = np.meshgrid(*reversed(axes), indexing="ij")
+    return list(reversed(grids))  # [X, Y(, Z)] each shaped like the grid
+
+
+def gaussian_source(dim: int, M, n_pml: int, h: float, L: float, centre, s: float) -> np.ndarray:
+    """Unit-mass Gaussian (2 pi s^2)^(-dim/2) exp(-|x - x0|^2 / (2 s^2)),
+    sampled at physical nodes (0 <= x <= L) and zero in the PML."""
+    X = _mesh(dim, M, n_pml, h)
+    r2 = sum((X[d] - centre[d]) ** 2 for d in range(dim))
+    f = (2 * math.pi * s * s) ** (-dim / 2.0) * np.exp(-r2 / (2 * s * s))
+    inside = np.ones_like(f, dtype=bool)
+    for d in range(dim):
+        inside &= (X[d] >= -1e-12) & (X[d] <= L + 1e-12)
+    return np.where(inside, f, 0.0).astype(np.complex128)
+
+
+def paper_gaussian_source(dim: int, M, n_pml: int, h: float, L: float, centre, k: float) -> np.ndarray:
+    """The paper's Gaussian sources of Sec. 4.1: 16 k^2/pi^3 exp(-(4k/pi)^2 r^2)
+    in 2D, 64 k^3/pi^(9/2) exp(-(4k/pi)^2 r^2) in 3D (both of unit mass)."""
+    X = _mesh(dim, M, n_pml, h)
+    r2 = sum((X[d] - centre[d]) ** 2 for d in range(dim))
+    amp = 16 * k * k / math.pi ** 3 if dim == 2 else 64 * k ** 3 / math.pi ** 4.5
+    f = amp * np.exp(-((4 * k / math.pi) ** 2) * r2)
+    return f.astype(np.complex128)
+
+
+def delta_shot(dim: int, M, n_pml: int, h: float, node) -> np.ndarray:
+    """Approximate delta source 1/h^dim at one physical node (Sec. 4.2)."""
+    shape = tuple(m + 2 * n_pml - 1 for m in reversed(M))
+    f = np.zeros(shape, dtype=np.complex128)
+    idx = tuple(int(node[d]) + n_pml - 1 for d in reversed(range(dim)))
+    f[idx] = 1.0 / h ** dim
+    return f
+
+
+def constant_k2(dim: int, M, n_pml: int, k: float) -> np.ndarray:
+    shape = tuple(m + 2 * n_pml - 1 for m in reversed(M))
+    return np.full(shape, k * k, dtype=np.float64)
+
+
+def layered_velocity(dim: int, M, n_pml: int, h: float, L: float, rng: np.random.Generator,
+                     n_layers: int = 8, v_lo: float = 1.5, v_hi: float = 4.5, pert: float = 0.10,
+                     smooth_cells: float = 16.0) -> np.ndarray:
+    """Synthetic layered medium: n_layers flat layers in the last axis (depth),
+    interfaces at sorted uniform depths, layer velocities uniform in
+    [v_lo, v_hi], times (1 + pert * p) with p white noise smoothed by a
+    Gaussian of std smooth_cells cells and normalised to unit std, clipped to
+    [v_lo, v_hi].  Constant extension into the PML (coordinates clamped)."""
+    from scipy.ndimage import gaussian_filter
+
+    depth = np.sort(rng.uniform(0.0, L, size=n_layers - 1))
+    vel = rng.uniform(v_lo, v_hi, size=n_layers)
+    X = _mesh(dim, M, n_pml, h)
+    zc = np.clip(X[dim - 1], 0.0, L)
+    layer = np.searchsorted(depth, zc)
+    c = vel[layer]
+    # perturbation on the physical nodes, then clamp-extended
+    phys_shape = tuple(m + 1 for m in reversed(M))
+    p = rng.standard_normal(phys_shape)
+    p = gaussian_filter(p, sigma=smooth_cells, mode="reflect")
+    p /= max(p.std(), 1e-300)
+    idx = []
+    for d in reversed(range(dim)):
+        g = np.arange(-n_pml + 1, M[d] + n_pml)
+        idx.append(np.clip(g, 0, M[d]))
+    pe = p[np.ix_(*idx)]
+    c = np.clip(c * (1.0 + pert * pe), v_lo, v_hi)
+    return c
+
+
+# ---------------------------------------------------------------------------
+# The five benchmark configurations (seed = BASE_SEED + config index).
+# ---------------------------------------------------------------------------
+
+def config1() -> Workload:
+    """2D constant medium, omega = 2 pi 8 (10 ppw), M = 80, PML 10 cells,
+    R = 1e-6, 2x2 subdomains, overlap 4, one Gaussian (s = 2h) at the centre."""
+    M, n_pml, L = 80, 10, 1.0
+    h = L / M
+    omega = 2 * math.pi * 8
+    k = omega
+    s0 = sigma0_for_reflection(1e-6, k, n_pml * h)
+    k2 = constant_k2(2, (M, M), n_pml, k)
+    f = gaussian_source(2, (M, M), n_pml, h, L, (0.5, 0.5), 2 * h)[None]
+    return Workload("cfg1-2d-80-2x2", 2, (M, M), L, omega, n_pml, 4, (2, 2), s0, k2, f)
+
+
+def config2(nrhs: int = 4) -> Workload:
+    """2D constant medium, M = 1024 (10 ppw, omega = 2 pi 102.4), PML 16,
+    8x8 subdomains of 128^2, overlap 8, nrhs seeded Gaussians (s = 2h) with
+    centres uniform in [0.1, 0.9]^2."""
+    M, n_pml, L = 1024, 16, 1.0
+    h = L / M
+    omega = 2 * math.pi * 102.4
+    k = omega
+    s0 = sigma0_for_reflection(1e-6, k, n_pml * h)
+    k2 = constant_k2(2, (M, M), n_pml, k)
+    rng = np.random.default_rng(BASE_SEED + 2)
+    centres = rng.uniform(0.1, 0.9, size=(nrhs, 2))
+    f = np.stack([gaussian_source(2, (M, M), n_pml, h, L, tuple(c), 2 * h) for c in centres])
+    return Workload("cfg2-2d-1024-8x8", 2, (M, M), L, omega, n_pml, 8, (8, 8), s0, k2, f,
+                    notes="centres=%s" % np.round(centres, 4).tolist())
+
+
+def config3(nrhs: int = 16, M: int = 2048, N: int = 16) -> Workload:
+    """2D layered medium (8 layers, 1.5-4.5, 10% smoothed perturbation),
+    8 ppw at c = 1.5, PML 20, 16x16 subdomains, overlap 8, nrhs Gaussians."""
+    n_pml, L = 20, 1.0
+    h = L / M
+    omega = 2 * math.pi * 1.5 / (8 * h)
+    rng = np.random.default_rng(BASE_SEED + 3)
+    c = layered_velocity(2, (M, M), n_pml, h, L, rng, smooth_cells=16.0 * M / 2048)
+    k2 = (omega / c) ** 2
+    s0 = sigma0_for_reflection(1e-6, omega / 4.5, n_pml * h)
+    centres = rng.uniform(0.1, 0.9, size=(nrhs, 2))
+    f = np.stack([gaussian_source(2, (M, M), n_pml, h, L, tuple(cc), 2 * h) for cc in centres])
+    return Workload("cfg3-2d-%d-%dx%d-layered" % (M, N, N), 2, (M, M), L, omega, n_pml, 8, (N, N), s0,
+                    k2, f, c_min=float(c.min()), c_max=float(c.max()))
+
+
+def config5(M: int = 96, N: int = 3, n_pml: int = 6, n_ov: int = 2) -> Workload:
+    """3D constant medium, M = 96 (10 ppw, omega = 2 pi 9.6), PML 6, 3x3x3
+    subdomains, overlap 2, Gaussian (s = 2h) at the centre."""
+    L = 1.0
+    h = L / M
+    omega = 2 * math.pi * M / 10.0
+    k = omega
+    s0 = sigma0_for_reflection(1e-6, k, n_pml * h)
+    k2 = constant_k2(3, (M, M, M), n_pml, k)
+    f = gaussian_source(3, (M, M, M), n_pml, h, L, (0.5, 0.5, 0.5), 2 * h)[None]
+    return Workload("cfg5-3d-%d-%dx%dx%d" % (M, N, N, N), 3, (M, M, M), L, omega, n_pml, n_ov, (N, N, N),
+                    s0, k2, f)
+
+
+def small_2d(M: int = 32, N=(2, 2), n_pml: int = 4, n_ov: int = 3, ppw: float = 10.0, nrhs: int = 1,
+             layered: bool = False, seed: int = 0) -> Workload:
+    """Small 2D problem for parity tests (oracle finishes in seconds)."""
+    L = 1.0
+    h = L / M
+    rng = np.random.default_rng(BASE_SEED + 100 + seed)
+    if layered:
+        c = layered_velocity(2, (M, M), n_pml, h, L, rng, n_layers=4, smooth_cells=2.0)
+        omega = 2 * math.pi * float(c.min()) / (ppw * h)
+        k2 = (omega / c) ** 2
+        kref = omega / float(c.max())
+    else:
+        omega = 2 * math.pi / (ppw * h)
+        k2 = constant_k2(2, (M, M), n_pml, omega)
+        kref = omega
+        c = np.ones(1)
+    s0 = sigma0_for_reflection(1e-6, kref, n_pml * h)
+    centres = rng.uniform(0.15, 0.85, size=(nrhs, 2))
+    f = np.stack([gaussian_source(2, (M, M), n_pml, h, L, tuple(cc), 2 * h) for cc in centres])
+    return Workload("small2d-%d-%dx%d" % (M, N[0], N[1]), 2, (M, M), L, omega, n_pml, n_ov, tuple(N), s0,
+                    k2, f, c_min=float(c.min()), c_max=float(c.max()))
+
+
+def small_3d(M: int = 16, N=(2, 2, 2), n_pml: int = 3, n_ov: int = 2, ppw: float = 8.0, nrhs: int = 1,
+             seed: int = 0) -> Workload:
+    L = 1.0
+    h = L / M
+    omega = 2 * math.pi / (ppw * h)
+    k2 = constant_k2(3, (M, M, M), n_pml, omega)
+    s0 = sigma0_for_reflection(1e-6, omega, n_pml * h)
+    rng = np.random.default_rng(BASE_SEED + 200 + seed)
+    centres = rng.uniform(0.2, 0.8, size=(nrhs, 3))
+    f = np.stack([gaussian_source(3, (M, M, M), n_pml, h, L, tuple(cc), 2 * h) for cc in centres])
+    return Workload("small3d-%d" % M, 3, (M, M, M), L, omega, n_pml, n_ov, tuple(N), s0, k2, f)
+
+
+def random_field(shape, seed: int) -> np.ndarray:
+    """Seeded complex normal field (for operator and solve parity tests)."""
+    rng = np.random.default_rng(BASE_SEED + 1000 + seed)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex128)
