@@ -1,0 +1,188 @@
+/*
+ * ddm.h -- C-ABI of libddm, an MI355X (gfx950) implementation of the additive
+ * overlapping domain decomposition method (DDM) for the Helmholtz equation of
+ * W. Leng and L. Ju, "An Additive Overlapping Domain Decomposition Method for
+ * the Helmholtz Equation" (arXiv 1807.04180).
+ *
+ * Problem (Sec. 1 eq. helm, Sec. 3.1 eq. PMLweak0): the truncated PML problem
+ *     J^{-1} div(A grad u) + k(x)^2 u = f   on the box extended by the PML,
+ *     u = 0 on its boundary,
+ * with A = diag(alpha_2/alpha_1, alpha_1/alpha_2) (3D analogue), J = prod
+ * alpha_j, alpha_j = 1 + i sigma_j (Sec. 2.1), discretised by the 5-point
+ * (2D) / 7-point (3D) finite-difference scheme on a uniform mesh (Sec. 4).
+ *
+ * Grid: per axis the physical interval [0, M h] has M cells; the unknowns
+ * are the nodes g = -n_pml+1 .. M+n_pml-1 (M + 2 n_pml - 1 of them) with
+ * Dirichlet nodes at g = -n_pml and g = M + n_pml, and sigma(x) =
+ * sigma0 (t/n_pml)^2, t = distance in cells outside [0, M].  Global vectors
+ * are row-major [nrhs][z][y][x] over the unknowns ("nglob" entries per RHS).
+ *
+ * Partition (Sec. 2.2, Sec. 3.1): N[d] subdomains per axis, cores of
+ * C = M/N cells (half-open; the first and last also hold the global PML);
+ * every interior side of a subdomain is extended by n_ov overlap cells with
+ * sigma = 0 and n_pml PML cells (the shifted profile of eq. PMLprofile).
+ * "Packed" vectors hold one vector per subdomain box: [nrhs][subdomain a]
+ * [box, x fastest]; ddm_geometry gives each box and its offset.
+ *
+ * Every pointer argument named f, u, g, uhat, U, r, out is a DEVICE pointer
+ * (HIP global memory, e.g. from a torch tensor), complex128 interleaved;
+ * relres / norms / info are HOST pointers.  The caller owns all of them;
+ * the library owns its factors and workspaces (freed by ddm_destroy).  All
+ * work is enqueued on the stream given to ddm_setup; calls that return host
+ * values synchronise that stream before returning.
+ *
+ * Errors: every call returns 0 on success, a negative code on a hard error
+ * (nothing useful was written) and a positive code on a soft one (outputs
+ * hold the best result reached).  ddm_last_error gives a message.  No C++
+ * exception crosses this boundary.
+ */
+#ifndef DDM_H
+#define DDM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DDM_OK = 0,
+    DDM_EINVAL = -1,      /* bad argument, layout or non-finite input         */
+    DDM_ENOMEM = -2,      /* device allocation failed or HBM budget exceeded  */
+    DDM_ESINGULAR = -3,   /* zero / tiny pivot in a subdomain block          */
+    DDM_EHIP = -4,        /* HIP runtime error                                */
+    DDM_ESTATE = -5,      /* call out of order (e.g. iterate before factor)  */
+    DDM_ENOCONV = 1,      /* tolerance not reached within maxiter            */
+    DDM_EDIVERGED = 2     /* residual grew by more than 1e6 over its minimum */
+};
+
+typedef enum { DDM_FP64 = 0, DDM_MIXED = 1 } ddm_precision;
+typedef enum { DDM_STATIONARY = 0, DDM_FGMRES = 1 } ddm_method;
+
+typedef struct {
+    int dim;                  /* 2 or 3                                          */
+    int M[3];                 /* interior cells per axis (unused axes ignored)   */
+    double h;                 /* mesh size (equal on all axes)                   */
+    int n_pml;                /* PML cells, >= 2                                  */
+    double sigma0;            /* PML strength (alpha = 1 + i sigma), >= 0        */
+    int N[3];                 /* subdomains per axis; M[d] % N[d] == 0            */
+    int n_ov;                 /* overlap cells (the d~ of Sec. 2.2), >= 2;
+                                 core width M/N >= n_ov + 2 when N > 1          */
+    ddm_precision precision;  /* DDM_FP64: everything in complex128.
+                                 DDM_MIXED: subdomain factors, local solves and
+                                 transfers in complex64; residual, assembly and
+                                 the outer Krylov / refinement in FP64.          */
+    size_t hbm_budget_bytes;  /* 0 = no limit; else ddm_setup refuses a plan
+                                 larger than this (DDM_ENOMEM)                   */
+} ddm_problem;
+
+typedef struct {
+    ddm_method method;   /* DDM_STATIONARY: Algorithm 3.1 continued as an
+                            iterative solver (Sec. 4.2.1); DDM_FGMRES: flexible
+                            GMRES right-preconditioned by K DDM steps
+                            (Sec. 4.2.2)                                       */
+    double tol;          /* stop when ||f - L u||_2 / ||f||_2 <= tol (per RHS) */
+    int maxiter;         /* max DDM steps (stationary) / Arnoldi steps (FGMRES)*/
+    int restart;         /* FGMRES restart length (e.g. 30)                    */
+    int K;               /* DDM steps per preconditioner application; 0 means
+                            N1 + N2 (+ N3)                                     */
+    int refine_every;    /* DDM_MIXED stationary: restart the c64 DDM on the
+                            FP64 residual after this many steps without a 2x
+                            gain (0 = library default)                         */
+} ddm_solve_opts;
+
+typedef struct {
+    int iters;           /* DDM steps (stationary) or Arnoldi steps (FGMRES)  */
+    int local_solves;    /* local solves per subdomain (n_Local_Solve)         */
+    double relres;       /* final FP64 relative residual                      */
+    double seconds;      /* wall time of the solve                            */
+    int status;          /* DDM_OK / DDM_ENOCONV / DDM_EDIVERGED for this RHS */
+} ddm_rhs_info;
+
+typedef struct ddm_handle ddm_handle;
+
+/* Device bytes that ddm_setup + ddm_factor will allocate for at most
+ * nrhs_max right-hand sides per call (factors + workspaces), for admission
+ * control.  Returns DDM_EINVAL for an invalid problem. */
+int ddm_memory_required(const ddm_problem *p, int nrhs_max, size_t *bytes);
+
+/* Build the discretisation and partition tables (Sec. 3.1, Sec. 2.2) and
+ * allocate device memory for up to nrhs_max right-hand sides per call.
+ * k2: DEVICE pointer to k(x)^2 (double, nglob entries) -- copied, so the
+ * caller may free it afterwards.  stream: hipStream_t (NULL = default
+ * stream).  On success *out receives a handle. */
+int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream, ddm_handle **out);
+
+/* Factor every subdomain operator L_{i,j} of Algorithm 3.1 once (the direct
+ * local solver of Sec. 4) as a block-tridiagonal LU with grid-line (2D) /
+ * grid-plane (3D) blocks: S_l = D_l - C_l S_{l-1}^{-1} B_{l-1}, stored as
+ * W_l = S_l^{-1} (complex128 for DDM_FP64, complex64 for DDM_MIXED).
+ * Returns DDM_ESINGULAR if a block pivot vanishes. */
+int ddm_factor(ddm_handle *h);
+
+/* Run nsteps steps of Algorithm 3.1 from a zero state for nrhs sources f
+ * (nrhs x nglob) and write the DDM iterate u = sum_a beta_{0;a} U_a
+ * (eq. tsum) after the last step.  relres (host, nsteps x nrhs, may be NULL)
+ * receives ||f - L u|| / ||f|| after every step. */
+int ddm_iterate(ddm_handle *h, const void *f, void *u, int nrhs, int nsteps, double *relres);
+
+/* Solve L u = f to opts->tol with the DDM as iterative solver or as FGMRES
+ * preconditioner (Sec. 4.2).  info (host, nrhs entries, may be NULL) gets the
+ * per-RHS outcome.  Returns DDM_OK when every RHS converged, else the worst
+ * per-RHS status. */
+int ddm_solve(ddm_handle *h, const void *f, void *u, int nrhs, const ddm_solve_opts *opts,
+              ddm_rhs_info *info);
+
+/* Text of the last error on this handle (or of the last failed ddm_setup
+ * when h is NULL).  Valid until the next call on the handle. */
+const char *ddm_last_error(const ddm_handle *h);
+
+/* Release all device memory of the handle. */
+void ddm_destroy(ddm_handle *h);
+
+/* ---- geometry and single-row entry points (Sec. 2.2 / Alg. 3.1 steps) ---- */
+
+/* Sizes: out[0] = nglob, out[1] = packed size per RHS (sum of |E_a|),
+ * out[2] = number of subdomains, out[3] = factor bytes. */
+int ddm_sizes(const ddm_handle *h, long *out);
+
+/* Boxes of subdomain a in physical node indices: out[0..2] core low,
+ * out[3..5] core high, out[6..8] extended-box low, out[9..11] extended-box
+ * high (unused axes 0), out[12] packed offset, out[13] box size. */
+int ddm_geometry(const ddm_handle *h, int a, long *out);
+
+/* out = L_h u on the global grid (the 5/7-point PML operator). */
+int ddm_apply(ddm_handle *h, const void *u, void *out, int nrhs);
+
+/* r = f - L_h u (r may be NULL) and per-RHS squared 2-norms of r and f,
+ * summed in FP64 in a fixed order (host arrays, nrhs entries each). */
+int ddm_residual(ddm_handle *h, const void *f, const void *u, void *r, int nrhs,
+                 double *rnorm2, double *fnorm2);
+
+/* Step-1 sources: g_a = f restricted to the core of a (f_{i,j} of Sec. 2.2),
+ * written to the packed vector g (zero outside the cores). */
+int ddm_restrict_core(ddm_handle *h, const void *f, void *g, int nrhs);
+
+/* Local solves of one step: uhat_a = L_a^{-1} g_a for every subdomain a and
+ * RHS (packed in, packed out; may alias).  Requires ddm_factor.  With
+ * DDM_MIXED the solve runs in complex64 and is widened on output. */
+int ddm_local_solve(ddm_handle *h, const void *g, void *uhat, int nrhs);
+
+/* Source transfer of Sec. 2.2 / eq. talg_2: g_a = sum over the 8 (2D) / 26
+ * (3D) neighbours b of Psi_{b->a}(uhat_b), Psi_{b->a}(v) = -L_a(beta_{b->a}
+ * v) restricted to chi_{b->a}; edge / face neighbours read lag1, corner /
+ * edge neighbours lag2, 3D vertex neighbours lag3 (packed; NULL = zero). */
+int ddm_transfer(ddm_handle *h, const void *lag1, const void *lag2, const void *lag3, void *g,
+                 int nrhs);
+
+/* Assembly of eq. tsum: u = sum_a beta_{0;a} U_a (packed U in, global u out). */
+int ddm_assemble(ddm_handle *h, const void *U, void *u, int nrhs);
+
+/* Library version string. */
+const char *ddm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDM_H */

@@ -1,0 +1,684 @@
+// C-ABI of libddm: setup, factorisation, the DDM step loop of Algorithm 3.1
+// (as iterative solver and as FGMRES preconditioner, Sec. 4.2) and the
+// single-step entry points.  Host orchestration only; every O(unknowns)
+// operation runs in a HIP kernel on the handle's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cplx.h"
+#include "ddm_internal.h"
+
+using namespace ddm;
+
+namespace {
+
+std::string g_setup_error;
+
+struct HipFail {
+    hipError_t e;
+    const char *what;
+};
+
+#define HIPCHK(expr)                                        \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) throw HipFail{e_, #expr};     \
+    } while (0)
+
+int fail(ddm_handle *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    else g_setup_error = msg;
+    return code;
+}
+
+int hip_fail(ddm_handle *h, const HipFail &f) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "HIP error %d (%s) in %s", (int)f.e, hipGetErrorString(f.e), f.what);
+    return fail(h, f.e == hipErrorOutOfMemory ? DDM_ENOMEM : DDM_EHIP, buf);
+}
+
+template <typename T>
+void dalloc(ddm_handle *h, T **p, size_t count) {
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 16;
+    HIPCHK(hipMalloc((void **)p, bytes));
+    h->bytes += bytes;
+}
+
+size_t elem_size(bool mixed) { return mixed ? sizeof(float2) : sizeof(double2); }
+
+int norm_blocks(const Plan &P) { return (int)((P.nglob + 255) / 256); }
+
+constexpr int kDotBlocks = 256;
+
+size_t part_doubles(const Plan &P, int nrhs, int m) {
+    size_t a = 2 * (size_t)nrhs * norm_blocks(P);
+    size_t b = 2 * (size_t)(m + 1) * nrhs * kDotBlocks;
+    size_t c = (size_t)nrhs * 512;
+    return std::max(a, std::max(b, c));
+}
+
+// device bytes of a plan for nrhs right-hand sides (factors, tables and step
+// workspaces; the FGMRES basis for restart m if m > 0)
+size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
+    size_t es = elem_size(mixed);
+    size_t b = 0;
+    b += P.subs.size() * sizeof(SubDesc) + (P.coef.size() + P.gcoef.size()) * sizeof(Coef);
+    b += P.owner.size() * sizeof(int) + P.btab.size() * sizeof(double) + P.items.size() * sizeof(SolveItem);
+    b += (size_t)P.nglob * sizeof(double);                         // k2
+    b += (size_t)P.fel * es;                                       // factors
+    b += (size_t)P.nsub * P.bs_max * P.bs_max * sizeof(double2);   // FP64 factor scratch (freed after factor)
+    b += (size_t)(1 + P.ring) * nrhs * P.etot * es;                // g + ring
+    b += (size_t)nrhs * P.nglob * sizeof(double2);                 // residual / operator output
+    if (mixed) b += (size_t)nrhs * P.etot * sizeof(double2);       // widening scratch
+    b += part_doubles(P, nrhs, m > 0 ? m : 30) * sizeof(double);
+    if (m > 0) b += (size_t)(2 * m + 1) * nrhs * P.nglob * sizeof(double2) + (size_t)nrhs * P.nglob * sizeof(double2);
+    return b;
+}
+
+void free_all(ddm_handle *h) {
+    void *ptrs[] = {h->d_subs, h->d_coef, h->d_gcoef, h->d_owner, h->d_btab, h->d_k2, h->d_items, h->d_W,
+                    h->d_scratch, h->d_flags, h->d_g, h->d_ring[0], h->d_ring[1], h->d_ring[2], h->d_ring[3],
+                    h->d_r, h->d_wide, h->d_part, h->d_norm, h->d_active, h->d_V, h->d_Z, h->d_dots,
+                    h->d_coef_y};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->h_norm) (void)hipHostFree(h->h_norm);
+    if (h->h_dots) (void)hipHostFree(h->h_dots);
+}
+
+template <typename T>
+const T *ring_at(ddm_handle *h, int s) {  // uhat^s (s >= 1) or null for s <= 0
+    return s >= 1 ? (const T *)h->d_ring[s % h->plan.ring] : nullptr;
+}
+
+// Run nsteps steps of Algorithm 3.1 with source f (global, complex128) and
+// accumulate u += sum_a beta_{0;a} uhat^s_a after every step.  When check is
+// given it is called after each step with the per-RHS relative residuals and
+// may deactivate RHS (their u is frozen) or request a restart of the
+// recursion on a new source (refinement); it returns false to stop.
+template <typename T, typename Check>
+void run_steps(ddm_handle *h, const double2 *f, double2 *u, int nrhs, int nsteps, Check check) {
+    const Plan &P = h->plan;
+    const double2 *src = f;
+    int s = 0;
+    for (int it = 1; it <= nsteps; ++it) {
+        ++s;
+        T *g = (T *)h->d_g;
+        if (s == 1) HIPCHK((launch_restrict<double2, T>(h, src, g, nrhs)));
+        else HIPCHK((launch_transfer<T, T>(h, ring_at<T>(h, s - 1), ring_at<T>(h, s - 2), ring_at<T>(h, s - 3), g, nrhs)));
+        T *us = (T *)h->d_ring[s % P.ring];
+        HIPCHK(launch_local_solve<T>(h, g, us, nrhs));
+        HIPCHK(launch_assemble<T>(h, us, u, nrhs, true, h->d_active));
+        const double2 *restart_src = nullptr;
+        if (!check(it, &restart_src)) break;
+        if (restart_src) {
+            src = restart_src;
+            s = 0;
+        }
+    }
+}
+
+void set_active(ddm_handle *h, const std::vector<int> &act) {
+    HIPCHK(hipMemcpyAsync(h->d_active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+}
+
+// relres per RHS of u for source f; fills h->h_norm[0..2 nrhs)
+void residual_host(ddm_handle *h, const double2 *f, const double2 *u, double2 *r, int nrhs, std::vector<double> &rel,
+                   std::vector<double> *fn = nullptr) {
+    HIPCHK(launch_residual(h, f, u, r, nrhs, h->d_norm, h->d_norm + nrhs));
+    HIPCHK(hipMemcpyAsync(h->h_norm, h->d_norm, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    rel.resize(nrhs);
+    if (fn) fn->resize(nrhs);
+    for (int q = 0; q < nrhs; ++q) {
+        double rn = std::sqrt(h->h_norm[q]), fnq = std::sqrt(h->h_norm[nrhs + q]);
+        rel[q] = fnq > 0 ? rn / fnq : rn;
+        if (fn) (*fn)[q] = fnq;
+    }
+}
+
+int check_args(ddm_handle *h, int nrhs) {
+    if (!h) return DDM_EINVAL;
+    if (nrhs < 1 || nrhs > h->nrhs_max) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "nrhs=%d outside [1, %d]", nrhs, h->nrhs_max);
+        return fail(h, DDM_EINVAL, buf);
+    }
+    return DDM_OK;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// Stationary DDM (Sec. 4.2.1), FP64 or mixed with residual restarts
+// ---------------------------------------------------------------------------
+template <typename T>
+int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, const ddm_solve_opts &o,
+                     ddm_rhs_info *info) {
+    const Plan &P = h->plan;
+    double t0 = now_s();
+    HIPCHK(launch_fill_zero(u, (long long)nrhs * P.nglob * sizeof(double2), h->stream));
+    std::vector<int> act(nrhs, 1);
+    set_active(h, act);
+    std::vector<double> rel, fn, best(nrhs, 1e300), last_gain_rel(nrhs, 1.0);
+    std::vector<int> steps(nrhs, 0), status(nrhs, DDM_ENOCONV), since_gain(nrhs, 0);
+    std::vector<double> secs(nrhs, 0.0), final_rel(nrhs, 1.0);
+    int nsum = P.N[0] + P.N[1] + P.N[2] - (3 - P.dim);
+    int refine_every = o.refine_every > 0 ? o.refine_every : nsum;
+    double2 *rsrc = h->d_r;  // restart source (residual) lives in d_r
+    auto check = [&](int it, const double2 **restart) -> bool {
+        residual_host(h, f, u, nullptr, nrhs, rel, &fn);
+        bool all = true, changed = false;
+        bool stalled = false;
+        for (int q = 0; q < nrhs; ++q) {
+            if (!act[q]) continue;
+            steps[q] = it;
+            final_rel[q] = rel[q];
+            if (!std::isfinite(rel[q])) { status[q] = DDM_EDIVERGED; act[q] = 0; changed = true; continue; }
+            if (rel[q] <= o.tol) {
+                status[q] = DDM_OK; act[q] = 0; changed = true;
+                secs[q] = now_s() - t0;
+                continue;
+            }
+            if (rel[q] > 1e6 * best[q]) { status[q] = DDM_EDIVERGED; act[q] = 0; changed = true; continue; }
+            if (rel[q] < best[q]) best[q] = rel[q];
+            if (rel[q] < 0.5 * last_gain_rel[q]) { last_gain_rel[q] = rel[q]; since_gain[q] = 0; }
+            else if (++since_gain[q] >= refine_every) stalled = true;
+            all = false;
+        }
+        if (changed) set_active(h, act);
+        if (all || it >= o.maxiter) return false;
+        if (h->mixed && stalled) {
+            // iterative refinement: restart the complex64 recursion on the FP64
+            // residual r = f - L u; u keeps accumulating the corrections
+            HIPCHK(launch_residual(h, f, u, rsrc, nrhs, h->d_norm, h->d_norm + nrhs));
+            for (int q = 0; q < nrhs; ++q) { since_gain[q] = 0; last_gain_rel[q] = rel[q]; }
+            *restart = rsrc;
+        }
+        return true;
+    };
+    run_steps<T>(h, f, u, nrhs, o.maxiter, check);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    int worst = DDM_OK;
+    double t1 = now_s();
+    for (int q = 0; q < nrhs; ++q) {
+        if (status[q] != DDM_OK) secs[q] = t1 - t0;
+        if (info) {
+            info[q].iters = steps[q];
+            info[q].local_solves = steps[q];
+            info[q].relres = final_rel[q];
+            info[q].seconds = secs[q];
+            info[q].status = status[q];
+        }
+        if (status[q] > worst) worst = status[q];
+    }
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES(m) right-preconditioned by K DDM steps (Sec. 4.2.2), lockstep over
+// the RHS of a batch, classical Gram-Schmidt applied twice, FP64.
+// ---------------------------------------------------------------------------
+void ensure_krylov(ddm_handle *h, int m, int nrhs) {
+    if (h->d_V && h->krylov_m >= m && h->krylov_nrhs >= nrhs) return;
+    if (h->d_V) { HIPCHK(hipFree(h->d_V)); h->d_V = nullptr; }
+    if (h->d_Z) { HIPCHK(hipFree(h->d_Z)); h->d_Z = nullptr; }
+    if (h->d_dots) { HIPCHK(hipFree(h->d_dots)); h->d_dots = nullptr; }
+    if (h->d_coef_y) { HIPCHK(hipFree(h->d_coef_y)); h->d_coef_y = nullptr; }
+    if (h->h_dots) { HIPCHK(hipHostFree(h->h_dots)); h->h_dots = nullptr; }
+    long long n = h->plan.nglob;
+    size_t need = part_doubles(h->plan, std::max(nrhs, h->nrhs_max), m);
+    if (need > h->part_cap) {
+        HIPCHK(hipFree(h->d_part));
+        h->d_part = nullptr;
+        HIPCHK(hipMalloc((void **)&h->d_part, need * sizeof(double)));
+        h->part_cap = need;
+    }
+    HIPCHK(hipMalloc((void **)&h->d_V, (size_t)(m + 1) * nrhs * n * sizeof(double2)));
+    HIPCHK(hipMalloc((void **)&h->d_Z, (size_t)m * nrhs * n * sizeof(double2)));
+    HIPCHK(hipMalloc((void **)&h->d_dots, (size_t)3 * (m + 1) * nrhs * sizeof(double2)));
+    HIPCHK(hipMalloc((void **)&h->d_coef_y, (size_t)(m + 1) * nrhs * sizeof(double2)));
+    HIPCHK(hipHostMalloc((void **)&h->h_dots, (size_t)3 * (m + 1) * nrhs * sizeof(double2), hipHostMallocDefault));
+    h->krylov_m = m;
+    h->krylov_nrhs = nrhs;
+}
+
+template <typename T>
+int solve_fgmres(ddm_handle *h, const double2 *f, double2 *x, int nrhs, const ddm_solve_opts &o, ddm_rhs_info *info) {
+    using cd = std::complex<double>;
+    const Plan &P = h->plan;
+    const long long n = P.nglob;
+    const int m = o.restart > 0 ? o.restart : 30;
+    int K = o.K > 0 ? o.K : (P.N[0] + P.N[1] + P.N[2] - (3 - P.dim));
+    double t0 = now_s();
+    ensure_krylov(h, m, nrhs);
+    // V_j of RHS q at d_V + (j * nrhs + q) * n; vstride = nrhs * n, ld = n
+    const long long vstride = (long long)nrhs * n;
+    double2 *V = h->d_V, *Z = h->d_Z, *w = h->d_r;
+    HIPCHK(launch_fill_zero(x, (long long)nrhs * n * sizeof(double2), h->stream));
+    std::vector<int> done(nrhs, 0), its(nrhs, 0), status(nrhs, DDM_ENOCONV);
+    std::vector<double> fnorm(nrhs, 0.0), rel(nrhs, 1.0);
+    std::vector<cd> H((size_t)nrhs * (m + 1) * m), cs((size_t)nrhs * m), sn((size_t)nrhs * m), gv((size_t)nrhs * (m + 1));
+    std::vector<int> jr(nrhs), fin(nrhs);
+    std::vector<double2> yh((size_t)nrhs * m);
+    std::vector<int> ones(nrhs, 1);
+    int total = 0;
+    bool first = true;
+    while (true) {
+        // r0 = f - A x  ->  V_0, norms
+        std::vector<double> rr, ff;
+        residual_host(h, f, x, V, nrhs, rr, &ff);
+        if (first) {
+            for (int q = 0; q < nrhs; ++q) {
+                fnorm[q] = ff[q];
+                if (!std::isfinite(ff[q])) throw std::string("non-finite source");
+                if (fnorm[q] == 0) { done[q] = 1; status[q] = DDM_OK; rel[q] = 0; }
+            }
+            first = false;
+        }
+        bool all = true;
+        for (int q = 0; q < nrhs; ++q) {
+            if (done[q]) continue;
+            rel[q] = rr[q];
+            if (rr[q] <= o.tol) { done[q] = 1; status[q] = DDM_OK; continue; }
+            if (its[q] >= o.maxiter) continue;
+            all = false;
+        }
+        if (all || total >= o.maxiter) break;
+        // V_0 /= ||r0|| (scale factors = squared residual norms in d_norm)
+        HIPCHK(launch_scale(V, V, h->d_norm, n, nrhs, n, h->stream));
+        for (int q = 0; q < nrhs; ++q) {
+            jr[q] = 0;
+            fin[q] = done[q] || its[q] >= o.maxiter;
+            std::fill(gv.begin() + (size_t)q * (m + 1), gv.begin() + (size_t)(q + 1) * (m + 1), cd(0));
+            gv[(size_t)q * (m + 1)] = cd(std::sqrt(h->h_norm[q]), 0.0);
+        }
+        for (int j = 0; j < m; ++j) {
+            double2 *vj = V + j * vstride, *zj = Z + j * vstride;
+            // z_j = M_K(v_j): K DDM steps from a zero state, output sum beta0 U
+            set_active(h, ones);
+            HIPCHK(launch_fill_zero(zj, vstride * (long long)sizeof(double2), h->stream));
+            run_steps<T>(h, vj, zj, nrhs, K, [](int, const double2 **) { return true; });
+            HIPCHK(launch_apply(h, zj, w, nrhs));
+            double2 *h1 = h->d_dots, *h2 = h->d_dots + (size_t)(m + 1) * nrhs;
+            double *hn = (double *)(h->d_dots + (size_t)2 * (m + 1) * nrhs);
+            // dots are laid out [rhs][i] for i <= j
+            HIPCHK(launch_dots(V, j + 1, vstride, w, n, nrhs, n, h1, h->d_part, kDotBlocks, h->stream));
+            HIPCHK(launch_axpy_multi(w, V, j + 1, vstride, h1, -1.0, n, nrhs, n, h->stream));
+            HIPCHK(launch_dots(V, j + 1, vstride, w, n, nrhs, n, h2, h->d_part, kDotBlocks, h->stream));
+            HIPCHK(launch_axpy_multi(w, V, j + 1, vstride, h2, -1.0, n, nrhs, n, h->stream));
+            HIPCHK(launch_norm2(h, w, n, nrhs, n, hn));
+            HIPCHK(launch_scale(V + (j + 1) * vstride, w, hn, n, nrhs, n, h->stream));
+            HIPCHK(hipMemcpyAsync(h->h_dots, h->d_dots, (size_t)3 * (m + 1) * nrhs * sizeof(double2),
+                                  hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            ++total;
+            const double2 *H1 = h->h_dots, *H2 = h->h_dots + (size_t)(m + 1) * nrhs;
+            const double *HN = (const double *)(h->h_dots + (size_t)2 * (m + 1) * nrhs);
+            bool cycle_done = true;
+            for (int q = 0; q < nrhs; ++q) {
+                if (fin[q]) continue;
+                cd *Hq = &H[(size_t)q * (m + 1) * m];
+                for (int i = 0; i <= j; ++i)
+                    Hq[i * m + j] = cd(H1[q * (j + 1) + i].x + H2[q * (j + 1) + i].x,
+                                       H1[q * (j + 1) + i].y + H2[q * (j + 1) + i].y);
+                double hnq = std::sqrt(HN[q]);
+                Hq[(j + 1) * m + j] = cd(hnq, 0);
+                cd *c = &cs[(size_t)q * m], *sN = &sn[(size_t)q * m], *g = &gv[(size_t)q * (m + 1)];
+                for (int i = 0; i < j; ++i) {
+                    cd a = Hq[i * m + j], b = Hq[(i + 1) * m + j];
+                    Hq[i * m + j] = std::conj(c[i]) * a + std::conj(sN[i]) * b;
+                    Hq[(i + 1) * m + j] = -sN[i] * a + c[i] * b;
+                }
+                cd a = Hq[j * m + j], b = Hq[(j + 1) * m + j];
+                double rn = std::sqrt(std::norm(a) + std::norm(b));
+                if (rn == 0) { c[j] = 1; sN[j] = 0; }
+                else { c[j] = a / rn; sN[j] = b / rn; }
+                Hq[j * m + j] = rn;
+                Hq[(j + 1) * m + j] = 0;
+                g[j + 1] = -sN[j] * g[j];
+                g[j] = std::conj(c[j]) * g[j];
+                jr[q] = j + 1;
+                its[q] += 1;
+                double est = std::abs(g[j + 1]) / fnorm[q];
+                if (est <= o.tol || hnq == 0 || its[q] >= o.maxiter) fin[q] = 1;
+                else cycle_done = false;
+            }
+            if (cycle_done) break;
+        }
+        // x_q += Z y_q, y from the triangular system of the cycle
+        for (int q = 0; q < nrhs; ++q) {
+            std::vector<cd> y(m, cd(0));
+            int jq = done[q] ? 0 : jr[q];
+            cd *Hq = &H[(size_t)q * (m + 1) * m];
+            cd *g = &gv[(size_t)q * (m + 1)];
+            for (int i = jq - 1; i >= 0; --i) {
+                cd s = g[i];
+                for (int k = i + 1; k < jq; ++k) s -= Hq[i * m + k] * y[k];
+                y[i] = s / Hq[i * m + i];
+            }
+            for (int i = 0; i < m; ++i) yh[(size_t)q * m + i] = make_double2(y[i].real(), y[i].imag());
+        }
+        HIPCHK(hipMemcpyAsync(h->d_coef_y, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(launch_axpy_multi(x, Z, m, vstride, h->d_coef_y, 1.0, n, nrhs, n, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double t1 = now_s();
+    int worst = DDM_OK;
+    for (int q = 0; q < nrhs; ++q) {
+        if (info) {
+            info[q].iters = its[q];
+            info[q].local_solves = its[q] * K;
+            info[q].relres = rel[q];
+            info[q].seconds = t1 - t0;
+            info[q].status = status[q];
+        }
+        if (status[q] > worst) worst = status[q];
+    }
+    return worst;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char *ddm_version(void) { return "libddm 0.1 (gfx950, HIP)"; }
+
+const char *ddm_last_error(const ddm_handle *h) { return h ? h->err.c_str() : g_setup_error.c_str(); }
+
+int ddm_memory_required(const ddm_problem *p, int nrhs_max, size_t *bytes) {
+    if (!bytes || nrhs_max < 1) return fail(nullptr, DDM_EINVAL, "bytes must be non-null and nrhs_max >= 1");
+    Plan P;
+    std::string err;
+    int st = build_plan(p, &P, &err);
+    if (st) return fail(nullptr, st, err);
+    *bytes = plan_bytes(P, p->precision == DDM_MIXED, nrhs_max, 0);
+    return DDM_OK;
+}
+
+int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream, ddm_handle **out) {
+    if (!out || !k2 || nrhs_max < 1) return fail(nullptr, DDM_EINVAL, "out and k2 must be non-null, nrhs_max >= 1");
+    *out = nullptr;
+    ddm_handle *h = new (std::nothrow) ddm_handle();
+    if (!h) return fail(nullptr, DDM_ENOMEM, "host allocation failed");
+    std::string err;
+    int st = build_plan(p, &h->plan, &err);
+    if (st) { delete h; return fail(nullptr, st, err); }
+    h->prob = *p;
+    h->mixed = p->precision == DDM_MIXED;
+    h->nrhs_max = nrhs_max;
+    h->stream = (hipStream_t)stream;
+    const Plan &P = h->plan;
+    size_t need = plan_bytes(P, h->mixed, nrhs_max, 0);
+    if (p->hbm_budget_bytes > 0 && need > p->hbm_budget_bytes) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "plan needs %zu bytes, budget is %zu", need, p->hbm_budget_bytes);
+        delete h;
+        return fail(nullptr, DDM_ENOMEM, buf);
+    }
+    try {
+        // k2 must be finite
+        std::vector<double> hk2(P.nglob);
+        HIPCHK(hipMemcpy(hk2.data(), k2, P.nglob * sizeof(double), hipMemcpyDeviceToHost));
+        for (double v : hk2)
+            if (!std::isfinite(v)) { free_all(h); delete h; return fail(nullptr, DDM_EINVAL, "k2 has non-finite entries"); }
+        dalloc(h, &h->d_subs, P.subs.size());
+        dalloc(h, &h->d_coef, P.coef.size());
+        dalloc(h, &h->d_gcoef, P.gcoef.size());
+        dalloc(h, &h->d_owner, P.owner.size());
+        dalloc(h, &h->d_btab, P.btab.size());
+        dalloc(h, &h->d_items, P.items.size());
+        dalloc(h, &h->d_k2, (size_t)P.nglob);
+        dalloc(h, &h->d_flags, (size_t)P.nsub);
+        HIPCHK(hipMemcpy(h->d_subs, P.subs.data(), P.subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(h->d_coef, P.coef.data(), P.coef.size() * sizeof(Coef), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(h->d_gcoef, P.gcoef.data(), P.gcoef.size() * sizeof(Coef), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(h->d_owner, P.owner.data(), P.owner.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(h->d_btab, P.btab.data(), P.btab.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(h->d_items, P.items.data(), P.items.size() * sizeof(SolveItem), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(h->d_k2, hk2.data(), P.nglob * sizeof(double), hipMemcpyHostToDevice));
+        size_t es = elem_size(h->mixed);
+        HIPCHK(hipMalloc(&h->d_W, (size_t)P.fel * es));
+        h->bytes += (size_t)P.fel * es;
+        HIPCHK(hipMalloc(&h->d_g, (size_t)nrhs_max * P.etot * es));
+        for (int k = 0; k < P.ring; ++k) HIPCHK(hipMalloc(&h->d_ring[k], (size_t)nrhs_max * P.etot * es));
+        h->bytes += (size_t)(1 + P.ring) * nrhs_max * P.etot * es;
+        dalloc(h, &h->d_r, (size_t)nrhs_max * P.nglob);
+        if (h->mixed) dalloc(h, &h->d_wide, (size_t)nrhs_max * P.etot);
+        h->part_cap = part_doubles(P, nrhs_max, 30);
+        dalloc(h, &h->d_part, h->part_cap);
+        dalloc(h, &h->d_norm, (size_t)4 * nrhs_max);
+        dalloc(h, &h->d_active, (size_t)nrhs_max);
+        HIPCHK(hipHostMalloc((void **)&h->h_norm, 4 * nrhs_max * sizeof(double), hipHostMallocDefault));
+        std::vector<int> ones(nrhs_max, 1);
+        HIPCHK(hipMemcpy(h->d_active, ones.data(), nrhs_max * sizeof(int), hipMemcpyHostToDevice));
+    } catch (const HipFail &e) {
+        int code = hip_fail(nullptr, e);
+        free_all(h);
+        delete h;
+        return code;
+    }
+    *out = h;
+    return DDM_OK;
+}
+
+void ddm_destroy(ddm_handle *h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    free_all(h);
+    delete h;
+}
+
+int ddm_sizes(const ddm_handle *h, long *out) {
+    if (!h || !out) return DDM_EINVAL;
+    out[0] = (long)h->plan.nglob;
+    out[1] = (long)h->plan.etot;
+    out[2] = h->plan.nsub;
+    out[3] = (long)(h->plan.fel * elem_size(h->mixed));
+    return DDM_OK;
+}
+
+int ddm_geometry(const ddm_handle *h, int a, long *out) {
+    if (!h || !out || a < 0 || a >= h->plan.nsub) return DDM_EINVAL;
+    const SubDesc &s = h->plan.subs[a];
+    for (int d = 0; d < 3; ++d) {
+        out[d] = s.clo[d];
+        out[3 + d] = s.chi[d];
+        out[6 + d] = s.lo[d];
+        out[9 + d] = s.hi[d];
+    }
+    out[12] = (long)s.off;
+    out[13] = (long)s.nloc;
+    return DDM_OK;
+}
+
+int ddm_factor(ddm_handle *h) {
+    if (!h) return DDM_EINVAL;
+    const Plan &P = h->plan;
+    try {
+        if (!h->d_scratch) {
+            HIPCHK(hipMalloc((void **)&h->d_scratch, (size_t)P.nsub * P.bs_max * P.bs_max * sizeof(double2)));
+        }
+        if (h->mixed) HIPCHK(launch_factor<float2>(h));
+        else HIPCHK(launch_factor<double2>(h));
+        std::vector<int> flags(P.nsub);
+        HIPCHK(hipMemcpyAsync(flags.data(), h->d_flags, P.nsub * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        HIPCHK(hipFree(h->d_scratch));
+        h->d_scratch = nullptr;
+        for (int a = 0; a < P.nsub; ++a)
+            if (flags[a]) {
+                char buf[160];
+                int t = flags[a] - 1;
+                snprintf(buf, sizeof buf, "subdomain %d: pivot below threshold in block %d, column %d", a,
+                         t / P.subs[a].bs, t % P.subs[a].bs);
+                h->factored = false;
+                return fail(h, DDM_ESINGULAR, buf);
+            }
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    h->factored = true;
+    return DDM_OK;
+}
+
+int ddm_apply(ddm_handle *h, const void *u, void *out, int nrhs) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    try {
+        HIPCHK(launch_apply(h, (const double2 *)u, (double2 *)out, nrhs));
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
+int ddm_residual(ddm_handle *h, const void *f, const void *u, void *r, int nrhs, double *rnorm2, double *fnorm2) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    try {
+        HIPCHK(launch_residual(h, (const double2 *)f, (const double2 *)u, (double2 *)r, nrhs, h->d_norm,
+                               h->d_norm + nrhs));
+        HIPCHK(hipMemcpyAsync(h->h_norm, h->d_norm, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int q = 0; q < nrhs; ++q) {
+            if (rnorm2) rnorm2[q] = h->h_norm[q];
+            if (fnorm2) fnorm2[q] = h->h_norm[nrhs + q];
+        }
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
+int ddm_restrict_core(ddm_handle *h, const void *f, void *g, int nrhs) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    try {
+        HIPCHK((launch_restrict<double2, double2>(h, (const double2 *)f, (double2 *)g, nrhs)));
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
+int ddm_transfer(ddm_handle *h, const void *lag1, const void *lag2, const void *lag3, void *g, int nrhs) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    try {
+        HIPCHK((launch_transfer<double2, double2>(h, (const double2 *)lag1, (const double2 *)lag2,
+                                                  (const double2 *)lag3, (double2 *)g, nrhs)));
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
+int ddm_assemble(ddm_handle *h, const void *U, void *u, int nrhs) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    try {
+        HIPCHK(launch_assemble<double2>(h, (const double2 *)U, (double2 *)u, nrhs, false, nullptr));
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
+int ddm_local_solve(ddm_handle *h, const void *g, void *uhat, int nrhs) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    if (!h->factored) return fail(h, DDM_ESTATE, "ddm_local_solve before ddm_factor");
+    const Plan &P = h->plan;
+    long long n = (long long)nrhs * P.etot;
+    try {
+        if (h->mixed) {
+            HIPCHK(launch_convert_c128_to_c64((const double2 *)g, (float2 *)h->d_g, n, h->stream));
+            HIPCHK(launch_local_solve<float2>(h, (const float2 *)h->d_g, (float2 *)h->d_ring[0], nrhs));
+            HIPCHK(launch_convert_c64_to_c128((const float2 *)h->d_ring[0], (double2 *)uhat, n, h->stream));
+        } else {
+            const double2 *src = (const double2 *)g;
+            if (g == uhat) {
+                HIPCHK(hipMemcpyAsync(h->d_g, g, n * sizeof(double2), hipMemcpyDeviceToDevice, h->stream));
+                src = (const double2 *)h->d_g;
+            }
+            HIPCHK(launch_local_solve<double2>(h, src, (double2 *)uhat, nrhs));
+        }
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
+int ddm_iterate(ddm_handle *h, const void *f, void *u, int nrhs, int nsteps, double *relres) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    if (!h->factored) return fail(h, DDM_ESTATE, "ddm_iterate before ddm_factor");
+    if (nsteps < 0) return fail(h, DDM_EINVAL, "nsteps < 0");
+    const Plan &P = h->plan;
+    try {
+        HIPCHK(launch_fill_zero(u, (long long)nrhs * P.nglob * sizeof(double2), h->stream));
+        std::vector<int> ones(nrhs, 1);
+        set_active(h, ones);
+        std::vector<double> rel;
+        auto check = [&](int it, const double2 **) -> bool {
+            if (relres) {
+                residual_host(h, (const double2 *)f, (const double2 *)u, nullptr, nrhs, rel);
+                for (int q = 0; q < nrhs; ++q) relres[(size_t)(it - 1) * nrhs + q] = rel[q];
+            }
+            return true;
+        };
+        if (h->mixed) run_steps<float2>(h, (const double2 *)f, (double2 *)u, nrhs, nsteps, check);
+        else run_steps<double2>(h, (const double2 *)f, (double2 *)u, nrhs, nsteps, check);
+        HIPCHK(hipStreamSynchronize(h->stream));
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
+int ddm_solve(ddm_handle *h, const void *f, void *u, int nrhs, const ddm_solve_opts *opts, ddm_rhs_info *info) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    if (!opts) return fail(h, DDM_EINVAL, "opts is null");
+    if (!h->factored) return fail(h, DDM_ESTATE, "ddm_solve before ddm_factor");
+    if (!(opts->tol > 0) || opts->maxiter < 1) return fail(h, DDM_EINVAL, "tol must be > 0 and maxiter >= 1");
+    try {
+        // reject non-finite sources up front
+        std::vector<double> rel, fn;
+        HIPCHK(launch_norm2(h, (const double2 *)f, h->plan.nglob, nrhs, h->plan.nglob, h->d_norm + 2 * nrhs));
+        HIPCHK(hipMemcpyAsync(h->h_norm, h->d_norm + 2 * nrhs, nrhs * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int q = 0; q < nrhs; ++q)
+            if (!std::isfinite(h->h_norm[q])) return fail(h, DDM_EINVAL, "source has non-finite entries");
+        ddm_solve_opts o = *opts;
+        if (o.method == DDM_FGMRES) {
+            if (h->mixed) return solve_fgmres<float2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
+            return solve_fgmres<double2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
+        }
+        if (h->mixed) return solve_stationary<float2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
+        return solve_stationary<double2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    } catch (const std::string &s) {
+        return fail(h, DDM_EINVAL, s);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal declarations of libddm (HIP, gfx950).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ddm.h"
+
+namespace ddm {
+
+// Device-side descriptor of one subdomain (extended box E_a of Sec. 3.1).
+struct SubDesc {
+    int lo[3], hi[3];      // extended box, physical node indices (unused axes: 0)
+    int clo[3], chi[3];    // core box
+    int n[3];              // box extents (1 on unused axes)
+    int sid[3];            // subdomain multi-index
+    long long off;         // packed offset (elements per RHS)
+    long long nloc;        // box size
+    int nb;                // number of blocks (grid lines / planes) along the last axis
+    int bs;                // block size (n[0] in 2D, n[0]*n[1] in 3D)
+    long long foff;        // factor offset (elements)
+    int coff[3];           // offsets of this box's per-axis coefficient tables
+    int nbr[26];           // neighbour ids for the 26 offsets (-1: none)
+    int lag[26];           // lag = number of differing axes
+};
+
+// Per-node 1D coefficients of the PML operator along one axis:
+// (T u)(x) = cp (u(x+1) - u(x)) - cm (u(x) - u(x-1)),
+// cp = 1/(alpha(x) alpha(x+1/2) h^2), cm = 1/(alpha(x) alpha(x-1/2) h^2).
+struct Coef {
+    double2 cp, cm;
+};
+
+// One GEMV work item of the substitution kernels: rows [r0, r0 + 64) of the
+// blocks of subdomain a.
+struct SolveItem {
+    int a, r0;
+};
+
+struct Plan {
+    int dim = 2;
+    int M[3] = {0, 0, 0}, N[3] = {1, 1, 1}, C[3] = {1, 1, 1};
+    int G[3] = {1, 1, 1}, glo[3] = {0, 0, 0};
+    int n_pml = 0, n_ov = 0;
+    double h = 0, sigma0 = 0;
+    long long nglob = 0, etot = 0;
+    int nsub = 0;
+    int ring = 3;               // generations of local solutions kept (lags)
+    int bs_max = 0, nb_max = 0;
+    long long fel = 0;          // factor elements
+    std::vector<SubDesc> subs;
+    std::vector<Coef> coef;     // local tables (per subdomain, per axis)
+    std::vector<Coef> gcoef;    // global tables per axis (offsets gcoff)
+    int gcoff[3] = {0, 0, 0};
+    std::vector<int> owner;     // per axis, per global index: owning core index
+    int ooff[3] = {0, 0, 0};
+    std::vector<double> btab;   // side cut-off factor b(m), m = 0 .. n_ov
+    std::vector<SolveItem> items;
+};
+
+int build_plan(const ddm_problem *p, Plan *plan, std::string *err);
+
+}  // namespace ddm
+
+struct ddm_handle {
+    ddm_problem prob;
+    ddm::Plan plan;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int nrhs_max = 0;
+    bool mixed = false;
+    bool factored = false;
+    // device tables
+    ddm::SubDesc *d_subs = nullptr;
+    ddm::Coef *d_coef = nullptr, *d_gcoef = nullptr;
+    int *d_owner = nullptr;
+    double *d_btab = nullptr;
+    double *d_k2 = nullptr;
+    ddm::SolveItem *d_items = nullptr;
+    // factors: complex128 (FP64) or complex64 (MIXED), column-major blocks
+    void *d_W = nullptr;
+    double2 *d_scratch = nullptr;   // per-subdomain FP64 block during factorisation
+    int *d_flags = nullptr;         // per-subdomain status flags
+    // step workspaces, element type T (double2 or float2), nrhs_max * etot each
+    void *d_g = nullptr;
+    void *d_ring[4] = {nullptr, nullptr, nullptr, nullptr};
+    // FP64 global workspaces
+    double2 *d_r = nullptr;         // residual / operator output, nrhs_max * nglob
+    double2 *d_wide = nullptr;      // packed complex128 scratch for the ABI row entries
+    double *d_part = nullptr;       // norm partial sums
+    size_t part_cap = 0;            // doubles in d_part
+    double *d_norm = nullptr;       // per-RHS norms (device)
+    double *h_norm = nullptr;       // pinned host copy
+    int *d_active = nullptr;        // per-RHS flags for the assembly
+    int nblk_norm = 0;
+    size_t bytes = 0;
+    // FGMRES storage (allocated on first use)
+    double2 *d_V = nullptr, *d_Z = nullptr;
+    int krylov_m = 0, krylov_nrhs = 0;
+    double2 *d_dots = nullptr;      // (m+1) * nrhs dot products
+    double2 *h_dots = nullptr;      // pinned
+    double2 *d_coef_y = nullptr;    // Krylov combination coefficients
+};
+
+namespace ddm {
+
+// ---- launchers (all enqueue on h->stream; return hipError_t) ----
+hipError_t launch_apply(ddm_handle *h, const double2 *u, double2 *out, int nrhs);
+hipError_t launch_residual(ddm_handle *h, const double2 *f, const double2 *u, double2 *r, int nrhs,
+                           double *d_rn2, double *d_fn2);
+hipError_t launch_norm2(ddm_handle *h, const double2 *x, long long n, int nrhs, long long ld, double *d_out);
+
+template <typename TIN, typename TOUT>
+hipError_t launch_restrict(ddm_handle *h, const TIN *f, TOUT *g, int nrhs);
+template <typename TIN, typename TOUT>
+hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TIN *l3, TOUT *g, int nrhs);
+template <typename TIN>
+hipError_t launch_assemble(ddm_handle *h, const TIN *U, double2 *u, int nrhs, bool accumulate,
+                           const int *d_active);
+
+template <typename T>
+hipError_t launch_factor(ddm_handle *h);
+template <typename T>
+hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs);
+
+hipError_t launch_convert_c128_to_c64(const double2 *in, float2 *out, long long n, hipStream_t s);
+hipError_t launch_convert_c64_to_c128(const float2 *in, double2 *out, long long n, hipStream_t s);
+hipError_t launch_fill_zero(void *p, long long bytes, hipStream_t s);
+
+// Krylov helpers (FP64 complex, batched over RHS; vectors of length n, RHS stride ld)
+hipError_t launch_dots(const double2 *V, int nvec, long long vstride, const double2 *w, long long n, int nrhs,
+                       long long ld, double2 *d_out, double *d_part, int nblk, hipStream_t s);
+hipError_t launch_axpy_multi(double2 *w, const double2 *V, int nvec, long long vstride, const double2 *coef,
+                             double sign, long long n, int nrhs, long long ld, hipStream_t s);
+hipError_t launch_scale(double2 *y, const double2 *x, const double *scale, long long n, int nrhs, long long ld,
+                        hipStream_t s);
+
+}  // namespace ddm

@@ -1,0 +1,532 @@
+// Memory-bound kernels of the DDM step: 5/7-point PML operator and residual
+// with FP64 norms (stopping test of Sec. 4.2), step-1 source restriction,
+// 8/26-direction source transfer (Sec. 2.2, eq. talg_2), assembly
+// u = sum_a beta_{0;a} U_a (eq. tsum), precision casts and the batched
+// Krylov vector operations of the FGMRES driver.
+//
+// All reductions use a fixed assignment of elements to threads and a fixed
+// reduction tree: results are bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "cplx.h"
+#include "ddm_internal.h"
+
+namespace ddm {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// block-wide sum of doubles (fixed tree)
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    return s;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------------------
+// Operator apply / residual on the global grid.
+// L u(p) = k^2 u(p) + sum_axes [cp (u(p+e) - u(p)) - cm (u(p) - u(p-e))]
+// ---------------------------------------------------------------------------
+struct GridArgs {
+    int G0, G1, G2, dim;
+    int c0, c1, c2;
+    long long nglob;
+};
+
+__device__ inline double2 apply_global_at(const double2 *__restrict__ u, const double *__restrict__ k2,
+                                          const Coef *__restrict__ gc, const GridArgs &g, long long idx, int x,
+                                          int y, int z) {
+    double2 uc = u[idx];
+    double2 Lu = cscale(uc, k2[idx]);
+    {
+        Coef c = gc[g.c0 + x];
+        double2 up = x + 1 < g.G0 ? u[idx + 1] : make_double2(0, 0);
+        double2 um = x > 0 ? u[idx - 1] : make_double2(0, 0);
+        Lu = cadd(Lu, csub(cmul(c.cp, csub(up, uc)), cmul(c.cm, csub(uc, um))));
+    }
+    if (g.dim >= 2) {
+        Coef c = gc[g.c1 + y];
+        long long s = g.G0;
+        double2 up = y + 1 < g.G1 ? u[idx + s] : make_double2(0, 0);
+        double2 um = y > 0 ? u[idx - s] : make_double2(0, 0);
+        Lu = cadd(Lu, csub(cmul(c.cp, csub(up, uc)), cmul(c.cm, csub(uc, um))));
+    }
+    if (g.dim >= 3) {
+        Coef c = gc[g.c2 + z];
+        long long s = (long long)g.G0 * g.G1;
+        double2 up = z + 1 < g.G2 ? u[idx + s] : make_double2(0, 0);
+        double2 um = z > 0 ? u[idx - s] : make_double2(0, 0);
+        Lu = cadd(Lu, csub(cmul(c.cp, csub(up, uc)), cmul(c.cm, csub(uc, um))));
+    }
+    return Lu;
+}
+
+// mode 0: out = f - L u and partial norms of out and f; mode 1: out = L u
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil(const double2 *__restrict__ f, const double2 *__restrict__ u,
+                                                    double2 *__restrict__ out, const double *__restrict__ k2,
+                                                    const Coef *__restrict__ gc, GridArgs g,
+                                                    double *__restrict__ part_r, double *__restrict__ part_f) {
+    __shared__ double sh[kBlock / 64];
+    int rhs = blockIdx.y;
+    long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const double2 *ur = u + rhs * g.nglob;
+    double rn = 0.0, fn = 0.0;
+    if (idx < g.nglob) {
+        int x = (int)(idx % g.G0);
+        long long t = idx / g.G0;
+        int y = (int)(t % g.G1);
+        int z = (int)(t / g.G1);
+        double2 Lu = apply_global_at(ur, k2, gc, g, idx, x, y, z);
+        if (MODE == 0) {
+            double2 fv = f[rhs * g.nglob + idx];
+            double2 rv = csub(fv, Lu);
+            if (out) out[rhs * g.nglob + idx] = rv;
+            rn = cabs2(rv);
+            fn = cabs2(fv);
+        } else {
+            out[rhs * g.nglob + idx] = Lu;
+        }
+    }
+    if (MODE == 0) {
+        double a = block_sum(rn, sh);
+        if (threadIdx.x == 0) part_r[(long long)rhs * gridDim.x + blockIdx.x] = a;
+        double b = block_sum(fn, sh);
+        if (threadIdx.x == 0) part_f[(long long)rhs * gridDim.x + blockIdx.x] = b;
+    }
+}
+
+// sum nblk partials per RHS in a fixed order: one block per RHS
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double *__restrict__ part, int nblk,
+                                                         double *__restrict__ out) {
+    __shared__ double sh[kBlock / 64];
+    int rhs = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kBlock) s += part[(long long)rhs * nblk + i];
+    double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[rhs] = t;
+}
+
+// squared norms of nrhs vectors (length n, stride ld)
+__global__ __launch_bounds__(kBlock) void k_norm2_part(const double2 *__restrict__ x, long long n, long long ld,
+                                                       double *__restrict__ part) {
+    __shared__ double sh[kBlock / 64];
+    int rhs = blockIdx.y;
+    double s = 0.0;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        s += cabs2(x[rhs * ld + i]);
+    double t = block_sum(s, sh);
+    if (threadIdx.x == 0) part[(long long)rhs * gridDim.x + blockIdx.x] = t;
+}
+
+static GridArgs grid_args(const Plan &P) {
+    GridArgs g;
+    g.G0 = P.G[0]; g.G1 = P.G[1]; g.G2 = P.G[2]; g.dim = P.dim;
+    g.c0 = P.gcoff[0]; g.c1 = P.gcoff[1]; g.c2 = P.gcoff[2];
+    g.nglob = P.nglob;
+    return g;
+}
+
+hipError_t launch_apply(ddm_handle *h, const double2 *u, double2 *out, int nrhs) {
+    const Plan &P = h->plan;
+    dim3 grid((unsigned)((P.nglob + kBlock - 1) / kBlock), nrhs);
+    k_stencil<1><<<grid, kBlock, 0, h->stream>>>(nullptr, u, out, h->d_k2, h->d_gcoef, grid_args(P), nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(ddm_handle *h, const double2 *f, const double2 *u, double2 *r, int nrhs, double *d_rn2,
+                           double *d_fn2) {
+    const Plan &P = h->plan;
+    int nblk = (int)((P.nglob + kBlock - 1) / kBlock);
+    dim3 grid(nblk, nrhs);
+    double *part_r = h->d_part, *part_f = h->d_part + (long long)nrhs * nblk;
+    k_stencil<0><<<grid, kBlock, 0, h->stream>>>(f, u, r, h->d_k2, h->d_gcoef, grid_args(P), part_r, part_f);
+    k_sum_partials<<<nrhs, kBlock, 0, h->stream>>>(part_r, nblk, d_rn2);
+    k_sum_partials<<<nrhs, kBlock, 0, h->stream>>>(part_f, nblk, d_fn2);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2(ddm_handle *h, const double2 *x, long long n, int nrhs, long long ld, double *d_out) {
+    int nblk = 512;
+    k_norm2_part<<<dim3(nblk, nrhs), kBlock, 0, h->stream>>>(x, n, ld, h->d_part);
+    k_sum_partials<<<nrhs, kBlock, 0, h->stream>>>(h->d_part, nblk, d_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Packed subdomain vectors: helpers
+// ---------------------------------------------------------------------------
+struct PackArgs {
+    int dim, n_ov;
+    int G0, G1;
+    int glo0, glo1, glo2;
+    long long etot, nglob;
+};
+
+__device__ inline double side_factor(const double *__restrict__ btab, int n_ov, int m) {
+    if (m <= 1) return 1.0;
+    if (m >= n_ov) return 0.0;
+    return btab[m];
+}
+
+__device__ inline long long glob_index(const PackArgs &A, int px, int py, int pz) {
+    return (long long)(px - A.glo0) + (long long)A.G0 * ((long long)(py - A.glo1) + (long long)A.G1 * (pz - A.glo2));
+}
+
+// ---------------------------------------------------------------------------
+// Step-1 sources: g_a = f on the core of a, 0 elsewhere.
+// grid: (ceil(max box / 256), nsub, nrhs)
+// ---------------------------------------------------------------------------
+template <typename TIN, typename TOUT>
+__global__ __launch_bounds__(kBlock) void k_restrict(const SubDesc *__restrict__ subs, const TIN *__restrict__ f,
+                                                     TOUT *__restrict__ g, PackArgs A) {
+    int a = blockIdx.y, rhs = blockIdx.z;
+    const SubDesc &s = subs[a];
+    long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= s.nloc) return;
+    int x = (int)(e % s.n[0]);
+    long long t = e / s.n[0];
+    int y = (int)(t % s.n[1]);
+    int z = (int)(t / s.n[1]);
+    int p0 = s.lo[0] + x, p1 = s.lo[1] + y, p2 = s.lo[2] + z;
+    bool core = p0 >= s.clo[0] && p0 <= s.chi[0] && p1 >= s.clo[1] && p1 <= s.chi[1] && p2 >= s.clo[2] &&
+                p2 <= s.chi[2];
+    double2 v = make_double2(0, 0);
+    if (core) v = to_d2(f[rhs * A.nglob + glob_index(A, p0, p1, p2)]);
+    g[rhs * A.etot + s.off + e] = from_d2<TOUT>(v);
+}
+
+// ---------------------------------------------------------------------------
+// Source transfer (Sec. 2.2 transfer operators, eq. talg_2):
+//   g_a(p) = - sum_b [p in chi_{b->a}] (L_a (beta_{b->a} uhat_b))(p)
+// b over the 8 / 26 neighbours, lag = number of differing axes.
+// Only the first n_ov core layers of a facing b can be non-zero (beta
+// vanishes n_ov nodes past b's core); every other node gets 0.
+// ---------------------------------------------------------------------------
+template <typename TIN>
+__device__ inline double2 weighted(const SubDesc &b, const int *dd, const TIN *__restrict__ src,
+                                   const double *__restrict__ btab, int n_ov, int q0, int q1, int q2) {
+    if (q0 < b.lo[0] || q0 > b.hi[0] || q1 < b.lo[1] || q1 > b.hi[1] || q2 < b.lo[2] || q2 > b.hi[2])
+        return make_double2(0, 0);
+    int q[3] = {q0, q1, q2};
+    double beta = 1.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (dd[d] < 0) beta *= side_factor(btab, n_ov, q[d] - b.chi[d]);       // b below a: b's high side
+        else if (dd[d] > 0) beta *= side_factor(btab, n_ov, b.clo[d] - q[d]);  // b above a: b's low side
+    }
+    if (beta == 0.0) return make_double2(0, 0);
+    long long li = (long long)(q0 - b.lo[0]) + (long long)b.n[0] * ((long long)(q1 - b.lo[1]) + (long long)b.n[1] * (q2 - b.lo[2]));
+    return cscale(to_d2(src[b.off + li]), beta);
+}
+
+template <typename TIN, typename TOUT>
+__global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__ subs, const Coef *__restrict__ coef,
+                                                     const double *__restrict__ k2, const double *__restrict__ btab,
+                                                     const TIN *__restrict__ l1, const TIN *__restrict__ l2,
+                                                     const TIN *__restrict__ l3, TOUT *__restrict__ g, PackArgs A) {
+    int a = blockIdx.y, rhs = blockIdx.z;
+    const SubDesc &s = subs[a];
+    long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= s.nloc) return;
+    int lx = (int)(e % s.n[0]);
+    long long t = e / s.n[0];
+    int ly = (int)(t % s.n[1]);
+    int lz = (int)(t / s.n[1]);
+    int p[3] = {s.lo[0] + lx, s.lo[1] + ly, s.lo[2] + lz};
+    int l[3] = {lx, ly, lz};
+    double2 acc = make_double2(0, 0);
+    // strip membership per axis: inlo = one of the first n_ov core layers
+    // (faces the lower neighbour), inhi = one of the last n_ov core layers;
+    // both can hold when the core is narrower than 2 n_ov
+    bool inlo[3], inhi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        inlo[d] = d < A.dim && p[d] >= s.clo[d] && p[d] <= s.clo[d] + A.n_ov - 1;
+        inhi[d] = d < A.dim && p[d] <= s.chi[d] && p[d] >= s.chi[d] - A.n_ov + 1;
+    }
+    bool any = inlo[0] || inhi[0] || inlo[1] || inhi[1] || inlo[2] || inhi[2];
+    if (any) {
+        double kk = k2[glob_index(A, p[0], p[1], p[2])];
+        Coef cf[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cf[d] = coef[s.coff[d] + l[d]];
+        int k = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (dx == 0 && dy == 0 && dz == 0) continue;
+                    int slot = k++;
+                    int bidx = s.nbr[slot];
+                    if (bidx < 0) continue;
+                    int dd[3] = {dx, dy, dz};
+                    // every differing axis must put p in the strip facing b
+                    bool ok = true;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        if (dd[d] < 0 && !inlo[d]) ok = false;
+                        if (dd[d] > 0 && !inhi[d]) ok = false;
+                    }
+                    if (!ok) continue;
+                    int lag = s.lag[slot];
+                    const TIN *src = lag == 1 ? l1 : (lag == 2 ? l2 : l3);
+                    if (!src) continue;
+                    src += rhs * A.etot;
+                    const SubDesc &b = subs[bidx];
+                    double2 w0 = weighted(b, dd, src, btab, A.n_ov, p[0], p[1], p[2]);
+                    double2 Lw = cscale(w0, kk);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        if (d >= A.dim) continue;
+                        int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
+                        qp[d] += 1;
+                        qm[d] -= 1;
+                        double2 wp = p[d] < s.hi[d] ? weighted(b, dd, src, btab, A.n_ov, qp[0], qp[1], qp[2])
+                                                    : make_double2(0, 0);
+                        double2 wm = p[d] > s.lo[d] ? weighted(b, dd, src, btab, A.n_ov, qm[0], qm[1], qm[2])
+                                                    : make_double2(0, 0);
+                        Lw = cadd(Lw, csub(cmul(cf[d].cp, csub(wp, w0)), cmul(cf[d].cm, csub(w0, wm))));
+                    }
+                    acc = csub(acc, Lw);
+                }
+    }
+    g[rhs * A.etot + s.off + e] = from_d2<TOUT>(acc);
+}
+
+// ---------------------------------------------------------------------------
+// Assembly u(p) (+)= sum_a beta_{0;a}(p) U_a(p) (eq. tsum).  At most 2 owners
+// per axis have a non-zero cut-off at p.  active[rhs] == 0 skips the RHS.
+// ---------------------------------------------------------------------------
+template <typename TIN>
+__global__ __launch_bounds__(kBlock) void k_assemble(const SubDesc *__restrict__ subs, const int *__restrict__ owner,
+                                                     int o0, int o1, int o2, int N0, int N1, int N2,
+                                                     const double *__restrict__ btab, const TIN *__restrict__ U,
+                                                     double2 *__restrict__ u, PackArgs A, int accumulate,
+                                                     const int *__restrict__ active) {
+    int rhs = blockIdx.y;
+    if (active && !active[rhs]) return;
+    long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= A.nglob) return;
+    int gx = (int)(idx % A.G0);
+    long long t = idx / A.G0;
+    int gy = (int)(t % A.G1);
+    int gz = (int)(t / A.G1);
+    int p[3] = {gx + A.glo0, gy + A.glo1, gz + A.glo2};
+    int own[3] = {owner[o0 + gx], owner[o1 + gy], owner[o2 + gz]};
+    int Nn[3] = {N0, N1, N2};
+    double2 acc = make_double2(0, 0);
+    const TIN *Ur = U + rhs * A.etot;
+    for (int dz = -1; dz <= 1; ++dz) {
+        int iz = own[2] + dz;
+        if (iz < 0 || iz >= Nn[2]) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            int iy = own[1] + dy;
+            if (iy < 0 || iy >= Nn[1]) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                int ix = own[0] + dx;
+                if (ix < 0 || ix >= Nn[0]) continue;
+                const SubDesc &s = subs[ix + N0 * (iy + N1 * iz)];
+                double bz = 1.0;
+                bool inside = true;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (p[d] < s.lo[d] || p[d] > s.hi[d]) inside = false;
+                    else if (p[d] > s.chi[d]) bz *= side_factor(btab, A.n_ov, p[d] - s.chi[d]);
+                    else if (p[d] < s.clo[d]) bz *= side_factor(btab, A.n_ov, s.clo[d] - p[d]);
+                }
+                if (!inside || bz == 0.0) continue;
+                long long li = (long long)(p[0] - s.lo[0]) +
+                               (long long)s.n[0] * ((long long)(p[1] - s.lo[1]) + (long long)s.n[1] * (p[2] - s.lo[2]));
+                acc = cadd(acc, cscale(to_d2(Ur[s.off + li]), bz));
+            }
+        }
+    }
+    double2 *ur = u + rhs * A.nglob + idx;
+    *ur = accumulate ? cadd(*ur, acc) : acc;
+}
+
+static PackArgs pack_args(const Plan &P) {
+    PackArgs A;
+    A.dim = P.dim; A.n_ov = P.n_ov;
+    A.G0 = P.G[0]; A.G1 = P.G[1];
+    A.glo0 = P.glo[0]; A.glo1 = P.glo[1]; A.glo2 = P.glo[2];
+    A.etot = P.etot; A.nglob = P.nglob;
+    return A;
+}
+
+static long long max_box(const Plan &P) {
+    long long m = 0;
+    for (const SubDesc &s : P.subs) m = s.nloc > m ? s.nloc : m;
+    return m;
+}
+
+template <typename TIN, typename TOUT>
+hipError_t launch_restrict(ddm_handle *h, const TIN *f, TOUT *g, int nrhs) {
+    const Plan &P = h->plan;
+    dim3 grid((unsigned)((max_box(P) + kBlock - 1) / kBlock), P.nsub, nrhs);
+    k_restrict<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, f, g, pack_args(P));
+    return hipGetLastError();
+}
+
+template <typename TIN, typename TOUT>
+hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TIN *l3, TOUT *g, int nrhs) {
+    const Plan &P = h->plan;
+    dim3 grid((unsigned)((max_box(P) + kBlock - 1) / kBlock), P.nsub, nrhs);
+    k_transfer<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g,
+                                                          pack_args(P));
+    return hipGetLastError();
+}
+
+template <typename TIN>
+hipError_t launch_assemble(ddm_handle *h, const TIN *U, double2 *u, int nrhs, bool accumulate, const int *d_active) {
+    const Plan &P = h->plan;
+    dim3 grid((unsigned)((P.nglob + kBlock - 1) / kBlock), nrhs);
+    k_assemble<TIN><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_owner, P.ooff[0], P.ooff[1], P.ooff[2], P.N[0],
+                                                    P.N[1], P.N[2], h->d_btab, U, u, pack_args(P),
+                                                    accumulate ? 1 : 0, d_active);
+    return hipGetLastError();
+}
+
+template hipError_t launch_restrict<double2, double2>(ddm_handle *, const double2 *, double2 *, int);
+template hipError_t launch_restrict<double2, float2>(ddm_handle *, const double2 *, float2 *, int);
+template hipError_t launch_transfer<double2, double2>(ddm_handle *, const double2 *, const double2 *,
+                                                      const double2 *, double2 *, int);
+template hipError_t launch_transfer<float2, float2>(ddm_handle *, const float2 *, const float2 *, const float2 *,
+                                                    float2 *, int);
+template hipError_t launch_assemble<double2>(ddm_handle *, const double2 *, double2 *, int, bool, const int *);
+template hipError_t launch_assemble<float2>(ddm_handle *, const float2 *, double2 *, int, bool, const int *);
+
+// ---------------------------------------------------------------------------
+// casts and fills
+// ---------------------------------------------------------------------------
+__global__ void k_c128_to_c64(const double2 *__restrict__ in, float2 *__restrict__ out, long long n) {
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+__global__ void k_c64_to_c128(const float2 *__restrict__ in, double2 *__restrict__ out, long long n) {
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        out[i] = make_double2(in[i].x, in[i].y);
+}
+__global__ void k_fill_zero(uint4 *__restrict__ p, long long n16, unsigned char *__restrict__ tail, int ntail) {
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (long long)gridDim.x * kBlock)
+        p[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+static unsigned grid_for(long long n) {
+    long long b = (n + kBlock - 1) / kBlock;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+hipError_t launch_convert_c128_to_c64(const double2 *in, float2 *out, long long n, hipStream_t s) {
+    k_c128_to_c64<<<grid_for(n), kBlock, 0, s>>>(in, out, n);
+    return hipGetLastError();
+}
+hipError_t launch_convert_c64_to_c128(const float2 *in, double2 *out, long long n, hipStream_t s) {
+    k_c64_to_c128<<<grid_for(n), kBlock, 0, s>>>(in, out, n);
+    return hipGetLastError();
+}
+// zero fill with a kernel (a memset node is avoided so that a captured step
+// replays correctly)
+hipError_t launch_fill_zero(void *p, long long bytes, hipStream_t s) {
+    long long n16 = bytes / 16;
+    int ntail = (int)(bytes - n16 * 16);
+    k_fill_zero<<<grid_for(n16 > 0 ? n16 : 1), kBlock, 0, s>>>((uint4 *)p, n16, (unsigned char *)p + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Krylov vector operations (FP64 complex; RHS r's vectors at stride ld)
+// ---------------------------------------------------------------------------
+// partial dot products conj(V_i) . w, grid (nblk, nvec, nrhs)
+__global__ __launch_bounds__(kBlock) void k_dots_part(const double2 *__restrict__ V, long long vstride,
+                                                      const double2 *__restrict__ w, long long n, long long ld,
+                                                      double *__restrict__ part) {
+    __shared__ double sh[kBlock / 64];
+    int i = blockIdx.y, rhs = blockIdx.z, nvec = gridDim.y;
+    const double2 *v = V + i * vstride + rhs * ld;
+    const double2 *wr = w + rhs * ld;
+    double sr = 0.0, si = 0.0;
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) {
+        double2 c = cconjmul(v[q], wr[q]);
+        sr += c.x;
+        si += c.y;
+    }
+    double a = block_sum(sr, sh);
+    double b = block_sum(si, sh);
+    if (threadIdx.x == 0) {
+        long long base = ((long long)rhs * nvec + i) * gridDim.x + blockIdx.x;
+        part[2 * base] = a;
+        part[2 * base + 1] = b;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dots_sum(const double *__restrict__ part, int nblk,
+                                                     double2 *__restrict__ out) {
+    __shared__ double sh[kBlock / 64];
+    long long item = blockIdx.x;  // rhs * nvec + i
+    double sr = 0.0, si = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        sr += part[2 * (item * nblk + b)];
+        si += part[2 * (item * nblk + b) + 1];
+    }
+    double a = block_sum(sr, sh);
+    double c = block_sum(si, sh);
+    if (threadIdx.x == 0) out[item] = make_double2(a, c);
+}
+
+hipError_t launch_dots(const double2 *V, int nvec, long long vstride, const double2 *w, long long n, int nrhs,
+                       long long ld, double2 *d_out, double *d_part, int nblk, hipStream_t s) {
+    k_dots_part<<<dim3(nblk, nvec, nrhs), kBlock, 0, s>>>(V, vstride, w, n, ld, d_part);
+    k_dots_sum<<<nvec * nrhs, kBlock, 0, s>>>(d_part, nblk, d_out);
+    return hipGetLastError();
+}
+
+// w_r += sign * sum_i coef[r * nvec + i] V_i,r
+__global__ __launch_bounds__(kBlock) void k_axpy_multi(double2 *__restrict__ w, const double2 *__restrict__ V,
+                                                       int nvec, long long vstride, const double2 *__restrict__ coef,
+                                                       double sign, long long n, long long ld) {
+    int rhs = blockIdx.y;
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock) {
+        double2 acc = w[rhs * ld + q];
+        for (int i = 0; i < nvec; ++i) {
+            double2 c = cscale(coef[rhs * nvec + i], sign);
+            acc = cadd(acc, cmul(c, V[i * vstride + rhs * ld + q]));
+        }
+        w[rhs * ld + q] = acc;
+    }
+}
+
+hipError_t launch_axpy_multi(double2 *w, const double2 *V, int nvec, long long vstride, const double2 *coef,
+                             double sign, long long n, int nrhs, long long ld, hipStream_t s) {
+    k_axpy_multi<<<dim3(grid_for(n) > 2048 ? 2048 : grid_for(n), nrhs), kBlock, 0, s>>>(w, V, nvec, vstride, coef,
+                                                                                      sign, n, ld);
+    return hipGetLastError();
+}
+
+// y_r = x_r / sqrt(scale[r]) (0 if scale[r] == 0)
+__global__ __launch_bounds__(kBlock) void k_scale(double2 *__restrict__ y, const double2 *__restrict__ x,
+                                                  const double *__restrict__ scale, long long n, long long ld) {
+    int rhs = blockIdx.y;
+    double s = scale[rhs];
+    double inv = s > 0 ? 1.0 / sqrt(s) : 0.0;
+    for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < n; q += (long long)gridDim.x * kBlock)
+        y[rhs * ld + q] = cscale(x[rhs * ld + q], inv);
+}
+
+hipError_t launch_scale(double2 *y, const double2 *x, const double *scale, long long n, int nrhs, long long ld,
+                        hipStream_t s) {
+    k_scale<<<dim3(grid_for(n) > 2048 ? 2048 : grid_for(n), nrhs), kBlock, 0, s>>>(y, x, scale, n, ld);
+    return hipGetLastError();
+}
+
+}  // namespace ddm

@@ -1,0 +1,165 @@
+"""GPU parity: every step of the HIP path (through the C-ABI) against the CPU
+oracle on the same seeded inputs, element by element.
+
+Sizes: subdomain blocks of 75-98 nodes span two 64-row tiles of the
+substitution kernel with a ragged tail; RHS counts 1, 3, 5 and 9 exercise
+ragged RHS tiles; layouts 2x2, 3x2 and 3x3 mix interior, edge and corner
+boxes of different sizes in one launch.
+
+Tolerances (relative, max-abs or L2 per RHS as stated):
+  operator, restriction, transfer, assembly : 1e-13 (same FP64 formula, only
+      rounding order differs)
+  FP64 local solves and DDM iterates         : 1e-10 (spec bound for the
+      FP64 path; block inverses vs banded LU differ by rounding amplified by
+      the local condition number)
+  mixed (complex64) local solves            : 5e-5 (c64 unit roundoff 6e-8
+      times the local condition number, < 1e3 here)
+"""
+import numpy as np
+import pytest
+import torch
+
+import ddm_inputs as di
+from oracle import Oracle
+import paper_1807_04180_amd as ddm
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def make_pair(w, nrhs_max=None, mixed=False):
+    o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
+    g = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=mixed), _t(w.k2.reshape(-1)),
+                         nrhs_max or max(w.nrhs, 1))
+    return o, g
+
+
+def relerr(a, b, axis=None):
+    a = np.asarray(a).reshape(b.shape)
+    num = np.linalg.norm(a - b, axis=axis)
+    den = np.linalg.norm(b, axis=axis)
+    return np.max(num / np.maximum(den, 1e-300))
+
+
+CASES = {
+    "2d-2x2-const": lambda: di.small_2d(M=160, N=(2, 2), n_pml=8, n_ov=4, nrhs=3),
+    "2d-3x2-layered": lambda: di.small_2d(M=144, N=(3, 2), n_pml=6, n_ov=3, nrhs=1, layered=True, seed=3),
+    "2d-3x3-layered": lambda: di.small_2d(M=192, N=(3, 3), n_pml=7, n_ov=5, nrhs=5, layered=True, seed=4),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def pair(request):
+    w = CASES[request.param]()
+    # 3x2: unequal subdomain counts per axis need M divisible by both
+    o, g = make_pair(w, nrhs_max=9)
+    yield w, o, g
+    g.close()
+
+
+def test_geometry_matches_oracle(pair):
+    w, o, g = pair
+    assert g.nglob == o.nglob and g.etot == o.etot and g.nsub == o.nsub
+    for a in range(o.nsub):
+        go, gg = o.subdomain(a), g.geometry(a)
+        for k in ("core_lo", "core_hi", "ext_lo", "ext_hi", "off", "n"):
+            assert tuple(np.atleast_1d(go[k])) == tuple(np.atleast_1d(gg[k])), (a, k)
+
+
+def test_operator_and_residual(pair):
+    w, o, g = pair
+    u = di.random_field((3, o.nglob), seed=11)
+    Lo = o.apply(u)
+    Lg = _n(g.apply(_t(u)))
+    assert relerr(Lg, Lo) < 1e-13
+    f = di.random_field((3, o.nglob), seed=12)
+    r, rn, fn = g.residual(_t(f), _t(u))
+    ro = f - Lo
+    assert relerr(_n(r), ro) < 1e-13
+    np.testing.assert_allclose(np.sqrt(rn), np.linalg.norm(ro, axis=1), rtol=1e-13)
+    np.testing.assert_allclose(np.sqrt(fn), np.linalg.norm(f, axis=1), rtol=1e-13)
+
+
+def test_restrict_core_bitwise(pair):
+    w, o, g = pair
+    f = di.random_field((2, o.nglob), seed=13)
+    assert np.array_equal(_n(g.restrict_core(_t(f))), o.restrict_core(f))
+
+
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_transfer(pair, nrhs):
+    w, o, g = pair
+    lags = [di.random_field((nrhs, o.etot), seed=20 + k) for k in range(3)]
+    for use in ([0], [0, 1], [1], [0, 1, 2]):
+        args = [lags[k] if k in use else None for k in range(3)]
+        go = o.transfer(args, nrhs)
+        gg = _n(g.transfer(*[None if a is None else _t(a) for a in args]))
+        assert relerr(gg, go) < 1e-13, use
+
+
+def test_assemble(pair):
+    w, o, g = pair
+    U = di.random_field((3, o.etot), seed=30)
+    assert relerr(_n(g.assemble(_t(U))), o.assemble(U)) < 1e-14
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 9])
+def test_local_solve_fp64(pair, nrhs):
+    w, o, g = pair
+    gin = di.random_field((nrhs, o.etot), seed=40 + nrhs)
+    xo = o.local_solve(gin)
+    xg = _n(g.local_solve(_t(gin)))
+    for a in range(o.nsub):
+        sd = o.subdomain(a)
+        sl = slice(sd["off"], sd["off"] + sd["n"])
+        assert relerr(xg[:, sl], xo[:, sl], axis=1) < 1e-10, a
+
+
+def test_iterate_fp64_matches_oracle_every_step(pair):
+    w, o, g = pair
+    nsteps = 2 * sum(w.N) + 2
+    uo, rro = o.ddm_run(w.f, nsteps)
+    ug, rrg = g.iterate(_t(w.f.reshape(w.nrhs, -1)), nsteps)
+    assert relerr(_n(ug), uo, axis=1) < 1e-10
+    rrg = np.array(rrg)
+    # relres agrees while it is well above roundoff
+    big = rro > 1e-9
+    np.testing.assert_allclose(rrg[big], rro[big], rtol=1e-8)
+
+
+def test_local_solve_mixed():
+    w = CASES["2d-3x3-layered"]()
+    o, g = make_pair(w, nrhs_max=3, mixed=True)
+    gin = di.random_field((3, o.etot), seed=50)
+    xo = o.local_solve(gin)
+    xg = _n(g.local_solve(_t(gin)))
+    assert relerr(xg, xo, axis=1) < 5e-5
+    g.close()
+
+
+def test_batch_invariance_bitwise(pair):
+    """Each RHS alone gives bit-for-bit the same local solves and iterates as
+    inside a batch of 9."""
+    w, o, g = pair
+    gin = di.random_field((9, o.etot), seed=60)
+    xb = _n(g.local_solve(_t(gin)))
+    for q in (0, 4, 8):
+        xq = _n(g.local_solve(_t(gin[q:q + 1])))
+        assert np.array_equal(xq[0], xb[q])
+
+
+def test_deterministic_bitwise(pair):
+    w, o, g = pair
+    f = _t(w.f.reshape(w.nrhs, -1))
+    u1, r1 = g.iterate(f, 5)
+    u2, r2 = g.iterate(f, 5)
+    assert torch.equal(u1, u2) and r1 == r2
