@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Helmholtz solves/s of the additive overlapping DDM on one MI355X.
+
+Workload (one "step" = one batch solve): the 2D constant-medium problem on
+the unit square, 1024^2 interior cells (h = 1/1024, omega = 2 pi 102.4, 10
+points per wavelength), 5-point PML operator with a 16-cell PML (sigma0 for
+1e-6 reflection), 8x8 subdomains of 128^2 cells with 8-cell overlap, four
+seeded unit-mass Gaussian sources (std 2h); the batch of 4 right-hand sides is
+solved by the DDM as a stationary iteration to FP64 relative residual 1e-6 in
+complex128.  Factorisation happens once before the timed region (reported
+separately), as in the paper's timings.
+
+Also measured on the same workload (outside `value`): the DDM as FGMRES(30)
+preconditioner (K = N1 + N2 = 16 steps) in FP64, and the mixed path
+(complex64 factors / local solves / transfers, FP64 residual, assembly and
+refinement), with each result's error against the FP64 solution.
+
+`roofline` is for the dominant kernel, the block substitution, from a live
+pass with HIP events around every substitution launch on the library's
+stream: algorithmic bytes (every stored block inverse read once per sweep,
+plus the block vectors) / summed launch time.  `cpu_baseline` runs the CPU
+oracle (unchanged) on a 4x4-subdomain cut of the same workload and scales the
+per-step time to the 64 subdomains and the step count of the full solve.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Helmholtz solves/sec at rel.resid 1e-6 (mixed vs FP64 DDM); p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(v, p):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=float), p)) if len(v) else None
+
+
+def run_cpu_baseline(nrhs_full, nsub_full, steps_full, tol):
+    """Oracle on a 4x4 cut of the workload; per-step time scaled by subdomain
+    count (the oracle's work per step is linear in it) and by the full
+    solve's step count."""
+    import numpy as np
+    import ddm_inputs as di
+    from oracle import Oracle
+
+    w = di.config2_cut(4, nrhs=nrhs_full)
+    o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
+    t0 = time.perf_counter()
+    o.factor()
+    t_fac = time.perf_counter() - t0
+    nsteps = 12
+    t0 = time.perf_counter()
+    u, rr = o.ddm_run(w.f, nsteps)
+    t_run = time.perf_counter() - t0
+    t_step = t_run / nsteps
+    conv = [int(np.argmax(rr[:, q] <= tol)) + 1 if np.any(rr[:, q] <= tol) else None for q in range(w.nrhs)]
+    scale = nsub_full / o.nsub
+    t_step_full = t_step * scale
+    value = nrhs_full / (t_step_full * steps_full)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": value, "unit": "solves/s", "cores": threads, "kind": "oracle",
+        "sample": ("oracle (FP64 banded-LU local solves, OpenMP) on a 4x4-subdomain cut of the workload "
+                   "(M=512, same h, omega, PML, overlap and 128^2 cores, %d seeded Gaussians): factor %.2f s, "
+                   "%d DDM steps in %.2f s (%.3f s/step, steps to 1e-6 on the cut %s); per-step time scaled "
+                   "x%.0f to the %d subdomains of the full workload and x%d steps of its FP64 GPU solve"
+                   % (w.nrhs, t_fac, nsteps, t_run, t_step, conv, scale, nsub_full, steps_full)),
+        "factor_s_sample": t_fac, "step_s_sample": t_step,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FGMRES and mixed-precision legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the DDM step has no multi-GPU path here); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import ddm_inputs as di
+    import paper_1807_04180_amd as ddm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = di.config2(nrhs=4)
+    nrhs = w.nrhs
+    log("bench: workload %s nglob=%d nrhs=%d on %s" % (w.name, int(np.prod(w.grid_shape)), nrhs,
+                                                        torch.cuda.get_device_name(0)))
+    k2 = torch.from_numpy(w.k2.reshape(-1)).to(dev)
+    f = torch.from_numpy(w.f.reshape(nrhs, -1)).to(dev)
+
+    # ---- FP64 handle: setup + factor ------------------------------------
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s64 = ddm.HelmholtzDDM(ddm.Problem.from_workload(w), k2, nrhs, factor=False)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s64.factor()
+    torch.cuda.synchronize()
+    t_factor = time.perf_counter() - t0
+    log("bench: setup %.3f s, factor %.3f s (%.2f GB of complex128 block inverses)"
+        % (t_setup, t_factor, s64.factor_bytes / 1e9))
+
+    def solve_fp64(u=None):
+        return s64.solve(f, method="stationary", tol=args.tol, maxiter=400, u=u)
+
+    u64 = torch.empty_like(f)
+    for i in range(args.warmup):
+        _, info, st = solve_fp64(u64)
+        log("bench: warmup %d status %d steps %s" % (i, st, [x["iters"] for x in info]))
+    torch.cuda.synchronize()
+    lat = []
+    steps_used = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, info, st = solve_fp64(u64)
+        lat += [x["seconds"] * 1e3 for x in info]
+        steps_used += [x["iters"] for x in info]
+        if st != 0:
+            log("bench: step %d status %d" % (i, st))
+    torch.cuda.synchronize()
+    t_timed = time.perf_counter() - t0
+    ms_per_step = t_timed / args.steps * 1e3
+    value = nrhs * args.steps / t_timed
+    relres = [x["relres"] for x in info]
+    log("bench: FP64 stationary: %.2f ms/batch, %.2f solves/s, steps %s, relres %s"
+        % (ms_per_step, value, sorted(set(steps_used)), ["%.2e" % r for r in relres]))
+    steps_full = max(steps_used)
+
+    # independent check of the result with the oracle's operator (full size)
+    from oracle import Oracle
+    o_full = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
+    rel_oracle = o_full.relres(w.f, u64.cpu().numpy()).tolist()
+    del o_full
+    log("bench: oracle-evaluated relres of the FP64 result %s" % ["%.2e" % r for r in rel_oracle])
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": ("2D constant medium, 1024^2 interior (h=1/1024, omega=2*pi*102.4, 10 ppw), "
+                                "5-point FD, PML 16 (R=1e-6), 8x8 subdomains of 128^2 with overlap 8, "
+                                "4 seeded Gaussian sources (std 2h), complex128 stationary DDM to relres %.0e"
+                                % args.tol),
+                   "global_batch": nrhs, "grid": [1024, 1024], "subdomains": [8, 8], "method": "stationary",
+                   "precision": "fp64"},
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "ddm_steps_per_solve": steps_full,
+        "relres": relres, "relres_oracle_operator": rel_oracle,
+        "factor_s": t_factor, "setup_s": t_setup, "factor_bytes": s64.factor_bytes,
+    }
+
+    # ---- roofline of the substitution kernel: live event-profiled pass --
+    s64.profile_enable(True)
+    u_tmp = torch.empty_like(f)
+    _, info_p, _ = solve_fp64(u_tmp)
+    prof = s64.profile_read()
+    s64.profile_enable(False)
+    sub = prof["substitution"]
+    avg_us = sub["ms"] / max(sub["launches"], 1) * 1e3
+    achieved = sub["bytes"] / (sub["ms"] * 1e-3) / 1e9 if sub["ms"] > 0 else 0.0
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_solve_line (block substitution)",
+                       "avg_launch_us": avg_us, "launches": sub["launches"],
+                       "bytes_per_launch": sub["bytes"] / max(sub["launches"], 1)}
+    out["kernel_time_ms_per_solve_batch"] = {k: v["ms"] for k, v in prof.items()}
+    out["kernel_achieved_GBs"] = {k: (v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None)
+                                  for k, v in prof.items()}
+    log("bench: substitution %d launches, avg %.2f us, %.0f GB/s (%.1f%% of HBM peak); per class ms %s"
+        % (sub["launches"], avg_us, achieved, 100 * achieved / HBM_PEAK_GBS,
+           {k: round(v["ms"], 2) for k, v in prof.items()}))
+
+    if not args.no_extras:
+        # ---- FGMRES(30) + DDM(K = N1 + N2), FP64 ----------------------------
+        uf = torch.empty_like(f)
+        s64.solve(f, method="fgmres", tol=args.tol, maxiter=200, restart=30, u=uf)  # warm-up / alloc
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, infof, stf = s64.solve(f, method="fgmres", tol=args.tol, maxiter=200, restart=30, u=uf)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        errf = (torch.linalg.vector_norm(uf - u64, dim=1) / torch.linalg.vector_norm(u64, dim=1)).tolist()
+        out["fgmres"] = {"solves_per_s": nrhs / tf, "ms_per_batch": tf * 1e3, "K": 16, "restart": 30,
+                         "gmres_iters": [x["iters"] for x in infof],
+                         "local_solves": [x["local_solves"] for x in infof],
+                         "relres": [x["relres"] for x in infof], "rel_diff_vs_stationary": errf, "status": stf}
+        log("bench: FP64 FGMRES: %.2f solves/s, iters %s" % (nrhs / tf, [x["iters"] for x in infof]))
+
+        # ---- mixed precision -------------------------------------------------
+        del s64
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        smx = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=True), k2, nrhs)
+        torch.cuda.synchronize()
+        t_factor_mx = time.perf_counter() - t0
+        umx = torch.empty_like(f)
+        for _ in range(args.warmup):
+            smx.solve(f, method="stationary", tol=args.tol, maxiter=400, u=umx)
+        torch.cuda.synchronize()
+        latm = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, infom, stm = smx.solve(f, method="stationary", tol=args.tol, maxiter=400, u=umx)
+            latm += [x["seconds"] * 1e3 for x in infom]
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        errm = (torch.linalg.vector_norm(umx - u64, dim=1) / torch.linalg.vector_norm(u64, dim=1)).tolist()
+        ufm = torch.empty_like(f)
+        t1 = time.perf_counter()
+        _, infofm, stfm = smx.solve(f, method="fgmres", tol=args.tol, maxiter=200, restart=30, u=ufm)
+        torch.cuda.synchronize()
+        tfm = time.perf_counter() - t1
+        out["mixed"] = {"solves_per_s": nrhs * args.steps / tm, "ms_per_batch": tm / args.steps * 1e3,
+                        "latency_ms": {"p50": pct(latm, 50), "p99": pct(latm, 99)},
+                        "steps": [x["iters"] for x in infom], "relres": [x["relres"] for x in infom],
+                        "rel_err_vs_fp64": errm, "status": stm, "factor_s": t_factor_mx,
+                        "speedup_vs_fp64": (nrhs * args.steps / tm) / value,
+                        "fgmres": {"solves_per_s": nrhs / tfm, "gmres_iters": [x["iters"] for x in infofm],
+                                   "relres": [x["relres"] for x in infofm], "status": stfm}}
+        log("bench: mixed stationary: %.2f solves/s (x%.2f), steps %s, err vs FP64 %s"
+            % (nrhs * args.steps / tm, (nrhs * args.steps / tm) / value, [x["iters"] for x in infom],
+               ["%.1e" % e for e in errm]))
+        del smx
+
+    if not args.no_cpu_baseline:
+        log("bench: CPU baseline (oracle) ...")
+        out["cpu_baseline"] = run_cpu_baseline(nrhs, 64, steps_full, args.tol)
+        log("bench: CPU baseline %.4f solves/s" % out["cpu_baseline"]["value"])
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

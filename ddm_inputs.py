@@ -180,6 +180,23 @@ def config2(nrhs: int = 4) -> Workload:
                     notes="centres=%s" % np.round(centres, 4).tolist())
 
 
+def config2_cut(Ncut: int = 2, nrhs: int = 4) -> Workload:
+    """A Ncut x Ncut block of the config-2 workload: same mesh size h = 1/1024,
+    frequency, PML, overlap and 128^2 cores (M = 128 Ncut cells), nrhs seeded
+    Gaussians inside it.  Used as a bounded sample of config 2."""
+    M, n_pml = 128 * Ncut, 16
+    h = 1.0 / 1024
+    L = M * h
+    omega = 2 * math.pi * 102.4
+    k = omega
+    s0 = sigma0_for_reflection(1e-6, k, n_pml * h)
+    k2 = constant_k2(2, (M, M), n_pml, k)
+    rng = np.random.default_rng(BASE_SEED + 20 + Ncut)
+    centres = rng.uniform(0.1 * L, 0.9 * L, size=(nrhs, 2))
+    f = np.stack([gaussian_source(2, (M, M), n_pml, h, L, tuple(c), 2 * h) for c in centres])
+    return Workload("cfg2-cut-%dx%d" % (Ncut, Ncut), 2, (M, M), L, omega, n_pml, 8, (Ncut, Ncut), s0, k2, f)
+
+
 def config3(nrhs: int = 16, M: int = 2048, N: int = 16) -> Workload:
     """2D layered medium (8 layers, 1.5-4.5, 10% smoothed perturbation),
     8 ppw at c = 1.5, PML 20, 16x16 subdomains, overlap 8, nrhs Gaussians."""

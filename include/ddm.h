@@ -178,6 +178,27 @@ int ddm_transfer(ddm_handle *h, const void *lag1, const void *lag2, const void *
 /* Assembly of eq. tsum: u = sum_a beta_{0;a} U_a (packed U in, global u out). */
 int ddm_assemble(ddm_handle *h, const void *U, void *u, int nrhs);
 
+/* ---- observability -------------------------------------------------------- */
+
+/* Kernel classes of one DDM step. */
+enum { DDM_K_SUBST = 0, DDM_K_TRANSFER = 1, DDM_K_ASSEMBLE = 2, DDM_K_RESIDUAL = 3, DDM_K_NCLASS = 4 };
+
+typedef struct {
+    long launches[DDM_K_NCLASS];  /* kernel launches recorded                   */
+    double ms[DDM_K_NCLASS];      /* summed GPU time between the HIP events that
+                                     bracket each launch on the handle's stream */
+    double bytes[DDM_K_NCLASS];   /* algorithmic HBM bytes of those launches:
+                                     substitution = every stored block inverse
+                                     read once per sweep plus the block vectors
+                                     it reads and writes                        */
+} ddm_profile;
+
+/* Start (on != 0, counters reset) or stop recording per-launch HIP events. */
+int ddm_profile_enable(ddm_handle *h, int on);
+
+/* Synchronise the stream and return the counters since the last enable. */
+int ddm_profile_read(ddm_handle *h, ddm_profile *out);
+
 /* Library version string. */
 const char *ddm_version(void);
 

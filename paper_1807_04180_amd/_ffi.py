@@ -30,6 +30,12 @@ class DdmRhsInfo(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("status", ctypes.c_int)]
 
 
+class DdmProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_long * 4), ("ms", ctypes.c_double * 4), ("bytes", ctypes.c_double * 4)]
+
+
+KERNEL_CLASSES = ("substitution", "transfer", "assembly", "residual")
+
 _lib = None
 
 
@@ -68,7 +74,9 @@ def lib():
     L.ddm_local_solve.argtypes = [H, P, P, I]
     L.ddm_transfer.argtypes = [H, P, P, P, P, I]
     L.ddm_assemble.argtypes = [H, P, P, I]
-    for name in ("ddm_memory_required", "ddm_setup", "ddm_factor", "ddm_iterate", "ddm_solve", "ddm_sizes",
+    L.ddm_profile_enable.argtypes = [H, I]
+    L.ddm_profile_read.argtypes = [H, ctypes.POINTER(DdmProfile)]
+    for name in ("ddm_profile_enable", "ddm_profile_read", "ddm_memory_required", "ddm_setup", "ddm_factor", "ddm_iterate", "ddm_solve", "ddm_sizes",
                  "ddm_geometry", "ddm_apply", "ddm_residual", "ddm_restrict_core", "ddm_local_solve",
                  "ddm_transfer", "ddm_assemble"):
         getattr(L, name).restype = ctypes.c_int

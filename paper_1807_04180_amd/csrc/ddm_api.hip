@@ -19,6 +19,34 @@
 
 using namespace ddm;
 
+namespace ddm {
+
+static hipEvent_t pool_get(ddm_handle *h) {
+    if (!h->ev_pool.empty()) {
+        hipEvent_t e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(ddm_handle *h_, int cls_, double bytes_) : h(h_), cls(cls_), bytes(bytes_) {
+    if (!h->prof_on) return;
+    a = pool_get(h);
+    b = pool_get(h);
+    if (a && b) (void)hipEventRecord(a, h->stream);
+}
+
+ProfScope::~ProfScope() {
+    if (!h->prof_on || !a || !b) return;
+    (void)hipEventRecord(b, h->stream);
+    h->prof_recs.push_back(ddm_handle::ProfRec{a, b, cls, bytes});
+}
+
+}  // namespace ddm
+
 namespace {
 
 std::string g_setup_error;
@@ -92,6 +120,8 @@ void free_all(ddm_handle *h) {
                     h->d_coef_y};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto &r : h->prof_recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
     if (h->h_dots) (void)hipHostFree(h->h_dots);
 }
@@ -396,6 +426,30 @@ int solve_fgmres(ddm_handle *h, const double2 *f, double2 *x, int nrhs, const dd
 // C-ABI
 // ===========================================================================
 extern "C" {
+
+int ddm_profile_enable(ddm_handle *h, int on) {
+    if (!h) return DDM_EINVAL;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto &r : h->prof_recs) { h->ev_pool.push_back(r.a); h->ev_pool.push_back(r.b); }
+    h->prof_recs.clear();
+    h->prof_on = on != 0;
+    return DDM_OK;
+}
+
+int ddm_profile_read(ddm_handle *h, ddm_profile *out) {
+    if (!h || !out) return DDM_EINVAL;
+    memset(out, 0, sizeof(*out));
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, DDM_EHIP, "stream synchronize failed");
+    for (auto &r : h->prof_recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.cls >= 0 && r.cls < DDM_K_NCLASS) {
+            out->launches[r.cls] += 1;
+            out->ms[r.cls] += ms;
+            out->bytes[r.cls] += r.bytes;
+        }
+    }
+    return DDM_OK;
+}
 
 const char *ddm_version(void) { return "libddm 0.1 (gfx950, HIP)"; }
 

@@ -59,6 +59,8 @@ struct Plan {
     int ooff[3] = {0, 0, 0};
     std::vector<double> btab;   // side cut-off factor b(m), m = 0 .. n_ov
     std::vector<SolveItem> items;
+    std::vector<double> w_el_by_l;  // sum over subdomains with > l blocks of bs^2
+    std::vector<double> v_el_by_l;  // same, of bs
 };
 
 int build_plan(const ddm_problem *p, Plan *plan, std::string *err);
@@ -103,9 +105,24 @@ struct ddm_handle {
     double2 *d_dots = nullptr;      // (m+1) * nrhs dot products
     double2 *h_dots = nullptr;      // pinned
     double2 *d_coef_y = nullptr;    // Krylov combination coefficients
+    // per-launch HIP event profiling (ddm_profile_enable)
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct ProfRec { hipEvent_t a, b; int cls; double bytes; };
+    std::vector<ProfRec> prof_recs;
 };
 
 namespace ddm {
+
+// Bracket one launch with a pair of events when profiling is on.
+struct ProfScope {
+    ddm_handle *h;
+    int cls;
+    double bytes;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(ddm_handle *h_, int cls_, double bytes_);
+    ~ProfScope();
+};
 
 // ---- launchers (all enqueue on h->stream; return hipError_t) ----
 hipError_t launch_apply(ddm_handle *h, const double2 *u, double2 *out, int nrhs);

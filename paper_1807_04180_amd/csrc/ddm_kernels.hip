@@ -147,6 +147,8 @@ hipError_t launch_residual(ddm_handle *h, const double2 *f, const double2 *u, do
     int nblk = (int)((P.nglob + kBlock - 1) / kBlock);
     dim3 grid(nblk, nrhs);
     double *part_r = h->d_part, *part_f = h->d_part + (long long)nrhs * nblk;
+    // f and u read, r written (if requested), k^2 read
+    ProfScope ps(h, DDM_K_RESIDUAL, (double)P.nglob * (nrhs * (r ? 48.0 : 32.0) + 8.0));
     k_stencil<0><<<grid, kBlock, 0, h->stream>>>(f, u, r, h->d_k2, h->d_gcoef, grid_args(P), part_r, part_f);
     k_sum_partials<<<nrhs, kBlock, 0, h->stream>>>(part_r, nblk, d_rn2);
     k_sum_partials<<<nrhs, kBlock, 0, h->stream>>>(part_f, nblk, d_fn2);
@@ -379,6 +381,11 @@ template <typename TIN, typename TOUT>
 hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TIN *l3, TOUT *g, int nrhs) {
     const Plan &P = h->plan;
     dim3 grid((unsigned)((max_box(P) + kBlock - 1) / kBlock), P.nsub, nrhs);
+    // packed g written; neighbour strips (n_ov + 1 layers) read
+    double strip = 0.0;
+    for (const SubDesc &sd : P.subs)
+        for (int d = 0; d < P.dim; ++d) strip += 2.0 * (P.n_ov + 1) * (double)sd.nloc / sd.n[d];
+    ProfScope ps(h, DDM_K_TRANSFER, (double)nrhs * ((double)P.etot * sizeof(TOUT) + strip * sizeof(TIN)));
     k_transfer<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g,
                                                           pack_args(P));
     return hipGetLastError();
@@ -388,6 +395,8 @@ template <typename TIN>
 hipError_t launch_assemble(ddm_handle *h, const TIN *U, double2 *u, int nrhs, bool accumulate, const int *d_active) {
     const Plan &P = h->plan;
     dim3 grid((unsigned)((P.nglob + kBlock - 1) / kBlock), nrhs);
+    // local solutions read once per global node, u read (if accumulating) and written
+    ProfScope ps(h, DDM_K_ASSEMBLE, (double)P.nglob * nrhs * (sizeof(TIN) + (accumulate ? 32.0 : 16.0)));
     k_assemble<TIN><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_owner, P.ooff[0], P.ooff[1], P.ooff[2], P.N[0],
                                                     P.N[1], P.N[2], h->d_btab, U, u, pack_args(P),
                                                     accumulate ? 1 : 0, d_active);

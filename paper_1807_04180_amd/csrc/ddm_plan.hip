@@ -188,6 +188,13 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
     }
     P.etot = off;
     P.fel = foff;
+    P.w_el_by_l.assign(P.nb_max, 0.0);
+    P.v_el_by_l.assign(P.nb_max, 0.0);
+    for (const SubDesc &s : P.subs)
+        for (int l = 0; l < s.nb; ++l) {
+            P.w_el_by_l[l] += (double)s.bs * s.bs;
+            P.v_el_by_l[l] += (double)s.bs;
+        }
     P.btab.resize(p->n_ov + 1);
     for (int m = 0; m <= p->n_ov; ++m)
         P.btab[m] = m <= 1 ? 1.0 : (m >= p->n_ov ? 0.0 : beta0((double)(m - 1) / (double)(p->n_ov - 1)));

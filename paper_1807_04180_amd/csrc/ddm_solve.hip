@@ -121,12 +121,22 @@ template <typename T2, int RT>
 static hipError_t run_sweeps(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     const Plan &P = h->plan;
     const int nitems = (int)P.items.size();
+    const double es = sizeof(T2);
     for (int l = 0; l < P.nb_max; ++l) {
+        // algorithmic bytes: W_l once, g_l and z_{l-1} read, z_l written
+        ProfScope ps(h, DDM_K_SUBST, es * (P.w_el_by_l[l] + 3.0 * nrhs * P.v_el_by_l[l]));
         k_solve_line<T2, RT, false><<<nitems, kSThreads, 0, h->stream>>>(h->d_subs, h->d_items, h->d_coef,
                                                                            (const T2 *)h->d_W, g, x, l, nrhs, P.etot,
                                                                            P.dim);
     }
     for (int t = 0; t + 1 < P.nb_max; ++t) {
+        // lines l = nb - 2 - t of every subdomain: W_l once, x_{l+1} and z_l read, x_l written
+        double wb = 0.0, vb = 0.0;
+        for (const SubDesc &sd : P.subs) {
+            int l = sd.nb - 2 - t;
+            if (l >= 0) { wb += (double)sd.bs * sd.bs; vb += sd.bs; }
+        }
+        ProfScope ps(h, DDM_K_SUBST, es * (wb + 3.0 * nrhs * vb));
         k_solve_line<T2, RT, true><<<nitems, kSThreads, 0, h->stream>>>(h->d_subs, h->d_items, h->d_coef,
                                                                           (const T2 *)h->d_W, g, x, t, nrhs, P.etot,
                                                                           P.dim);

@@ -185,6 +185,16 @@ class HelmholtzDDM:
         self._check(self.lib.ddm_assemble(self._h, _ptr(U), _ptr(u), nrhs))
         return u
 
+    # -- observability -----------------------------------------------------
+    def profile_enable(self, on: bool = True):
+        self._check(self.lib.ddm_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        p = _ffi.DdmProfile()
+        self._check(self.lib.ddm_profile_read(self._h, ctypes.byref(p)))
+        return {name: dict(launches=int(p.launches[i]), ms=float(p.ms[i]), bytes=float(p.bytes[i]))
+                for i, name in enumerate(_ffi.KERNEL_CLASSES)}
+
     # -- drivers -------------------------------------------------------------
     def iterate(self, f: torch.Tensor, nsteps: int, want_relres: bool = True):
         nrhs = _check_c128(f, self.nglob, "f")
