@@ -199,6 +199,41 @@ int ddm_profile_enable(ddm_handle *h, int on);
 /* Synchronise the stream and return the counters since the last enable. */
 int ddm_profile_read(ddm_handle *h, ddm_profile *out);
 
+/* ---- tuning --------------------------------------------------------------- */
+
+/* Block-substitution kernel variants (the local solves of every DDM step):
+ *   0  one launch per block index over all subdomains (any block size; only
+ *      with the one-directional factor layout);
+ *   1  one workgroup per elimination chain walking all its blocks, the block
+ *      recurrence kept on chip (block size <= 256).  With the twisted layout
+ *      (default when there are at most 128 subdomains) every subdomain has two
+ *      chains that meet once at a middle block. */
+enum { DDM_SOLVE_PERLINE = 0, DDM_SOLVE_CHAIN = 1, DDM_SOLVE_NVARIANTS = 2 };
+
+/* Factor layout: twisted != 0 eliminates every subdomain from both ends
+ * towards a middle block (two chains per subdomain), 0 from the first block
+ * on.  Default: twisted when there are at most 128 subdomains.  Changing it
+ * discards the factors (call ddm_factor again). */
+int ddm_set_factor_layout(ddm_handle *h, int twisted);
+
+/* Select a variant; DDM_EINVAL if it does not apply to this problem. */
+int ddm_set_solve_variant(ddm_handle *h, int variant);
+
+/* Currently selected variant. */
+int ddm_get_solve_variant(const ddm_handle *h);
+
+/* Time every applicable variant on nrhs right-hand sides (reps local solves
+ * each, after one warm-up) and keep the fastest.  times_ms (host, may be
+ * NULL, DDM_SOLVE_NVARIANTS entries) receives the mean time per local solve,
+ * -1 for variants that do not apply or could not be launched. */
+int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms);
+
+/* Bound on the spin iterations of the wait of one chain for its partner at
+ * the middle block (default 2^22).  When a wait exceeds it the launch drains
+ * without waiting and the call reports DDM_EHIP.  Exposed so that this
+ * failure path can be exercised from the host. */
+int ddm_set_spin_limit(ddm_handle *h, int limit);
+
 /* Library version string. */
 const char *ddm_version(void);
 

@@ -42,6 +42,19 @@ __device__ inline void cfma(float2 &acc, float2 a, float2 b) {
     acc.y = fmaf(a.y, b.x, acc.y);
 }
 
+// c * x and g - c * x with every rounding fixed by explicit fma calls, so that
+// all template instantiations round identically (no contraction freedom)
+__device__ inline double2 cmul_fixed(double2 c, double2 x) {
+    double re = fma(c.x, x.x, -(c.y * x.y));
+    double im = fma(c.x, x.y, c.y * x.x);
+    return make_double2(re, im);
+}
+__device__ inline double2 cmsub_fixed(double2 g, double2 c, double2 x) {
+    double re = fma(-c.x, x.x, fma(c.y, x.y, g.x));
+    double im = fma(-c.x, x.y, fma(-c.y, x.x, g.y));
+    return make_double2(re, im);
+}
+
 __device__ inline double2 to_d2(double2 a) { return a; }
 __device__ inline double2 to_d2(float2 a) { return make_double2(a.x, a.y); }
 

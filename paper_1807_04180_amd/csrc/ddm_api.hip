@@ -104,7 +104,7 @@ size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
     b += P.owner.size() * sizeof(int) + P.btab.size() * sizeof(double) + P.items.size() * sizeof(SolveItem);
     b += (size_t)P.nglob * sizeof(double);                         // k2
     b += (size_t)P.fel * es;                                       // factors
-    b += (size_t)P.nsub * P.bs_max * P.bs_max * sizeof(double2);   // FP64 factor scratch (freed after factor)
+    b += (size_t)2 * P.nsub * P.bs_max * P.bs_max * sizeof(double2);  // FP64 factor scratch (freed after factor)
     b += (size_t)(1 + P.ring) * nrhs * P.etot * es;                // g + ring
     b += (size_t)nrhs * P.nglob * sizeof(double2);                 // residual / operator output
     if (mixed) b += (size_t)nrhs * P.etot * sizeof(double2);       // widening scratch
@@ -117,7 +117,7 @@ void free_all(ddm_handle *h) {
     void *ptrs[] = {h->d_subs, h->d_coef, h->d_gcoef, h->d_owner, h->d_btab, h->d_k2, h->d_items, h->d_W,
                     h->d_scratch, h->d_flags, h->d_g, h->d_ring[0], h->d_ring[1], h->d_ring[2], h->d_ring[3],
                     h->d_r, h->d_wide, h->d_part, h->d_norm, h->d_active, h->d_V, h->d_Z, h->d_dots,
-                    h->d_coef_y};
+                    h->d_coef_y, h->d_sync};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &r : h->prof_recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
@@ -175,6 +175,20 @@ void residual_host(ddm_handle *h, const double2 *f, const double2 *u, double2 *r
         rel[q] = fnq > 0 ? rn / fnq : rn;
         if (fn) (*fn)[q] = fnq;
     }
+}
+
+// The chain substitution raises a sticky flag when the wait for the partner
+// chain exceeded its spin bound; read and clear it (synchronises the stream).
+int check_abort(ddm_handle *h) {
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, h->d_sync + 2 * h->plan.nsub, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (flag) {
+        HIPCHK(hipMemsetAsync(h->d_sync + 2 * h->plan.nsub, 0, sizeof(int), h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return fail(h, DDM_EHIP, "substitution: the wait for the partner chain exceeded its spin bound; results invalid");
+    }
+    return DDM_OK;
 }
 
 int check_args(ddm_handle *h, int nrhs) {
@@ -451,6 +465,81 @@ int ddm_profile_read(ddm_handle *h, ddm_profile *out) {
     return DDM_OK;
 }
 
+int ddm_set_solve_variant(ddm_handle *h, int variant) {
+    if (!h) return DDM_EINVAL;
+    if (variant < 0 || variant >= kSolveNVariants || !solve_variant_ok(h->plan, variant))
+        return fail(h, DDM_EINVAL, "substitution variant does not apply to this problem");
+    h->solve_variant = variant;
+    return DDM_OK;
+}
+
+int ddm_set_factor_layout(ddm_handle *h, int twisted) {
+    if (!h) return DDM_EINVAL;
+    (void)hipStreamSynchronize(h->stream);
+    plan_set_twist(&h->plan, twisted != 0);
+    if (hipMemcpy(h->d_subs, h->plan.subs.data(), h->plan.subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return fail(h, DDM_EHIP, "descriptor upload failed");
+    h->factored = false;
+    if (!solve_variant_ok(h->plan, h->solve_variant))
+        h->solve_variant = solve_variant_ok(h->plan, kSolveChain) ? kSolveChain : kSolvePerLine;
+    return DDM_OK;
+}
+
+int ddm_get_solve_variant(const ddm_handle *h) { return h ? h->solve_variant : -1; }
+
+int ddm_set_spin_limit(ddm_handle *h, int limit) {
+    if (!h || limit < 1) return DDM_EINVAL;
+    h->spin_limit = limit;
+    return DDM_OK;
+}
+
+int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    if (!h->factored) return fail(h, DDM_ESTATE, "ddm_autotune before ddm_factor");
+    if (reps < 1) reps = 1;
+    const Plan &P = h->plan;
+    int best = -1, keep = h->solve_variant;
+    double best_ms = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        size_t es = elem_size(h->mixed);
+        HIPCHK(launch_fill_zero(h->d_g, (long long)nrhs * P.etot * es, h->stream));
+        for (int v = 0; v < kSolveNVariants; ++v) {
+            if (times_ms) times_ms[v] = -1.0;
+            if (!solve_variant_ok(P, v)) continue;
+            h->solve_variant = v;
+            hipError_t e = h->mixed ? launch_local_solve<float2>(h, (const float2 *)h->d_g, (float2 *)h->d_ring[0], nrhs)
+                                    : launch_local_solve<double2>(h, (const double2 *)h->d_g, (double2 *)h->d_ring[0], nrhs);
+            if (e != hipSuccess) { (void)hipGetLastError(); continue; }
+            HIPCHK(hipEventRecord(e0, h->stream));
+            for (int r = 0; r < reps; ++r)
+                HIPCHK(h->mixed ? launch_local_solve<float2>(h, (const float2 *)h->d_g, (float2 *)h->d_ring[0], nrhs)
+                                : launch_local_solve<double2>(h, (const double2 *)h->d_g, (double2 *)h->d_ring[0], nrhs));
+            HIPCHK(hipEventRecord(e1, h->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (check_abort(h) != DDM_OK) continue;
+            double mean = ms / reps;
+            if (times_ms) times_ms[v] = mean;
+            if (best < 0 || mean < best_ms) { best = v; best_ms = mean; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    } catch (const HipFail &e) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        h->solve_variant = keep;
+        return hip_fail(h, e);
+    }
+    h->solve_variant = best >= 0 ? best : kSolvePerLine;
+    return DDM_OK;
+}
+
 const char *ddm_version(void) { return "libddm 0.1 (gfx950, HIP)"; }
 
 const char *ddm_last_error(const ddm_handle *h) { return h ? h->err.c_str() : g_setup_error.c_str(); }
@@ -498,7 +587,7 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         dalloc(h, &h->d_btab, P.btab.size());
         dalloc(h, &h->d_items, P.items.size());
         dalloc(h, &h->d_k2, (size_t)P.nglob);
-        dalloc(h, &h->d_flags, (size_t)P.nsub);
+        dalloc(h, &h->d_flags, (size_t)3 * P.nsub);
         HIPCHK(hipMemcpy(h->d_subs, P.subs.data(), P.subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_coef, P.coef.data(), P.coef.size() * sizeof(Coef), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_gcoef, P.gcoef.data(), P.gcoef.size() * sizeof(Coef), hipMemcpyHostToDevice));
@@ -518,6 +607,9 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         dalloc(h, &h->d_part, h->part_cap);
         dalloc(h, &h->d_norm, (size_t)4 * nrhs_max);
         dalloc(h, &h->d_active, (size_t)nrhs_max);
+        dalloc(h, &h->d_sync, (size_t)2 * P.nsub + 1);
+        HIPCHK(hipMemset(h->d_sync, 0, (2 * P.nsub + 1) * sizeof(int)));
+        h->solve_variant = solve_variant_ok(P, kSolveChain) ? kSolveChain : kSolvePerLine;
         HIPCHK(hipHostMalloc((void **)&h->h_norm, 4 * nrhs_max * sizeof(double), hipHostMallocDefault));
         std::vector<int> ones(nrhs_max, 1);
         HIPCHK(hipMemcpy(h->d_active, ones.data(), nrhs_max * sizeof(int), hipMemcpyHostToDevice));
@@ -567,19 +659,20 @@ int ddm_factor(ddm_handle *h) {
     const Plan &P = h->plan;
     try {
         if (!h->d_scratch) {
-            HIPCHK(hipMalloc((void **)&h->d_scratch, (size_t)P.nsub * P.bs_max * P.bs_max * sizeof(double2)));
+            HIPCHK(hipMalloc((void **)&h->d_scratch, (size_t)2 * P.nsub * P.bs_max * P.bs_max * sizeof(double2)));
         }
         if (h->mixed) HIPCHK(launch_factor<float2>(h));
         else HIPCHK(launch_factor<double2>(h));
-        std::vector<int> flags(P.nsub);
-        HIPCHK(hipMemcpyAsync(flags.data(), h->d_flags, P.nsub * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        std::vector<int> flags(3 * P.nsub);
+        HIPCHK(hipMemcpyAsync(flags.data(), h->d_flags, 3 * P.nsub * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         HIPCHK(hipFree(h->d_scratch));
         h->d_scratch = nullptr;
-        for (int a = 0; a < P.nsub; ++a)
-            if (flags[a]) {
+        for (int q = 0; q < 3 * P.nsub; ++q)
+            if (flags[q]) {
                 char buf[160];
-                int t = flags[a] - 1;
+                int a = q < 2 * P.nsub ? q / 2 : q - 2 * P.nsub;
+                int t = flags[q] - 1;
                 snprintf(buf, sizeof buf, "subdomain %d: pivot below threshold in block %d, column %d", a,
                          t / P.subs[a].bs, t % P.subs[a].bs);
                 h->factored = false;
@@ -674,10 +767,10 @@ int ddm_local_solve(ddm_handle *h, const void *g, void *uhat, int nrhs) {
             }
             HIPCHK(launch_local_solve<double2>(h, src, (double2 *)uhat, nrhs));
         }
+        return check_abort(h);
     } catch (const HipFail &e) {
         return hip_fail(h, e);
     }
-    return DDM_OK;
 }
 
 int ddm_iterate(ddm_handle *h, const void *f, void *u, int nrhs, int nsteps, double *relres) {
@@ -700,11 +793,10 @@ int ddm_iterate(ddm_handle *h, const void *f, void *u, int nrhs, int nsteps, dou
         };
         if (h->mixed) run_steps<float2>(h, (const double2 *)f, (double2 *)u, nrhs, nsteps, check);
         else run_steps<double2>(h, (const double2 *)f, (double2 *)u, nrhs, nsteps, check);
-        HIPCHK(hipStreamSynchronize(h->stream));
+        return check_abort(h);
     } catch (const HipFail &e) {
         return hip_fail(h, e);
     }
-    return DDM_OK;
 }
 
 int ddm_solve(ddm_handle *h, const void *f, void *u, int nrhs, const ddm_solve_opts *opts, ddm_rhs_info *info) {
@@ -722,12 +814,15 @@ int ddm_solve(ddm_handle *h, const void *f, void *u, int nrhs, const ddm_solve_o
         for (int q = 0; q < nrhs; ++q)
             if (!std::isfinite(h->h_norm[q])) return fail(h, DDM_EINVAL, "source has non-finite entries");
         ddm_solve_opts o = *opts;
-        if (o.method == DDM_FGMRES) {
-            if (h->mixed) return solve_fgmres<float2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
-            return solve_fgmres<double2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
-        }
-        if (h->mixed) return solve_stationary<float2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
-        return solve_stationary<double2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
+        int r;
+        if (o.method == DDM_FGMRES)
+            r = h->mixed ? solve_fgmres<float2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info)
+                         : solve_fgmres<double2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
+        else
+            r = h->mixed ? solve_stationary<float2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info)
+                         : solve_stationary<double2>(h, (const double2 *)f, (double2 *)u, nrhs, o, info);
+        int a = check_abort(h);
+        return a != DDM_OK ? a : r;
     } catch (const HipFail &e) {
         return hip_fail(h, e);
     } catch (const std::string &s) {

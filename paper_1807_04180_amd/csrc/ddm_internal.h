@@ -20,6 +20,9 @@ struct SubDesc {
     long long off;         // packed offset (elements per RHS)
     long long nloc;        // box size
     int nb;                // number of blocks (grid lines / planes) along the last axis
+    int mid;               // twist block: blocks < mid are eliminated from the first block
+                           // on, blocks > mid from the last block on; mid = nb - 1 gives
+                           // the one-directional factorisation
     int bs;                // block size (n[0] in 2D, n[0]*n[1] in 3D)
     long long foff;        // factor offset (elements)
     int coff[3];           // offsets of this box's per-axis coefficient tables
@@ -59,11 +62,14 @@ struct Plan {
     int ooff[3] = {0, 0, 0};
     std::vector<double> btab;   // side cut-off factor b(m), m = 0 .. n_ov
     std::vector<SolveItem> items;
+    bool twisted = false;           // factor layout: both-ends elimination
     std::vector<double> w_el_by_l;  // sum over subdomains with > l blocks of bs^2
     std::vector<double> v_el_by_l;  // same, of bs
 };
 
 int build_plan(const ddm_problem *p, Plan *plan, std::string *err);
+// choose the elimination layout (sets mid of every subdomain)
+void plan_set_twist(Plan *plan, bool twisted);
 
 }  // namespace ddm
 
@@ -105,6 +111,10 @@ struct ddm_handle {
     double2 *d_dots = nullptr;      // (m+1) * nrhs dot products
     double2 *h_dots = nullptr;      // pinned
     double2 *d_coef_y = nullptr;    // Krylov combination coefficients
+    // substitution kernel variant (autotuned) and persistent-launch sync state
+    int solve_variant = 0;
+    int *d_sync = nullptr;          // 2 nsub meeting flags + 1 abort flag
+    int spin_limit = 1 << 22;
     // per-launch HIP event profiling (ddm_profile_enable)
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;
@@ -142,6 +152,10 @@ template <typename T>
 hipError_t launch_factor(ddm_handle *h);
 template <typename T>
 hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs);
+
+// substitution variants
+enum { kSolvePerLine = 0, kSolveChain = 1, kSolveNVariants = 2 };
+bool solve_variant_ok(const Plan &P, int variant);
 
 hipError_t launch_convert_c128_to_c64(const double2 *in, float2 *out, long long n, hipStream_t s);
 hipError_t launch_convert_c64_to_c128(const float2 *in, double2 *out, long long n, hipStream_t s);

@@ -195,10 +195,18 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
             P.w_el_by_l[l] += (double)s.bs * s.bs;
             P.v_el_by_l[l] += (double)s.bs;
         }
+    // two chains per subdomain (both-ends elimination) while they all fit on
+    // the chip's 256 compute units, one otherwise
+    plan_set_twist(&P, P.nsub <= 128 && P.nb_max >= 4);
     P.btab.resize(p->n_ov + 1);
     for (int m = 0; m <= p->n_ov; ++m)
         P.btab[m] = m <= 1 ? 1.0 : (m >= p->n_ov ? 0.0 : beta0((double)(m - 1) / (double)(p->n_ov - 1)));
     return DDM_OK;
+}
+
+void plan_set_twist(Plan *plan, bool twisted) {
+    plan->twisted = twisted;
+    for (SubDesc &s : plan->subs) s.mid = twisted ? s.nb / 2 : s.nb - 1;
 }
 
 }  // namespace ddm

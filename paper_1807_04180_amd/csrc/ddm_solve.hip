@@ -58,9 +58,9 @@ __global__ __launch_bounds__(kSThreads) void k_solve_line(const SubDesc *__restr
                     const int j = j0 + jj;
                     if (!BACKWARD) {
                         v = to_d2(g[base + (long long)l * bs + j]);
-                        if (l > 0) v = csub(v, cmul(cpl, to_d2(x[base + (long long)(l - 1) * bs + j])));
+                        if (l > 0) v = cmsub_fixed(v, cpl, to_d2(x[base + (long long)(l - 1) * bs + j]));
                     } else {
-                        v = cmul(cpl, to_d2(x[base + (long long)(l + 1) * bs + j]));
+                        v = cmul_fixed(cpl, to_d2(x[base + (long long)(l + 1) * bs + j]));
                     }
                 }
                 vs[jj * RT + q] = from_d2<T2>(v);
@@ -117,6 +117,209 @@ __global__ __launch_bounds__(kSThreads) void k_solve_line(const SubDesc *__restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Chain variant: one workgroup (16 waves) owns a whole elimination chain of a
+// subdomain and walks its blocks; the recurrence never leaves the compute
+// unit (block vectors in LDS / registers), only W_l streams from HBM.
+//   chain 0 (blocks 0 .. mid-1):  y_0 = W_0 g_0, y_l = W_l (g_l - cm(l) y_{l-1})
+//   chain 1 (blocks nb-1 .. mid+1): y_l = W_l (g_l - cp(l) y_{l+1})
+//   middle:  x_mid = W_mid (g_mid - cm(mid) y_{mid-1} - cp(mid) y_{mid+1})
+//   back:    x_l = y_l - W_l (cp(l) x_{l+1})  (chain 0, l = mid-1 .. 0)
+//            x_l = y_l - W_l (cm(l) x_{l-1})  (chain 1, l = mid+1 .. nb-1)
+// (W_l here is the stored inverse of the chain's Schur block.)  The two
+// chains of a subdomain meet once, at the middle block: each publishes its
+// last y through global memory with an agent-scope release/acquire pair.
+// GEMV mapping: R = ceil(bs/64) row tiles, CG = 16 / R column groups; wave w
+// takes row tile w % R and columns w / R, w / R + CG, ...  The first batch of
+// the next block's W is loaded before the current block's reduction.
+// ---------------------------------------------------------------------------
+constexpr int kCThreads = 1024;
+constexpr int kCWaves = 16;
+
+__device__ inline void wait_flag(int *f, int target, int *abort_flag, int spin_limit) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins >= spin_limit) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    }
+    __syncthreads();
+}
+
+// columns per W batch (two batches in flight per wave)
+template <typename T2> struct ChainBatch { static constexpr int value = 8; };
+template <> struct ChainBatch<double2> { static constexpr int value = 4; };
+
+template <typename T2, int RT>
+__global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__restrict__ subs,
+                                                           const Coef *__restrict__ coef, const T2 *__restrict__ W,
+                                                           const T2 *__restrict__ g, T2 *__restrict__ x, int nrhs,
+                                                           long long etot, int dim, int twisted, int *flags,
+                                                           int *abort_flag, int spin_limit) {
+    extern __shared__ unsigned char lds_raw[];
+    constexpr int kCBatch = ChainBatch<T2>::value;
+    const int a = twisted ? (int)(blockIdx.x >> 1) : (int)blockIdx.x;
+    const int chain = twisted ? (int)(blockIdx.x & 1) : 0;
+    const SubDesc &s = subs[a];
+    const int nb = s.nb, bs = s.bs, mid = s.mid, ax = dim - 1;
+    const long long off = s.off;
+    const int R = (bs + 63) >> 6;
+    const int CG = kCWaves / R;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int rt = wv % R, cg = wv / R;
+    const bool gemv = cg < CG;
+    const int row = rt * 64 + lane;
+    const bool rowok = gemv && row < bs;
+    const int bsp = R * 64;
+    T2 *vs = (T2 *)lds_raw;                 // [bsp][RT]  current v
+    T2 *red = vs + (size_t)bsp * RT;        // [CG][RT][bsp] partial sums
+    // this chain's block sequence: forward blocks, the middle, backward blocks
+    const int nf = chain == 0 ? mid : nb - 1 - mid;
+    if (twisted == 0 && chain == 1) return;
+    const int nsteps = 2 * nf + 1;
+    const int dirf = chain == 0 ? 1 : -1;   // forward direction in l
+    const int lfirst = chain == 0 ? 0 : nb - 1;
+
+    for (int r0 = 0; r0 < nrhs; r0 += RT) {
+        const int nr = nrhs - r0 < RT ? nrhs - r0 : RT;
+        // initial v = g_{lfirst} (the middle step builds its own v)
+        if (nf > 0) {
+            const int l0 = lfirst;
+            for (int e = threadIdx.x; e < bsp * RT; e += kCThreads) {
+                const int i = e / RT, q = e % RT;
+                vs[e] = (i < bs && q < nr) ? g[(long long)(r0 + q) * etot + off + (long long)l0 * bs + i]
+                                           : czero<T2>();
+            }
+        }
+        __syncthreads();
+        auto step_l = [&](int t) {  // block index of step t
+            if (t < nf) return lfirst + dirf * t;
+            if (t == nf) return mid;
+            return mid - dirf * (t - nf);
+        };
+        const T2 *Wbase = W + s.foff;
+        const long long bs2 = (long long)bs * bs;
+        // W streaming, double-buffered in batches of kCBatch columns; the
+        // batch after a block's last is the next block's first
+        T2 wb[kCBatch];
+        {
+            const T2 *Wl = Wbase + (long long)step_l(0) * bs2;
+#pragma unroll
+            for (int u = 0; u < kCBatch; ++u) {
+                const int j = cg + CG * u;
+                wb[u] = (rowok && j < bs) ? Wl[(long long)j * bs + row] : czero<T2>();
+            }
+        }
+        for (int t = 0; t < nsteps; ++t) {
+            const int l = step_l(t);
+            const int kind = t < nf ? 0 : (t == nf ? 1 : 2);  // 0 forward, 1 middle, 2 backward
+            if (t == nf) {
+                // entering the middle block: v = g_mid - cm(mid) y_{mid-1} - cp(mid) y_{mid+1}
+                const Coef cmid = coef[s.coff[ax] + mid];
+                __syncthreads();  // this chain's y stores are issued
+                if (twisted) {
+                    // flags count RHS tiles: tile k publishes k + 1 (no reset
+                    // inside the launch, so a fast chain cannot erase a signal)
+                    const int epoch = r0 / RT + 1;
+                    __threadfence();
+                    __syncthreads();
+                    if (threadIdx.x == 0)
+                        __hip_atomic_store(flags + 2 * a + chain, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    wait_flag(flags + 2 * a + (1 - chain), epoch, abort_flag, spin_limit);
+                }
+                for (int e = threadIdx.x; e < bsp * RT; e += kCThreads) {
+                    const int i = e / RT, q = e % RT;
+                    double2 v = make_double2(0, 0);
+                    if (i < bs && q < nr) {
+                        const long long base = (long long)(r0 + q) * etot + off;
+                        v = to_d2(g[base + (long long)mid * bs + i]);
+                        if (mid > 0) v = cmsub_fixed(v, cmid.cm, to_d2(x[base + (long long)(mid - 1) * bs + i]));
+                        if (mid < nb - 1) v = cmsub_fixed(v, cmid.cp, to_d2(x[base + (long long)(mid + 1) * bs + i]));
+                    }
+                    vs[e] = from_d2<T2>(v);
+                }
+                __syncthreads();
+            }
+            // ---- GEMV: acc = W_l v ----
+            T2 acc[RT];
+#pragma unroll
+            for (int q = 0; q < RT; ++q) acc[q] = czero<T2>();
+            const int kmax = gemv ? (bs - cg + CG - 1) / CG : 0;  // columns of this wave
+            const int lnext = t + 1 < nsteps ? step_l(t + 1) : -1;
+            for (int k0 = 0; k0 < kmax; k0 += kCBatch) {
+                const bool more = k0 + kCBatch < kmax;
+                const int ln = more ? l : lnext;
+                const int kn = more ? k0 + kCBatch : 0;
+                T2 wn[kCBatch];
+                const T2 *Wn = Wbase + (long long)(ln >= 0 ? ln : 0) * bs2;
+#pragma unroll
+                for (int u = 0; u < kCBatch; ++u) {
+                    const int j = cg + CG * (kn + u);
+                    wn[u] = (ln >= 0 && rowok && j < bs) ? Wn[(long long)j * bs + row] : czero<T2>();
+                }
+#pragma unroll
+                for (int u = 0; u < kCBatch; ++u) {
+                    const int j = cg + CG * (k0 + u);
+                    if (j < bs) {
+#pragma unroll
+                        for (int q = 0; q < RT; ++q) cfma(acc[q], wb[u], vs[j * RT + q]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kCBatch; ++u) wb[u] = wn[u];
+            }
+            if (gemv) {
+#pragma unroll
+                for (int q = 0; q < RT; ++q) red[((size_t)cg * RT + q) * bsp + row] = acc[q];
+            }
+            __syncthreads();
+            // ---- reduce over column groups; update x; build the next v ----
+            // next-step coefficient and neighbour for v
+            const int tn = t + 1;
+            for (int e = threadIdx.x; e < bsp * RT; e += kCThreads) {
+                const int i = e / RT, q = e % RT;
+                if (i >= bs) continue;
+                T2 sum = red[(size_t)q * bsp + i];
+                for (int c = 1; c < CG; ++c) {
+                    T2 o = red[((size_t)c * RT + q) * bsp + i];
+                    sum.x += o.x;
+                    sum.y += o.y;
+                }
+                const long long base = (long long)(r0 + q) * etot + off;
+                T2 res = sum;                       // forward: y_l, middle: x_mid
+                if (kind == 2 && q < nr) {          // backward: x_l = y_l - W_l v
+                    T2 y = x[base + (long long)l * bs + i];
+                    res.x = y.x - sum.x;
+                    res.y = y.y - sum.y;
+                }
+                if (q < nr && (kind != 1 || chain == 0)) x[base + (long long)l * bs + i] = res;
+                if (tn < nsteps && tn != nf) {
+                    // next v from this block's result
+                    double2 v;
+                    const int ln = step_l(tn);
+                    if (kind == 0) {                // forward: g_ln - c * y_l
+                        const Coef cn = coef[s.coff[ax] + ln];
+                        const double2 c = chain == 0 ? cn.cm : cn.cp;
+                        v = q < nr ? cmsub_fixed(to_d2(g[base + (long long)ln * bs + i]), c, to_d2(res))
+                                   : make_double2(0, 0);
+                    } else {                        // after middle / backward: c * x_l
+                        const Coef cn = coef[s.coff[ax] + ln];
+                        const double2 c = chain == 0 ? cn.cp : cn.cm;
+                        v = q < nr ? cmul_fixed(c, to_d2(res)) : make_double2(0, 0);
+                    }
+                    vs[e] = from_d2<T2>(v);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <typename T2, int RT>
 static hipError_t run_sweeps(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     const Plan &P = h->plan;
@@ -144,14 +347,81 @@ static hipError_t run_sweeps(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     return hipGetLastError();
 }
 
-// g and x must not alias (rows of z_l are written while other workgroups of
-// the same subdomain still read g_l).
 template <typename T>
-hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs) {
+static hipError_t run_perline(ddm_handle *h, const T *g, T *x, int nrhs) {
     if (nrhs <= 1) return run_sweeps<T, 1>(h, g, x, nrhs);
     if (nrhs <= 2) return run_sweeps<T, 2>(h, g, x, nrhs);
     if (nrhs <= 4) return run_sweeps<T, 4>(h, g, x, nrhs);
     return run_sweeps<T, 8>(h, g, x, nrhs);
+}
+
+template <typename T2, int RT>
+static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
+    const Plan &P = h->plan;
+    const double es = sizeof(T2);
+    double vb = 0.0;
+    for (const SubDesc &sd : P.subs) vb += (double)sd.nloc;
+    const int ntile = (nrhs + RT - 1) / RT;
+    // W read once per sweep and RHS tile; block vectors: g read, y written,
+    // y read back and x written
+    ProfScope ps(h, DDM_K_SUBST, es * (2.0 * (double)P.fel * ntile + 4.0 * nrhs * vb));
+    const int R = (P.bs_max + 63) / 64;
+    const int CG = kCWaves / R;
+    size_t lds = (size_t)R * 64 * RT * (1 + CG) * sizeof(T2);
+    hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain<T2, RT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (P.twisted) {
+        e = launch_fill_zero(h->d_sync, (long long)(2 * P.nsub) * sizeof(int), h->stream);
+        if (e != hipSuccess) return e;
+        const SubDesc *a0 = h->d_subs;
+        const Coef *a1 = h->d_coef;
+        const T2 *a2 = (const T2 *)h->d_W;
+        const T2 *a3 = g;
+        T2 *a4 = x;
+        int a5 = nrhs;
+        long long a6 = P.etot;
+        int a7 = P.dim, a8 = 1;
+        int *a9 = h->d_sync, *a10 = h->d_sync + 2 * P.nsub;
+        int a11 = h->spin_limit;
+        void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11};
+        // the two chains of a subdomain meet once: they must be co-resident
+        return hipLaunchCooperativeKernel((const void *)k_solve_chain<T2, RT>, dim3(2 * P.nsub), dim3(kCThreads),
+                                          args, lds, h->stream);
+    }
+    k_solve_chain<T2, RT><<<P.nsub, kCThreads, lds, h->stream>>>(h->d_subs, h->d_coef, (const T2 *)h->d_W, g, x,
+                                                                 nrhs, P.etot, P.dim, 0, h->d_sync,
+                                                                 h->d_sync + 2 * P.nsub, h->spin_limit);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
+    if (nrhs <= 1) return run_chain<T, 1>(h, g, x, nrhs);
+    if (nrhs <= 2) return run_chain<T, 2>(h, g, x, nrhs);
+    if constexpr (sizeof(T) == sizeof(double2)) {
+        return run_chain<T, 4>(h, g, x, nrhs);
+    } else {
+        if (nrhs <= 4) return run_chain<T, 4>(h, g, x, nrhs);
+        return run_chain<T, 8>(h, g, x, nrhs);
+    }
+}
+
+bool solve_variant_ok(const Plan &P, int variant) {
+    switch (variant) {
+        case kSolvePerLine: return !P.twisted;
+        case kSolveChain: return P.bs_max <= 256;
+        default: return false;
+    }
+}
+
+// g and x must not alias (the substitution reads g_l while x_l is written).
+template <typename T>
+hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs) {
+    int v = h->solve_variant;
+    if (!solve_variant_ok(h->plan, v)) v = solve_variant_ok(h->plan, kSolveChain) ? kSolveChain : kSolvePerLine;
+    if (v == kSolveChain) return run_chain_rt<T>(h, g, x, nrhs);
+    return run_perline<T>(h, g, x, nrhs);
 }
 
 template hipError_t launch_local_solve<double2>(ddm_handle *, const double2 *, double2 *, int);

@@ -185,6 +185,29 @@ class HelmholtzDDM:
         self._check(self.lib.ddm_assemble(self._h, _ptr(U), _ptr(u), nrhs))
         return u
 
+    # -- tuning --------------------------------------------------------------
+    def set_factor_layout(self, twisted: bool, refactor: bool = True):
+        self._check(self.lib.ddm_set_factor_layout(self._h, 1 if twisted else 0))
+        self.factored = False
+        if refactor:
+            self.factor()
+
+    # -- tuning --------------------------------------------------------------
+    def set_solve_variant(self, variant):
+        v = _ffi.SOLVE_VARIANTS.index(variant) if isinstance(variant, str) else int(variant)
+        self._check(self.lib.ddm_set_solve_variant(self._h, v))
+
+    def solve_variant(self) -> str:
+        return _ffi.SOLVE_VARIANTS[self.lib.ddm_get_solve_variant(self._h)]
+
+    def autotune(self, nrhs: Optional[int] = None, reps: int = 3) -> dict:
+        t = (ctypes.c_double * len(_ffi.SOLVE_VARIANTS))()
+        self._check(self.lib.ddm_autotune(self._h, int(nrhs or self.nrhs_max), reps, t))
+        return {name: (t[i] if t[i] >= 0 else None) for i, name in enumerate(_ffi.SOLVE_VARIANTS)}
+
+    def set_spin_limit(self, limit: int):
+        self._check(self.lib.ddm_set_spin_limit(self._h, int(limit)))
+
     # -- observability -----------------------------------------------------
     def profile_enable(self, on: bool = True):
         self._check(self.lib.ddm_profile_enable(self._h, 1 if on else 0))

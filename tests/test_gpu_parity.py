@@ -163,3 +163,86 @@ def test_deterministic_bitwise(pair):
     u1, r1 = g.iterate(f, 5)
     u2, r2 = g.iterate(f, 5)
     assert torch.equal(u1, u2) and r1 == r2
+
+
+LAYOUTS = {"twisted": (True, ["chain"]), "onedir": (False, ["perline", "chain"])}
+
+
+@pytest.mark.parametrize("layout", sorted(LAYOUTS))
+def test_local_solve_layouts_and_variants(pair, layout):
+    """Both factor layouts (two-ended / one-directional elimination) and every
+    substitution variant that applies: oracle parity, repeatability and
+    batch invariance (bitwise)."""
+    w, o, g = pair
+    twisted, variants = LAYOUTS[layout]
+    g.set_factor_layout(twisted)
+    try:
+        for variant in variants:
+            g.set_solve_variant(variant)
+            for nrhs in (1, 5):
+                gin = di.random_field((nrhs, o.etot), seed=70 + nrhs)
+                xo = o.local_solve(gin)
+                xg = _n(g.local_solve(_t(gin)))
+                assert relerr(xg, xo, axis=1) < 1e-10, (variant, nrhs)
+                assert np.array_equal(_n(g.local_solve(_t(gin))), xg), (variant, nrhs)
+                x0 = _n(g.local_solve(_t(gin[nrhs - 1:nrhs])))
+                assert np.array_equal(x0[0], xg[nrhs - 1]), (variant, nrhs)
+    finally:
+        g.set_factor_layout(True)
+
+
+@pytest.mark.parametrize("layout", sorted(LAYOUTS))
+def test_iterate_layouts_match_oracle(pair, layout):
+    w, o, g = pair
+    twisted, variants = LAYOUTS[layout]
+    g.set_factor_layout(twisted)
+    try:
+        for variant in variants:
+            g.set_solve_variant(variant)
+            nsteps = sum(w.N) + 3
+            uo, _ = o.ddm_run(w.f, nsteps)
+            ug, _ = g.iterate(_t(w.f.reshape(w.nrhs, -1)), nsteps)
+            assert relerr(_n(ug), uo, axis=1) < 1e-10, variant
+    finally:
+        g.set_factor_layout(True)
+
+
+def test_chain_mixed_matches_oracle():
+    w = CASES["2d-3x3-layered"]()
+    o, g = make_pair(w, nrhs_max=9, mixed=True)
+    for nrhs in (3, 9):  # RHS tiles of 4 and 8
+        gin = di.random_field((nrhs, o.etot), seed=51)
+        assert relerr(_n(g.local_solve(_t(gin))), o.local_solve(gin), axis=1) < 5e-5
+    g.close()
+
+
+def test_chain_spin_bound_drains_and_reports():
+    """A spin bound of 1 lets a chain give up waiting for its partner at the
+    middle block: the launch must still drain (no hang) and report EHIP unless
+    the partner was already there; afterwards, with the normal bound, results
+    are correct again."""
+    w = CASES["2d-3x3-layered"]()
+    o, g = make_pair(w, nrhs_max=2)
+    g.set_solve_variant("chain")
+    gin = di.random_field((2, o.etot), seed=52)
+    xo = o.local_solve(gin)
+    g.set_spin_limit(1)
+    try:
+        x = g.local_solve(_t(gin))
+        assert relerr(_n(x), xo, axis=1) < 1e-10
+    except ddm.DDMError as e:
+        assert e.code == ddm._ffi.DDM_EHIP
+    g.set_spin_limit(1 << 22)
+    assert relerr(_n(g.local_solve(_t(gin))), xo, axis=1) < 1e-10
+    g.close()
+
+
+def test_autotune_picks_an_applicable_variant(pair):
+    w, o, g = pair
+    g.set_factor_layout(False)
+    try:
+        times = g.autotune(nrhs=3, reps=2)
+        assert times["perline"] is not None and times["chain"] is not None
+        assert times[g.solve_variant()] == min(t for t in times.values() if t is not None)
+    finally:
+        g.set_factor_layout(True)
