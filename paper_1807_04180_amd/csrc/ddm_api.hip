@@ -136,8 +136,11 @@ const T *ring_at(ddm_handle *h, int s) {  // uhat^s (s >= 1) or null for s <= 0
 // given it is called after each step with the per-RHS relative residuals and
 // may deactivate RHS (their u is frozen) or request a restart of the
 // recursion on a new source (refinement); it returns false to stop.
+// rcorr: residual-corrected sources (the check must leave r = f - L_h u of
+// the current iterate there after every step)
 template <typename T, typename Check>
-void run_steps(ddm_handle *h, const double2 *f, double2 *u, int nrhs, int nsteps, Check check) {
+void run_steps(ddm_handle *h, const double2 *f, double2 *u, int nrhs, int nsteps, Check check,
+               const double2 *rcorr = nullptr) {
     const Plan &P = h->plan;
     const double2 *src = f;
     int s = 0;
@@ -145,7 +148,8 @@ void run_steps(ddm_handle *h, const double2 *f, double2 *u, int nrhs, int nsteps
         ++s;
         T *g = (T *)h->d_g;
         if (s == 1) HIPCHK((launch_restrict<double2, T>(h, src, g, nrhs)));
-        else HIPCHK((launch_transfer<T, T>(h, ring_at<T>(h, s - 1), ring_at<T>(h, s - 2), ring_at<T>(h, s - 3), g, nrhs)));
+        else HIPCHK((launch_transfer<T, T>(h, ring_at<T>(h, s - 1), ring_at<T>(h, s - 2), ring_at<T>(h, s - 3), g, nrhs,
+                                           rcorr)));
         T *us = (T *)h->d_ring[s % P.ring];
         HIPCHK(launch_local_solve<T>(h, g, us, nrhs));
         HIPCHK(launch_assemble<T>(h, us, u, nrhs, true, h->d_active));
@@ -221,9 +225,9 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
     std::vector<double> secs(nrhs, 0.0), final_rel(nrhs, 1.0);
     int nsum = P.N[0] + P.N[1] + P.N[2] - (3 - P.dim);
     int refine_every = o.refine_every > 0 ? o.refine_every : nsum;
-    double2 *rsrc = h->d_r;  // restart source (residual) lives in d_r
+    double2 *rsrc = h->d_r;  // residual (corrected sources) / restart source
     auto check = [&](int it, const double2 **restart) -> bool {
-        residual_host(h, f, u, nullptr, nrhs, rel, &fn);
+        residual_host(h, f, u, h->mixed ? rsrc : nullptr, nrhs, rel, &fn);
         bool all = true, changed = false;
         bool stalled = false;
         for (int q = 0; q < nrhs; ++q) {
@@ -246,14 +250,13 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
         if (all || it >= o.maxiter) return false;
         if (h->mixed && stalled) {
             // iterative refinement: restart the complex64 recursion on the FP64
-            // residual r = f - L u; u keeps accumulating the corrections
-            HIPCHK(launch_residual(h, f, u, rsrc, nrhs, h->d_norm, h->d_norm + nrhs));
+            // residual r = f - L u (already in rsrc); u keeps accumulating
             for (int q = 0; q < nrhs; ++q) { since_gain[q] = 0; last_gain_rel[q] = rel[q]; }
             *restart = rsrc;
         }
         return true;
     };
-    run_steps<T>(h, f, u, nrhs, o.maxiter, check);
+    run_steps<T>(h, f, u, nrhs, o.maxiter, check, h->mixed ? rsrc : nullptr);
     HIPCHK(hipStreamSynchronize(h->stream));
     int worst = DDM_OK;
     double t1 = now_s();

@@ -143,7 +143,8 @@ hipError_t launch_norm2(ddm_handle *h, const double2 *x, long long n, int nrhs, 
 template <typename TIN, typename TOUT>
 hipError_t launch_restrict(ddm_handle *h, const TIN *f, TOUT *g, int nrhs);
 template <typename TIN, typename TOUT>
-hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TIN *l3, TOUT *g, int nrhs);
+hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TIN *l3, TOUT *g, int nrhs,
+                           const double2 *rcorr = nullptr);
 template <typename TIN>
 hipError_t launch_assemble(ddm_handle *h, const TIN *U, double2 *u, int nrhs, bool accumulate,
                            const int *d_active);

@@ -229,11 +229,18 @@ __device__ inline double2 weighted(const SubDesc &b, const int *dd, const TIN *_
     return cscale(to_d2(src[b.off + li]), beta);
 }
 
+// With rcorr (residual-corrected sources): on the core of a the source is
+// built from the FP64 residual r = f - L_h u of the current iterate instead:
+//     g_a(p) = r(p) - sum_{b: lag >= 2} Psi_{b->a}(uhat_b^s + ... + uhat_b^{s-lag+2})(p),
+// which equals the plain transfer in exact arithmetic (discrete residual
+// identity) and feeds the rounding errors of the local solves back as
+// sources.  Rows outside the core keep the plain transfer.
 template <typename TIN, typename TOUT>
 __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__ subs, const Coef *__restrict__ coef,
                                                      const double *__restrict__ k2, const double *__restrict__ btab,
                                                      const TIN *__restrict__ l1, const TIN *__restrict__ l2,
-                                                     const TIN *__restrict__ l3, TOUT *__restrict__ g, PackArgs A) {
+                                                     const TIN *__restrict__ l3, TOUT *__restrict__ g, PackArgs A,
+                                                     const double2 *__restrict__ rcorr) {
     int a = blockIdx.y, rhs = blockIdx.z;
     const SubDesc &s = subs[a];
     long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -255,6 +262,9 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
         inhi[d] = d < A.dim && p[d] <= s.chi[d] && p[d] >= s.chi[d] - A.n_ov + 1;
     }
     bool any = inlo[0] || inhi[0] || inlo[1] || inhi[1] || inlo[2] || inhi[2];
+    const bool corrected = rcorr && p[0] >= s.clo[0] && p[0] <= s.chi[0] && p[1] >= s.clo[1] &&
+                           p[1] <= s.chi[1] && p[2] >= s.clo[2] && p[2] <= s.chi[2];
+    if (corrected) acc = rcorr[rhs * A.nglob + glob_index(A, p[0], p[1], p[2])];
     if (any) {
         double kk = k2[glob_index(A, p[0], p[1], p[2])];
         Coef cf[3];
@@ -279,10 +289,24 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
                     if (!ok) continue;
                     int lag = s.lag[slot];
                     const TIN *src = lag == 1 ? l1 : (lag == 2 ? l2 : l3);
+                    const TIN *src2 = nullptr;
+                    if (corrected) {
+                        // edge / face terms are inside r; lag >= 2 terms use the
+                        // newer solutions: uhat^s (+ uhat^{s-1} for lag 3)
+                        if (lag == 1) continue;
+                        src = l1;
+                        src2 = lag == 3 ? l2 : nullptr;
+                    }
                     if (!src) continue;
                     src += rhs * A.etot;
+                    if (src2) src2 += rhs * A.etot;
                     const SubDesc &b = subs[bidx];
-                    double2 w0 = weighted(b, dd, src, btab, A.n_ov, p[0], p[1], p[2]);
+                    auto wsum = [&](int q0, int q1, int q2) {
+                        double2 v = weighted(b, dd, src, btab, A.n_ov, q0, q1, q2);
+                        if (src2) v = cadd(v, weighted(b, dd, src2, btab, A.n_ov, q0, q1, q2));
+                        return v;
+                    };
+                    double2 w0 = wsum(p[0], p[1], p[2]);
                     double2 Lw = cscale(w0, kk);
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
@@ -290,13 +314,12 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
                         int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
                         qp[d] += 1;
                         qm[d] -= 1;
-                        double2 wp = p[d] < s.hi[d] ? weighted(b, dd, src, btab, A.n_ov, qp[0], qp[1], qp[2])
-                                                    : make_double2(0, 0);
-                        double2 wm = p[d] > s.lo[d] ? weighted(b, dd, src, btab, A.n_ov, qm[0], qm[1], qm[2])
-                                                    : make_double2(0, 0);
+                        double2 wp = p[d] < s.hi[d] ? wsum(qp[0], qp[1], qp[2]) : make_double2(0, 0);
+                        double2 wm = p[d] > s.lo[d] ? wsum(qm[0], qm[1], qm[2]) : make_double2(0, 0);
                         Lw = cadd(Lw, csub(cmul(cf[d].cp, csub(wp, w0)), cmul(cf[d].cm, csub(w0, wm))));
                     }
-                    acc = csub(acc, Lw);
+                    // plain: acc += Psi = -L(beta v); corrected: acc -= Psi
+                    acc = corrected ? cadd(acc, Lw) : csub(acc, Lw);
                 }
     }
     g[rhs * A.etot + s.off + e] = from_d2<TOUT>(acc);
@@ -378,7 +401,8 @@ hipError_t launch_restrict(ddm_handle *h, const TIN *f, TOUT *g, int nrhs) {
 }
 
 template <typename TIN, typename TOUT>
-hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TIN *l3, TOUT *g, int nrhs) {
+hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TIN *l3, TOUT *g, int nrhs,
+                           const double2 *rcorr) {
     const Plan &P = h->plan;
     dim3 grid((unsigned)((max_box(P) + kBlock - 1) / kBlock), P.nsub, nrhs);
     // packed g written; neighbour strips (n_ov + 1 layers) read
@@ -387,7 +411,7 @@ hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TI
         for (int d = 0; d < P.dim; ++d) strip += 2.0 * (P.n_ov + 1) * (double)sd.nloc / sd.n[d];
     ProfScope ps(h, DDM_K_TRANSFER, (double)nrhs * ((double)P.etot * sizeof(TOUT) + strip * sizeof(TIN)));
     k_transfer<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g,
-                                                          pack_args(P));
+                                                          pack_args(P), rcorr);
     return hipGetLastError();
 }
 
@@ -406,9 +430,9 @@ hipError_t launch_assemble(ddm_handle *h, const TIN *U, double2 *u, int nrhs, bo
 template hipError_t launch_restrict<double2, double2>(ddm_handle *, const double2 *, double2 *, int);
 template hipError_t launch_restrict<double2, float2>(ddm_handle *, const double2 *, float2 *, int);
 template hipError_t launch_transfer<double2, double2>(ddm_handle *, const double2 *, const double2 *,
-                                                      const double2 *, double2 *, int);
+                                                      const double2 *, double2 *, int, const double2 *);
 template hipError_t launch_transfer<float2, float2>(ddm_handle *, const float2 *, const float2 *, const float2 *,
-                                                    float2 *, int);
+                                                    float2 *, int, const double2 *);
 template hipError_t launch_assemble<double2>(ddm_handle *, const double2 *, double2 *, int, bool, const int *);
 template hipError_t launch_assemble<float2>(ddm_handle *, const float2 *, double2 *, int, bool, const int *);
 

@@ -246,3 +246,46 @@ def test_autotune_picks_an_applicable_variant(pair):
         assert times[g.solve_variant()] == min(t for t in times.values() if t is not None)
     finally:
         g.set_factor_layout(True)
+
+
+def test_mixed_stationary_residual_corrected_converges():
+    """Mixed path (complex64 local solves and transfers, FP64 residual):
+    with residual-corrected sources it reaches a tight FP64 tolerance, and the
+    result matches the oracle's global direct solve."""
+    w = CASES["2d-3x3-layered"]()
+    o, g = make_pair(w, nrhs_max=w.nrhs, mixed=True)
+    f = _t(w.f.reshape(w.nrhs, -1))
+    u, info, st = g.solve(f, method="stationary", tol=1e-9, maxiter=400)
+    assert st == 0, info
+    uref = o.global_solve(w.f).reshape(w.nrhs, -1)
+    assert relerr(_n(u), uref, axis=1) < 1e-7
+    # FP64 path on the same problem for the step count comparison
+    o2, g64 = make_pair(w, nrhs_max=w.nrhs)
+    _, info64, _ = g64.solve(f, method="stationary", tol=1e-9, maxiter=400)
+    assert max(i["iters"] for i in info) <= max(i["iters"] for i in info64) + 3
+    g.close()
+    g64.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fgmres_matches_global_solve(mixed):
+    w = CASES["2d-3x3-layered"]()
+    o, g = make_pair(w, nrhs_max=w.nrhs, mixed=mixed)
+    f = _t(w.f.reshape(w.nrhs, -1))
+    u, info, st = g.solve(f, method="fgmres", tol=1e-10, maxiter=100, restart=30)
+    assert st == 0, info
+    uref = o.global_solve(w.f).reshape(w.nrhs, -1)
+    assert relerr(_n(u), uref, axis=1) < 1e-8
+    assert all(i["local_solves"] == i["iters"] * sum(w.N) for i in info)
+    g.close()
+
+
+def test_stationary_fp64_matches_global_solve():
+    w = CASES["2d-2x2-const"]()
+    o, g = make_pair(w, nrhs_max=w.nrhs)
+    f = _t(w.f.reshape(w.nrhs, -1))
+    u, info, st = g.solve(f, method="stationary", tol=1e-12, maxiter=200)
+    assert st == 0
+    uref = o.global_solve(w.f).reshape(w.nrhs, -1)
+    assert relerr(_n(u), uref, axis=1) < 1e-10
+    g.close()
