@@ -478,6 +478,8 @@ int ddm_set_solve_variant(ddm_handle *h, int variant) {
 
 int ddm_set_factor_layout(ddm_handle *h, int twisted) {
     if (!h) return DDM_EINVAL;
+    if (twisted && !solve_variant_ok(h->plan, kSolveChain))
+        return fail(h, DDM_EINVAL, "the twisted layout needs the chain substitution (block size <= 256)");
     (void)hipStreamSynchronize(h->stream);
     plan_set_twist(&h->plan, twisted != 0);
     if (hipMemcpy(h->d_subs, h->plan.subs.data(), h->plan.subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice) !=

@@ -196,8 +196,9 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
             P.v_el_by_l[l] += (double)s.bs;
         }
     // two chains per subdomain (both-ends elimination) while they all fit on
-    // the chip's 256 compute units, one otherwise
-    plan_set_twist(&P, P.nsub <= 128 && P.nb_max >= 4);
+    // the chip's 256 compute units and the chain kernel applies (block size
+    // <= 256), one otherwise
+    plan_set_twist(&P, P.nsub <= 128 && P.nb_max >= 4 && P.bs_max <= 256);
     P.btab.resize(p->n_ov + 1);
     for (int m = 0; m <= p->n_ov; ++m)
         P.btab[m] = m <= 1 ? 1.0 : (m >= p->n_ov ? 0.0 : beta0((double)(m - 1) / (double)(p->n_ov - 1)));

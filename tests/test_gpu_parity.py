@@ -54,6 +54,9 @@ CASES = {
     "2d-2x2-const": lambda: di.small_2d(M=160, N=(2, 2), n_pml=8, n_ov=4, nrhs=3),
     "2d-3x2-layered": lambda: di.small_2d(M=144, N=(3, 2), n_pml=6, n_ov=3, nrhs=1, layered=True, seed=3),
     "2d-3x3-layered": lambda: di.small_2d(M=192, N=(3, 3), n_pml=7, n_ov=5, nrhs=5, layered=True, seed=4),
+    # 3D: plane blocks of 100-196 unknowns, 26 transfer directions, lags 1-3
+    "3d-2x2x2": lambda: di.small_3d(M=16, N=(2, 2, 2), n_pml=3, n_ov=2, nrhs=2, seed=1),
+    "3d-3x2x2": lambda: di.small_3d(M=12, N=(3, 2, 2), n_pml=3, n_ov=2, nrhs=3, seed=2),
 }
 
 
@@ -126,7 +129,7 @@ def test_local_solve_fp64(pair, nrhs):
 
 def test_iterate_fp64_matches_oracle_every_step(pair):
     w, o, g = pair
-    nsteps = 2 * sum(w.N) + 2
+    nsteps = 2 * sum(w.N) + 2 if w.dim == 2 else sum(w.N) + 3
     uo, rro = o.ddm_run(w.f, nsteps)
     ug, rrg = g.iterate(_t(w.f.reshape(w.nrhs, -1)), nsteps)
     assert relerr(_n(ug), uo, axis=1) < 1e-10
@@ -288,4 +291,18 @@ def test_stationary_fp64_matches_global_solve():
     assert st == 0
     uref = o.global_solve(w.f).reshape(w.nrhs, -1)
     assert relerr(_n(u), uref, axis=1) < 1e-10
+    g.close()
+
+
+def test_3d_large_planes_perline():
+    """3D plane blocks of 289 unknowns (> 256): one-directional layout and the
+    one-launch-per-block substitution; local solves and iterates vs oracle."""
+    w = di.small_3d(M=22, N=(2, 2, 2), n_pml=3, n_ov=2, nrhs=2, seed=3)
+    o, g = make_pair(w, nrhs_max=2)
+    assert g.solve_variant() == "perline"
+    gin = di.random_field((2, o.etot), seed=80)
+    assert relerr(_n(g.local_solve(_t(gin))), o.local_solve(gin), axis=1) < 1e-10
+    uo, _ = o.ddm_run(w.f, 4)
+    ug, _ = g.iterate(_t(w.f.reshape(2, -1)), 4)
+    assert relerr(_n(ug), uo, axis=1) < 1e-10
     g.close()
