@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FGMRES and mixed-precision legs")
+    ap.add_argument("--probe", choices=["none", "traffic"], default="none",
+                    help="traffic: run 3 FP64 local solves of the workload and a 1 GiB device copy "
+                         "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the DDM step has no multi-GPU path here); "
@@ -119,8 +122,20 @@ def main():
     s64.factor()
     torch.cuda.synchronize()
     t_factor = time.perf_counter() - t0
-    log("bench: setup %.3f s, factor %.3f s (%.2f GB of complex128 block inverses)"
-        % (t_setup, t_factor, s64.factor_bytes / 1e9))
+    log("bench: setup %.3f s, factor %.3f s (%.2f GB of complex128 block inverses), substitution variant %s"
+        % (t_setup, t_factor, s64.factor_bytes / 1e9, s64.solve_variant()))
+
+    if args.probe == "traffic":
+        g = torch.zeros((nrhs, s64.etot), dtype=torch.complex128, device=dev)
+        g[:, ::7] = 1.0
+        for _ in range(3):
+            s64.local_solve(g)
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: traffic probe done (3 local solves, 1 GiB copy)")
+        return
 
     def solve_fp64(u=None):
         return s64.solve(f, method="stationary", tol=args.tol, maxiter=400, u=u)
@@ -182,7 +197,8 @@ def main():
     achieved = sub["bytes"] / (sub["ms"] * 1e-3) / 1e9 if sub["ms"] > 0 else 0.0
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                       "kernel": "k_solve_line (block substitution)",
+                       "kernel": ("k_solve_chain" if s64.solve_variant() == "chain" else "k_solve_line")
+                                 + " (block substitution)",
                        "avg_launch_us": avg_us, "launches": sub["launches"],
                        "bytes_per_launch": sub["bytes"] / max(sub["launches"], 1)}
     out["kernel_time_ms_per_solve_batch"] = {k: v["ms"] for k, v in prof.items()}
