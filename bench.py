@@ -46,6 +46,22 @@ def pct(v, p):
     return float(np.percentile(np.asarray(v, dtype=float), p)) if len(v) else None
 
 
+def recorded_traffic(kernel_variant):
+    """HBM traffic per launch of the substitution kernel from the committed
+    rocprofv3 counter summary, only if the kernel source is unchanged since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_solve_chain_cfg2_traffic.json")
+    src = os.path.join(ROOT, "paper_1807_04180_amd", "csrc", "ddm_solve.hip")
+    if kernel_variant != "chain" or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    with open(src, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != rec.get("source_sha256"):
+            return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def run_cpu_baseline(nrhs_full, nsub_full, steps_full, tol):
     """Oracle on a 4x4 cut of the workload; per-step time scaled by subdomain
     count (the oracle's work per step is linear in it) and by the full
@@ -196,7 +212,7 @@ def main():
     avg_us = sub["ms"] / max(sub["launches"], 1) * 1e3
     achieved = sub["bytes"] / (sub["ms"] * 1e-3) / 1e9 if sub["ms"] > 0 else 0.0
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(s64.solve_variant()),
                        "kernel": ("k_solve_chain" if s64.solve_variant() == "chain" else "k_solve_line")
                                  + " (block substitution)",
                        "avg_launch_us": avg_us, "launches": sub["launches"],
