@@ -68,29 +68,29 @@ __device__ inline double2 apply_global_at(const double2 *__restrict__ u, const d
     return Lu;
 }
 
-// mode 0: out = f - L u and partial norms of out and f; mode 1: out = L u
+// mode 0: out = f - L u and partial norms of out and f; mode 1: out = L u.
+// One block per grid row (fixed y, z) and RHS; threads along x.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil(const double2 *__restrict__ f, const double2 *__restrict__ u,
                                                     double2 *__restrict__ out, const double *__restrict__ k2,
                                                     const Coef *__restrict__ gc, GridArgs g,
                                                     double *__restrict__ part_r, double *__restrict__ part_f) {
     __shared__ double sh[kBlock / 64];
-    int rhs = blockIdx.y;
-    long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const int rhs = blockIdx.y;
+    const int rowi = blockIdx.x;  // y + G1 * z
+    const int y = rowi % g.G1, z = rowi / g.G1;
+    const long long row0 = (long long)rowi * g.G0;
     const double2 *ur = u + rhs * g.nglob;
     double rn = 0.0, fn = 0.0;
-    if (idx < g.nglob) {
-        int x = (int)(idx % g.G0);
-        long long t = idx / g.G0;
-        int y = (int)(t % g.G1);
-        int z = (int)(t / g.G1);
+    for (int x = threadIdx.x; x < g.G0; x += kBlock) {
+        const long long idx = row0 + x;
         double2 Lu = apply_global_at(ur, k2, gc, g, idx, x, y, z);
         if (MODE == 0) {
             double2 fv = f[rhs * g.nglob + idx];
             double2 rv = csub(fv, Lu);
             if (out) out[rhs * g.nglob + idx] = rv;
-            rn = cabs2(rv);
-            fn = cabs2(fv);
+            rn += cabs2(rv);
+            fn += cabs2(fv);
         } else {
             out[rhs * g.nglob + idx] = Lu;
         }
@@ -136,7 +136,7 @@ static GridArgs grid_args(const Plan &P) {
 
 hipError_t launch_apply(ddm_handle *h, const double2 *u, double2 *out, int nrhs) {
     const Plan &P = h->plan;
-    dim3 grid((unsigned)((P.nglob + kBlock - 1) / kBlock), nrhs);
+    dim3 grid((unsigned)(P.G[1] * P.G[2]), nrhs);
     k_stencil<1><<<grid, kBlock, 0, h->stream>>>(nullptr, u, out, h->d_k2, h->d_gcoef, grid_args(P), nullptr, nullptr);
     return hipGetLastError();
 }
@@ -144,7 +144,7 @@ hipError_t launch_apply(ddm_handle *h, const double2 *u, double2 *out, int nrhs)
 hipError_t launch_residual(ddm_handle *h, const double2 *f, const double2 *u, double2 *r, int nrhs, double *d_rn2,
                            double *d_fn2) {
     const Plan &P = h->plan;
-    int nblk = (int)((P.nglob + kBlock - 1) / kBlock);
+    int nblk = P.G[1] * P.G[2];
     dim3 grid(nblk, nrhs);
     double *part_r = h->d_part, *part_f = h->d_part + (long long)nrhs * nblk;
     // f and u read, r written (if requested), k^2 read
@@ -189,20 +189,20 @@ __device__ inline long long glob_index(const PackArgs &A, int px, int py, int pz
 template <typename TIN, typename TOUT>
 __global__ __launch_bounds__(kBlock) void k_restrict(const SubDesc *__restrict__ subs, const TIN *__restrict__ f,
                                                      TOUT *__restrict__ g, PackArgs A) {
-    int a = blockIdx.y, rhs = blockIdx.z;
+    const int a = blockIdx.y, rhs = blockIdx.z;
     const SubDesc &s = subs[a];
-    long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= s.nloc) return;
-    int x = (int)(e % s.n[0]);
-    long long t = e / s.n[0];
-    int y = (int)(t % s.n[1]);
-    int z = (int)(t / s.n[1]);
-    int p0 = s.lo[0] + x, p1 = s.lo[1] + y, p2 = s.lo[2] + z;
-    bool core = p0 >= s.clo[0] && p0 <= s.chi[0] && p1 >= s.clo[1] && p1 <= s.chi[1] && p2 >= s.clo[2] &&
-                p2 <= s.chi[2];
-    double2 v = make_double2(0, 0);
-    if (core) v = to_d2(f[rhs * A.nglob + glob_index(A, p0, p1, p2)]);
-    g[rhs * A.etot + s.off + e] = from_d2<TOUT>(v);
+    const int rowi = blockIdx.x;  // ly + n1 * lz
+    if (rowi >= s.n[1] * s.n[2]) return;
+    const int ly = rowi % s.n[1], lz = rowi / s.n[1];
+    const int p1 = s.lo[1] + ly, p2 = s.lo[2] + lz;
+    const bool rowcore = p1 >= s.clo[1] && p1 <= s.chi[1] && p2 >= s.clo[2] && p2 <= s.chi[2];
+    TOUT *gr = g + rhs * A.etot + s.off + (long long)rowi * s.n[0];
+    for (int lx = threadIdx.x; lx < s.n[0]; lx += kBlock) {
+        const int p0 = s.lo[0] + lx;
+        double2 v = make_double2(0, 0);
+        if (rowcore && p0 >= s.clo[0] && p0 <= s.chi[0]) v = to_d2(f[rhs * A.nglob + glob_index(A, p0, p1, p2)]);
+        gr[lx] = from_d2<TOUT>(v);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -241,14 +241,13 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
                                                      const TIN *__restrict__ l1, const TIN *__restrict__ l2,
                                                      const TIN *__restrict__ l3, TOUT *__restrict__ g, PackArgs A,
                                                      const double2 *__restrict__ rcorr) {
-    int a = blockIdx.y, rhs = blockIdx.z;
+    const int a = blockIdx.y, rhs = blockIdx.z;
     const SubDesc &s = subs[a];
-    long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= s.nloc) return;
-    int lx = (int)(e % s.n[0]);
-    long long t = e / s.n[0];
-    int ly = (int)(t % s.n[1]);
-    int lz = (int)(t / s.n[1]);
+    const int rowi = blockIdx.x;  // ly + n1 * lz
+    if (rowi >= s.n[1] * s.n[2]) return;
+    const int ly = rowi % s.n[1], lz = rowi / s.n[1];
+    for (int lx = threadIdx.x; lx < s.n[0]; lx += kBlock) {
+    const long long e = (long long)rowi * s.n[0] + lx;
     int p[3] = {s.lo[0] + lx, s.lo[1] + ly, s.lo[2] + lz};
     int l[3] = {lx, ly, lz};
     double2 acc = make_double2(0, 0);
@@ -323,6 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
                 }
     }
     g[rhs * A.etot + s.off + e] = from_d2<TOUT>(acc);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -335,14 +335,12 @@ __global__ __launch_bounds__(kBlock) void k_assemble(const SubDesc *__restrict__
                                                      const double *__restrict__ btab, const TIN *__restrict__ U,
                                                      double2 *__restrict__ u, PackArgs A, int accumulate,
                                                      const int *__restrict__ active) {
-    int rhs = blockIdx.y;
+    const int rhs = blockIdx.y;
     if (active && !active[rhs]) return;
-    long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= A.nglob) return;
-    int gx = (int)(idx % A.G0);
-    long long t = idx / A.G0;
-    int gy = (int)(t % A.G1);
-    int gz = (int)(t / A.G1);
+    const int rowi = blockIdx.x;  // gy + G1 * gz
+    const int gy = rowi % A.G1, gz = rowi / A.G1;
+    for (int gx = threadIdx.x; gx < A.G0; gx += kBlock) {
+    const long long idx = (long long)rowi * A.G0 + gx;
     int p[3] = {gx + A.glo0, gy + A.glo1, gz + A.glo2};
     int own[3] = {owner[o0 + gx], owner[o1 + gy], owner[o2 + gz]};
     int Nn[3] = {N0, N1, N2};
@@ -375,6 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(const SubDesc *__restrict__
     }
     double2 *ur = u + rhs * A.nglob + idx;
     *ur = accumulate ? cadd(*ur, acc) : acc;
+    }
 }
 
 static PackArgs pack_args(const Plan &P) {
@@ -386,16 +385,16 @@ static PackArgs pack_args(const Plan &P) {
     return A;
 }
 
-static long long max_box(const Plan &P) {
-    long long m = 0;
-    for (const SubDesc &s : P.subs) m = s.nloc > m ? s.nloc : m;
+static int max_rows(const Plan &P) {  // grid rows (n1 * n2) of the largest box
+    int m = 0;
+    for (const SubDesc &s : P.subs) m = s.n[1] * s.n[2] > m ? s.n[1] * s.n[2] : m;
     return m;
 }
 
 template <typename TIN, typename TOUT>
 hipError_t launch_restrict(ddm_handle *h, const TIN *f, TOUT *g, int nrhs) {
     const Plan &P = h->plan;
-    dim3 grid((unsigned)((max_box(P) + kBlock - 1) / kBlock), P.nsub, nrhs);
+    dim3 grid((unsigned)max_rows(P), P.nsub, nrhs);
     k_restrict<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, f, g, pack_args(P));
     return hipGetLastError();
 }
@@ -404,7 +403,7 @@ template <typename TIN, typename TOUT>
 hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TIN *l3, TOUT *g, int nrhs,
                            const double2 *rcorr) {
     const Plan &P = h->plan;
-    dim3 grid((unsigned)((max_box(P) + kBlock - 1) / kBlock), P.nsub, nrhs);
+    dim3 grid((unsigned)max_rows(P), P.nsub, nrhs);
     // packed g written; neighbour strips (n_ov + 1 layers) read
     double strip = 0.0;
     for (const SubDesc &sd : P.subs)
@@ -418,7 +417,7 @@ hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TI
 template <typename TIN>
 hipError_t launch_assemble(ddm_handle *h, const TIN *U, double2 *u, int nrhs, bool accumulate, const int *d_active) {
     const Plan &P = h->plan;
-    dim3 grid((unsigned)((P.nglob + kBlock - 1) / kBlock), nrhs);
+    dim3 grid((unsigned)(P.G[1] * P.G[2]), nrhs);
     // local solutions read once per global node, u read (if accumulating) and written
     ProfScope ps(h, DDM_K_ASSEMBLE, (double)P.nglob * nrhs * (sizeof(TIN) + (accumulate ? 32.0 : 16.0)));
     k_assemble<TIN><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_owner, P.ooff[0], P.ooff[1], P.ooff[2], P.N[0],

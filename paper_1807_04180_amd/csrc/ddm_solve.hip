@@ -245,6 +245,22 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
                 }
                 __syncthreads();
             }
+            // ---- prefetch the block-vector entries the reduction will need
+            // (forward: g of the next block; backward: this block's y) ----
+            constexpr int kPre = 2;  // bsp * RT <= 2 * kCThreads
+            const int tn = t + 1;
+            const int lnv = tn < nsteps && tn != nf ? step_l(tn) : -1;
+            T2 pre[kPre];
+#pragma unroll
+            for (int u = 0; u < kPre; ++u) {
+                const int e = threadIdx.x + u * kCThreads;
+                const int i = e / RT, q = e % RT;
+                const bool ok = e < bsp * RT && i < bs && q < nr;
+                const long long base = (long long)(ok ? r0 + q : 0) * etot + off;
+                if (kind == 2) pre[u] = ok ? x[base + (long long)l * bs + i] : czero<T2>();
+                else if (kind == 0 && lnv >= 0) pre[u] = ok ? g[base + (long long)lnv * bs + i] : czero<T2>();
+                else pre[u] = czero<T2>();
+            }
             // ---- GEMV: acc = W_l v ----
             T2 acc[RT];
 #pragma unroll
@@ -279,9 +295,10 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
             }
             __syncthreads();
             // ---- reduce over column groups; update x; build the next v ----
-            // next-step coefficient and neighbour for v
-            const int tn = t + 1;
-            for (int e = threadIdx.x; e < bsp * RT; e += kCThreads) {
+#pragma unroll
+            for (int u = 0; u < kPre; ++u) {
+                const int e = threadIdx.x + u * kCThreads;
+                if (e >= bsp * RT) continue;
                 const int i = e / RT, q = e % RT;
                 if (i >= bs) continue;
                 T2 sum = red[(size_t)q * bsp + i];
@@ -292,23 +309,19 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
                 }
                 const long long base = (long long)(r0 + q) * etot + off;
                 T2 res = sum;                       // forward: y_l, middle: x_mid
-                if (kind == 2 && q < nr) {          // backward: x_l = y_l - W_l v
-                    T2 y = x[base + (long long)l * bs + i];
-                    res.x = y.x - sum.x;
-                    res.y = y.y - sum.y;
+                if (kind == 2) {                    // backward: x_l = y_l - W_l v
+                    res.x = pre[u].x - sum.x;
+                    res.y = pre[u].y - sum.y;
                 }
                 if (q < nr && (kind != 1 || chain == 0)) x[base + (long long)l * bs + i] = res;
-                if (tn < nsteps && tn != nf) {
+                if (lnv >= 0) {
                     // next v from this block's result
                     double2 v;
-                    const int ln = step_l(tn);
+                    const Coef cn = coef[s.coff[ax] + lnv];
                     if (kind == 0) {                // forward: g_ln - c * y_l
-                        const Coef cn = coef[s.coff[ax] + ln];
                         const double2 c = chain == 0 ? cn.cm : cn.cp;
-                        v = q < nr ? cmsub_fixed(to_d2(g[base + (long long)ln * bs + i]), c, to_d2(res))
-                                   : make_double2(0, 0);
+                        v = q < nr ? cmsub_fixed(to_d2(pre[u]), c, to_d2(res)) : make_double2(0, 0);
                     } else {                        // after middle / backward: c * x_l
-                        const Coef cn = coef[s.coff[ax] + ln];
                         const double2 c = chain == 0 ? cn.cp : cn.cm;
                         v = q < nr ? cmul_fixed(c, to_d2(res)) : make_double2(0, 0);
                     }
