@@ -228,6 +228,16 @@ int ddm_get_solve_variant(const ddm_handle *h);
  * -1 for variants that do not apply or could not be launched. */
 int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms);
 
+/* Replay the steady-state step of the stationary solve (transfer, local
+ * solves, accumulation, residual and norms) as a captured hipGraph, one per
+ * generation of the ring of local solutions (default on).  The handle then
+ * iterates on its own copies of f and u.  Capture falls back to plain
+ * launches where it is unavailable. */
+int ddm_set_graphs(ddm_handle *h, int on);
+
+/* Number of step-graph launches since setup (observability). */
+long ddm_graph_launches(const ddm_handle *h);
+
 /* Bound on the spin iterations of the wait of one chain for its partner at
  * the middle block (default 2^22).  When a wait exceeds it the launch drains
  * without waiting and the call reports DDM_EHIP.  Exposed so that this

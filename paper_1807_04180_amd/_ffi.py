@@ -75,6 +75,9 @@ def lib():
     L.ddm_local_solve.argtypes = [H, P, P, I]
     L.ddm_transfer.argtypes = [H, P, P, P, P, I]
     L.ddm_assemble.argtypes = [H, P, P, I]
+    L.ddm_set_graphs.argtypes = [H, I]
+    L.ddm_graph_launches.argtypes = [H]
+    L.ddm_graph_launches.restype = ctypes.c_long
     L.ddm_set_factor_layout.argtypes = [H, I]
     L.ddm_set_solve_variant.argtypes = [H, I]
     L.ddm_get_solve_variant.argtypes = [H]
@@ -82,7 +85,7 @@ def lib():
     L.ddm_set_spin_limit.argtypes = [H, I]
     L.ddm_profile_enable.argtypes = [H, I]
     L.ddm_profile_read.argtypes = [H, ctypes.POINTER(DdmProfile)]
-    for name in ("ddm_set_factor_layout", "ddm_set_solve_variant", "ddm_get_solve_variant", "ddm_autotune", "ddm_set_spin_limit",
+    for name in ("ddm_set_graphs", "ddm_set_factor_layout", "ddm_set_solve_variant", "ddm_get_solve_variant", "ddm_autotune", "ddm_set_spin_limit",
                  "ddm_profile_enable", "ddm_profile_read", "ddm_memory_required", "ddm_setup", "ddm_factor", "ddm_iterate", "ddm_solve", "ddm_sizes",
                  "ddm_geometry", "ddm_apply", "ddm_residual", "ddm_restrict_core", "ddm_local_solve",
                  "ddm_transfer", "ddm_assemble"):

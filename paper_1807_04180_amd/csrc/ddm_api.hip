@@ -120,6 +120,11 @@ void free_all(ddm_handle *h) {
                     h->d_coef_y, h->d_sync};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (int k = 0; k < 4; ++k)
+        if (h->step_graph[k]) (void)hipGraphExecDestroy(h->step_graph[k]);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->d_fin) (void)hipFree(h->d_fin);
+    if (h->d_uin) (void)hipFree(h->d_uin);
     for (auto &r : h->prof_recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
@@ -136,23 +141,85 @@ const T *ring_at(ddm_handle *h, int s) {  // uhat^s (s >= 1) or null for s <= 0
 // given it is called after each step with the per-RHS relative residuals and
 // may deactivate RHS (their u is frozen) or request a restart of the
 // recursion on a new source (refinement); it returns false to stop.
-// rcorr: residual-corrected sources (the check must leave r = f - L_h u of
-// the current iterate there after every step)
+// One step of Algorithm 3.1 after the first ring generations: transfer,
+// local solves, accumulation and (optionally) the residual with its norms
+// into d_norm (rcorr: residual-corrected sources, the residual is kept there).
+template <typename T>
+void enqueue_step(ddm_handle *h, const double2 *f, double2 *u, int nrhs, int s, const double2 *src, bool restrict_src,
+                  const double2 *rcorr, bool with_residual) {
+    const Plan &P = h->plan;
+    T *g = (T *)h->d_g;
+    if (restrict_src) HIPCHK((launch_restrict<double2, T>(h, src, g, nrhs)));
+    else HIPCHK((launch_transfer<T, T>(h, ring_at<T>(h, s - 1), ring_at<T>(h, s - 2), ring_at<T>(h, s - 3), g, nrhs,
+                                       rcorr)));
+    T *us = (T *)h->d_ring[s % P.ring];
+    HIPCHK(launch_local_solve<T>(h, g, us, nrhs));
+    HIPCHK(launch_assemble<T>(h, us, u, nrhs, true, h->d_active));
+    if (with_residual)
+        HIPCHK(launch_residual(h, f, u, const_cast<double2 *>(rcorr), nrhs, h->d_norm, h->d_norm + nrhs));
+}
+
+// Capture the steady-state step of ring phase s % ring as a graph on the
+// library's capture stream (every buffer it touches is fixed for that phase).
+// Returns false if capture is not possible here (the caller runs eagerly).
+template <typename T>
+bool step_graph(ddm_handle *h, const double2 *f, double2 *u, int nrhs, int s, const double2 *rcorr) {
+    const int phase = s % h->plan.ring;
+    if (h->step_graph[phase] && h->step_graph_nrhs[phase] == nrhs) return true;
+    if (h->step_graph[phase]) {
+        (void)hipGraphExecDestroy(h->step_graph[phase]);
+        h->step_graph[phase] = nullptr;
+    }
+    if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) return false;
+    hipStream_t keep = h->stream;
+    h->stream = h->cap_stream;
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        try {
+            enqueue_step<T>(h, f, u, nrhs, s, nullptr, false, rcorr, true);
+        } catch (const HipFail &) {
+            ok = false;
+        }
+        hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+        ok = ok && e == hipSuccess && graph;
+    }
+    h->stream = keep;
+    if (ok) ok = hipGraphInstantiate(&h->step_graph[phase], graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!ok) {
+        h->step_graph[phase] = nullptr;
+        h->use_graphs = false;  // capture unsupported here: stay eager
+        return false;
+    }
+    h->step_graph_nrhs[phase] = nrhs;
+    return true;
+}
+
+// Run nsteps steps of Algorithm 3.1 with source f (global, complex128) and
+// accumulate u += sum_a beta_{0;a} uhat^s_a after every step, followed by the
+// residual norms of f - L_h u in d_norm.  check(it, &restart) is then called
+// (norms already computed, not yet copied) and may deactivate RHS (their u is
+// frozen), request a restart of the recursion on a new source (refinement),
+// or return false to stop.  rcorr: residual-corrected sources (the residual
+// is written there every step).  graphs: steady-state steps replay a
+// captured hipGraph (f and u must then be buffers that stay fixed).
 template <typename T, typename Check>
 void run_steps(ddm_handle *h, const double2 *f, double2 *u, int nrhs, int nsteps, Check check,
-               const double2 *rcorr = nullptr) {
+               const double2 *rcorr = nullptr, bool graphs = false) {
     const Plan &P = h->plan;
     const double2 *src = f;
     int s = 0;
     for (int it = 1; it <= nsteps; ++it) {
         ++s;
-        T *g = (T *)h->d_g;
-        if (s == 1) HIPCHK((launch_restrict<double2, T>(h, src, g, nrhs)));
-        else HIPCHK((launch_transfer<T, T>(h, ring_at<T>(h, s - 1), ring_at<T>(h, s - 2), ring_at<T>(h, s - 3), g, nrhs,
-                                           rcorr)));
-        T *us = (T *)h->d_ring[s % P.ring];
-        HIPCHK(launch_local_solve<T>(h, g, us, nrhs));
-        HIPCHK(launch_assemble<T>(h, us, u, nrhs, true, h->d_active));
+        bool done = false;
+        if (graphs && h->use_graphs && !h->prof_on && s > P.ring && step_graph<T>(h, f, u, nrhs, s, rcorr)) {
+            HIPCHK(hipGraphLaunch(h->step_graph[s % P.ring], h->stream));
+            ++h->graph_launches;
+            done = true;
+        }
+        if (!done) enqueue_step<T>(h, f, u, nrhs, s, src, s == 1, rcorr, true);
         const double2 *restart_src = nullptr;
         if (!check(it, &restart_src)) break;
         if (restart_src) {
@@ -162,8 +229,27 @@ void run_steps(ddm_handle *h, const double2 *f, double2 *u, int nrhs, int nsteps
     }
 }
 
+// step loop without residuals (the FGMRES preconditioner M_K)
+template <typename T>
+void run_steps_plain(ddm_handle *h, const double2 *f, double2 *u, int nrhs, int nsteps) {
+    for (int s = 1; s <= nsteps; ++s) enqueue_step<T>(h, f, u, nrhs, s, f, s == 1, nullptr, false);
+}
+
 void set_active(ddm_handle *h, const std::vector<int> &act) {
     HIPCHK(hipMemcpyAsync(h->d_active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+}
+
+// fetch the norms a step left in d_norm: relres per RHS
+void fetch_norms(ddm_handle *h, int nrhs, std::vector<double> &rel, std::vector<double> *fn = nullptr) {
+    HIPCHK(hipMemcpyAsync(h->h_norm, h->d_norm, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    rel.resize(nrhs);
+    if (fn) fn->resize(nrhs);
+    for (int q = 0; q < nrhs; ++q) {
+        double rn = std::sqrt(h->h_norm[q]), fnq = std::sqrt(h->h_norm[nrhs + q]);
+        rel[q] = fnq > 0 ? rn / fnq : rn;
+        if (fn) (*fn)[q] = fnq;
+    }
 }
 
 // relres per RHS of u for source f; fills h->h_norm[0..2 nrhs)
@@ -217,7 +303,20 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
                      ddm_rhs_info *info) {
     const Plan &P = h->plan;
     double t0 = now_s();
-    HIPCHK(launch_fill_zero(u, (long long)nrhs * P.nglob * sizeof(double2), h->stream));
+    // graph path: iterate on handle-owned copies of f and u so that captured
+    // steps stay valid across calls
+    const bool graphs = h->use_graphs && !h->prof_on;
+    const double2 *fout = f;
+    double2 *uout = u;
+    const size_t vbytes = (size_t)nrhs * P.nglob * sizeof(double2);
+    if (graphs) {
+        if (!h->d_fin) HIPCHK(hipMalloc((void **)&h->d_fin, (size_t)h->nrhs_max * P.nglob * sizeof(double2)));
+        if (!h->d_uin) HIPCHK(hipMalloc((void **)&h->d_uin, (size_t)h->nrhs_max * P.nglob * sizeof(double2)));
+        HIPCHK(hipMemcpyAsync(h->d_fin, f, vbytes, hipMemcpyDeviceToDevice, h->stream));
+        f = h->d_fin;
+        u = h->d_uin;
+    }
+    HIPCHK(launch_fill_zero(u, (long long)vbytes, h->stream));
     std::vector<int> act(nrhs, 1);
     set_active(h, act);
     std::vector<double> rel, fn, best(nrhs, 1e300), last_gain_rel(nrhs, 1.0);
@@ -227,7 +326,7 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
     int refine_every = o.refine_every > 0 ? o.refine_every : nsum;
     double2 *rsrc = h->d_r;  // residual (corrected sources) / restart source
     auto check = [&](int it, const double2 **restart) -> bool {
-        residual_host(h, f, u, h->mixed ? rsrc : nullptr, nrhs, rel, &fn);
+        fetch_norms(h, nrhs, rel, &fn);
         bool all = true, changed = false;
         bool stalled = false;
         for (int q = 0; q < nrhs; ++q) {
@@ -256,7 +355,9 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
         }
         return true;
     };
-    run_steps<T>(h, f, u, nrhs, o.maxiter, check, h->mixed ? rsrc : nullptr);
+    run_steps<T>(h, f, u, nrhs, o.maxiter, check, h->mixed ? rsrc : nullptr, graphs);
+    if (graphs) HIPCHK(hipMemcpyAsync(uout, u, vbytes, hipMemcpyDeviceToDevice, h->stream));
+    (void)fout;
     HIPCHK(hipStreamSynchronize(h->stream));
     int worst = DDM_OK;
     double t1 = now_s();
@@ -357,7 +458,7 @@ int solve_fgmres(ddm_handle *h, const double2 *f, double2 *x, int nrhs, const dd
             // z_j = M_K(v_j): K DDM steps from a zero state, output sum beta0 U
             set_active(h, ones);
             HIPCHK(launch_fill_zero(zj, vstride * (long long)sizeof(double2), h->stream));
-            run_steps<T>(h, vj, zj, nrhs, K, [](int, const double2 **) { return true; });
+            run_steps_plain<T>(h, vj, zj, nrhs, K);
             HIPCHK(launch_apply(h, zj, w, nrhs));
             double2 *h1 = h->d_dots, *h2 = h->d_dots + (size_t)(m + 1) * nrhs;
             double *hn = (double *)(h->d_dots + (size_t)2 * (m + 1) * nrhs);
@@ -472,6 +573,9 @@ int ddm_set_solve_variant(ddm_handle *h, int variant) {
     if (!h) return DDM_EINVAL;
     if (variant < 0 || variant >= kSolveNVariants || !solve_variant_ok(h->plan, variant))
         return fail(h, DDM_EINVAL, "substitution variant does not apply to this problem");
+    if (variant != h->solve_variant)
+        for (int k = 0; k < 4; ++k)
+            if (h->step_graph[k]) { (void)hipGraphExecDestroy(h->step_graph[k]); h->step_graph[k] = nullptr; }
     h->solve_variant = variant;
     return DDM_OK;
 }
@@ -486,10 +590,20 @@ int ddm_set_factor_layout(ddm_handle *h, int twisted) {
         hipSuccess)
         return fail(h, DDM_EHIP, "descriptor upload failed");
     h->factored = false;
+    for (int k = 0; k < 4; ++k)
+        if (h->step_graph[k]) { (void)hipGraphExecDestroy(h->step_graph[k]); h->step_graph[k] = nullptr; }
     if (!solve_variant_ok(h->plan, h->solve_variant))
         h->solve_variant = solve_variant_ok(h->plan, kSolveChain) ? kSolveChain : kSolvePerLine;
     return DDM_OK;
 }
+
+int ddm_set_graphs(ddm_handle *h, int on) {
+    if (!h) return DDM_EINVAL;
+    h->use_graphs = on != 0;
+    return DDM_OK;
+}
+
+long ddm_graph_launches(const ddm_handle *h) { return h ? h->graph_launches : -1; }
 
 int ddm_get_solve_variant(const ddm_handle *h) { return h ? h->solve_variant : -1; }
 
@@ -791,7 +905,7 @@ int ddm_iterate(ddm_handle *h, const void *f, void *u, int nrhs, int nsteps, dou
         std::vector<double> rel;
         auto check = [&](int it, const double2 **) -> bool {
             if (relres) {
-                residual_host(h, (const double2 *)f, (const double2 *)u, nullptr, nrhs, rel);
+                fetch_norms(h, nrhs, rel);
                 for (int q = 0; q < nrhs; ++q) relres[(size_t)(it - 1) * nrhs + q] = rel[q];
             }
             return true;

@@ -115,6 +115,13 @@ struct ddm_handle {
     int solve_variant = 0;
     int *d_sync = nullptr;          // 2 nsub meeting flags + 1 abort flag
     int spin_limit = 1 << 22;
+    // hipGraph capture of the stationary DDM step (one graph per ring phase)
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t step_graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    int step_graph_nrhs[4] = {0, 0, 0, 0};
+    double2 *d_fin = nullptr, *d_uin = nullptr;  // handle-owned f and u of the graph path
+    long graph_launches = 0;
     // per-launch HIP event profiling (ddm_profile_enable)
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;

@@ -205,6 +205,12 @@ class HelmholtzDDM:
         self._check(self.lib.ddm_autotune(self._h, int(nrhs or self.nrhs_max), reps, t))
         return {name: (t[i] if t[i] >= 0 else None) for i, name in enumerate(_ffi.SOLVE_VARIANTS)}
 
+    def set_graphs(self, on: bool):
+        self._check(self.lib.ddm_set_graphs(self._h, 1 if on else 0))
+
+    def graph_launches(self) -> int:
+        return int(self.lib.ddm_graph_launches(self._h))
+
     def set_spin_limit(self, limit: int):
         self._check(self.lib.ddm_set_spin_limit(self._h, int(limit)))
 

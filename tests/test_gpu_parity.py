@@ -306,3 +306,25 @@ def test_3d_large_planes_perline():
     ug, _ = g.iterate(_t(w.f.reshape(2, -1)), 4)
     assert relerr(_n(ug), uo, axis=1) < 1e-10
     g.close()
+
+
+@pytest.mark.parametrize("case,mixed", [("2d-3x3-layered", False), ("2d-3x3-layered", True), ("3d-2x2x2", False)])
+def test_step_graph_replays_match_eager(case, mixed):
+    """The stationary solve replays captured step graphs (one per ring
+    phase) many times with host work and synchronisation in between; every
+    solve must be bitwise identical to plain launches."""
+    w = CASES[case]()
+    o, g = make_pair(w, nrhs_max=w.nrhs, mixed=mixed)
+    f = _t(w.f.reshape(w.nrhs, -1))
+    g.set_graphs(False)
+    u0, i0, _ = g.solve(f, method="stationary", tol=1e-9, maxiter=300)
+    g.set_graphs(True)
+    n0 = g.graph_launches()
+    u1, i1, _ = g.solve(f, method="stationary", tol=1e-9, maxiter=300)
+    u2, i2, _ = g.solve(f, method="stationary", tol=1e-9, maxiter=300)
+    assert g.graph_launches() > n0
+    assert torch.equal(u1, u0) and torch.equal(u2, u0)
+    assert [i["iters"] for i in i1] == [i["iters"] for i in i0] == [i["iters"] for i in i2]
+    uref = o.global_solve(w.f).reshape(w.nrhs, -1)
+    assert relerr(_n(u1), uref, axis=1) < (1e-7 if mixed else 1e-8)
+    g.close()
