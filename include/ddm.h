@@ -88,7 +88,8 @@ typedef struct {
                             N1 + N2 (+ N3)                                     */
     int refine_every;    /* DDM_MIXED stationary: restart the c64 DDM on the
                             FP64 residual after this many steps without a 2x
-                            gain (0 = library default)                         */
+                            gain (0 = never; the residual-corrected sources
+                            make restarts unnecessary in practice)             */
 } ddm_solve_opts;
 
 typedef struct {
@@ -177,6 +178,30 @@ int ddm_transfer(ddm_handle *h, const void *lag1, const void *lag2, const void *
 
 /* Assembly of eq. tsum: u = sum_a beta_{0;a} U_a (packed U in, global u out). */
 int ddm_assemble(ddm_handle *h, const void *U, void *u, int nrhs);
+
+/* ---- continuous batching (slots) -------------------------------------------- */
+/* The handle's nrhs_max right-hand-side positions are slots that requests can
+ * join and leave at step boundaries while the others keep iterating: each
+ * slot runs Algorithm 3.1 from its own first step (its source, its own step
+ * count) on the shared factors.  Slot arithmetic does not depend on the other
+ * slots, so a slot's result is the same alone and in any mix. */
+
+/* Start a solve in a free slot: f is one DEVICE global vector (nglob
+ * complex128).  The slot's iterate starts at zero; its first step uses f
+ * restricted to the cores.  Returns DDM_EINVAL if the slot is in use. */
+int ddm_slot_admit(ddm_handle *h, int slot, const void *f);
+
+/* Enqueue nsteps DDM steps for every occupied slot (asynchronous). */
+int ddm_slots_step(ddm_handle *h, int nsteps);
+
+/* Synchronise and report per slot (nrhs_max entries each, host): relres of
+ * the slot's current iterate (-1 for a free slot) and its step count. */
+int ddm_slots_poll(ddm_handle *h, double *relres, int *steps);
+
+/* Copy a slot's iterate to u (DEVICE, nglob complex128; may be NULL) and free
+ * the slot.  ddm_iterate / ddm_solve return DDM_ESTATE while any slot of the
+ * handle is occupied (they share its buffers). */
+int ddm_slot_retire(ddm_handle *h, int slot, void *u);
 
 /* ---- observability -------------------------------------------------------- */
 

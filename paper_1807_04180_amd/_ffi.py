@@ -75,6 +75,10 @@ def lib():
     L.ddm_local_solve.argtypes = [H, P, P, I]
     L.ddm_transfer.argtypes = [H, P, P, P, P, I]
     L.ddm_assemble.argtypes = [H, P, P, I]
+    L.ddm_slot_admit.argtypes = [H, I, P]
+    L.ddm_slots_step.argtypes = [H, I]
+    L.ddm_slots_poll.argtypes = [H, DP, ctypes.POINTER(ctypes.c_int)]
+    L.ddm_slot_retire.argtypes = [H, I, P]
     L.ddm_set_graphs.argtypes = [H, I]
     L.ddm_graph_launches.argtypes = [H]
     L.ddm_graph_launches.restype = ctypes.c_long
@@ -85,7 +89,7 @@ def lib():
     L.ddm_set_spin_limit.argtypes = [H, I]
     L.ddm_profile_enable.argtypes = [H, I]
     L.ddm_profile_read.argtypes = [H, ctypes.POINTER(DdmProfile)]
-    for name in ("ddm_set_graphs", "ddm_set_factor_layout", "ddm_set_solve_variant", "ddm_get_solve_variant", "ddm_autotune", "ddm_set_spin_limit",
+    for name in ("ddm_slot_admit", "ddm_slots_step", "ddm_slots_poll", "ddm_slot_retire", "ddm_set_graphs", "ddm_set_factor_layout", "ddm_set_solve_variant", "ddm_get_solve_variant", "ddm_autotune", "ddm_set_spin_limit",
                  "ddm_profile_enable", "ddm_profile_read", "ddm_memory_required", "ddm_setup", "ddm_factor", "ddm_iterate", "ddm_solve", "ddm_sizes",
                  "ddm_geometry", "ddm_apply", "ddm_residual", "ddm_restrict_core", "ddm_local_solve",
                  "ddm_transfer", "ddm_assemble"):

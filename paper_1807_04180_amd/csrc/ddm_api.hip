@@ -281,6 +281,12 @@ int check_abort(ddm_handle *h) {
     return DDM_OK;
 }
 
+bool slots_busy(const ddm_handle *h) {
+    for (int s : h->slot_steps)
+        if (s >= 0) return true;
+    return false;
+}
+
 int check_args(ddm_handle *h, int nrhs) {
     if (!h) return DDM_EINVAL;
     if (nrhs < 1 || nrhs > h->nrhs_max) {
@@ -322,8 +328,9 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
     std::vector<double> rel, fn, best(nrhs, 1e300), last_gain_rel(nrhs, 1.0);
     std::vector<int> steps(nrhs, 0), status(nrhs, DDM_ENOCONV), since_gain(nrhs, 0);
     std::vector<double> secs(nrhs, 0.0), final_rel(nrhs, 1.0);
-    int nsum = P.N[0] + P.N[1] + P.N[2] - (3 - P.dim);
-    int refine_every = o.refine_every > 0 ? o.refine_every : nsum;
+    // restart on the residual after refine_every steps without a 2x gain
+    // (opt-in: the residual-corrected sources of the mixed path do not stall)
+    const int refine_every = o.refine_every;
     double2 *rsrc = h->d_r;  // residual (corrected sources) / restart source
     auto check = [&](int it, const double2 **restart) -> bool {
         fetch_norms(h, nrhs, rel, &fn);
@@ -342,7 +349,7 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
             if (rel[q] > 1e6 * best[q]) { status[q] = DDM_EDIVERGED; act[q] = 0; changed = true; continue; }
             if (rel[q] < best[q]) best[q] = rel[q];
             if (rel[q] < 0.5 * last_gain_rel[q]) { last_gain_rel[q] = rel[q]; since_gain[q] = 0; }
-            else if (++since_gain[q] >= refine_every) stalled = true;
+            else if (refine_every > 0 && ++since_gain[q] >= refine_every) stalled = true;
             all = false;
         }
         if (changed) set_active(h, act);
@@ -659,6 +666,145 @@ int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms) {
     return DDM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Continuous batching over slots.  The ring phase follows the handle's global
+// step counter; a slot that joins at global step S has its ring entries
+// zeroed (no lagged sources) and gets f restricted to the cores as its first
+// source, so its k-th own step computes exactly what step k of a solve alone
+// computes.  Mixed precision keeps the residual-corrected sources (the slot's
+// residual row starts as f).
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+static int slots_init(ddm_handle *h) {
+    if (!h->slot_steps.empty()) return DDM_OK;
+    const Plan &P = h->plan;
+    const size_t vb = (size_t)h->nrhs_max * P.nglob * sizeof(double2);
+    if (!h->d_fin) HIPCHK(hipMalloc((void **)&h->d_fin, vb));
+    if (!h->d_uin) HIPCHK(hipMalloc((void **)&h->d_uin, vb));
+    HIPCHK(launch_fill_zero(h->d_fin, (long long)vb, h->stream));
+    HIPCHK(launch_fill_zero(h->d_uin, (long long)vb, h->stream));
+    HIPCHK(launch_fill_zero(h->d_r, (long long)vb, h->stream));
+    const size_t es = elem_size(h->mixed);
+    HIPCHK(launch_fill_zero(h->d_g, (long long)h->nrhs_max * P.etot * es, h->stream));
+    for (int k = 0; k < P.ring; ++k)
+        HIPCHK(launch_fill_zero(h->d_ring[k], (long long)h->nrhs_max * P.etot * es, h->stream));
+    h->slot_steps.assign(h->nrhs_max, -1);
+    h->slot_global = 0;
+    std::vector<int> zero(h->nrhs_max, 0);
+    set_active(h, zero);
+    return DDM_OK;
+}
+
+extern "C" int ddm_slot_admit(ddm_handle *h, int slot, const void *f) {
+    if (!h || !f || slot < 0 || slot >= h->nrhs_max) return DDM_EINVAL;
+    if (!h->factored) return fail(h, DDM_ESTATE, "ddm_slot_admit before ddm_factor");
+    const Plan &P = h->plan;
+    try {
+        int st = slots_init(h);
+        if (st) return st;
+        if (h->slot_steps[slot] >= 0) return fail(h, DDM_EINVAL, "slot in use");
+        const size_t vb = (size_t)P.nglob * sizeof(double2);
+        const size_t es = elem_size(h->mixed);
+        HIPCHK(hipMemcpyAsync(h->d_fin + (size_t)slot * P.nglob, f, vb, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d_r + (size_t)slot * P.nglob, f, vb, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(launch_fill_zero(h->d_uin + (size_t)slot * P.nglob, (long long)vb, h->stream));
+        for (int k = 0; k < P.ring; ++k)
+            HIPCHK(launch_fill_zero((char *)h->d_ring[k] + (size_t)slot * P.etot * es, (long long)P.etot * es,
+                                    h->stream));
+        h->slot_steps[slot] = 0;
+        int one = 1;
+        HIPCHK(hipMemcpyAsync(h->d_active + slot, &one, sizeof(int), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
+template <typename T>
+static void slots_step_impl(ddm_handle *h, int nsteps) {
+    const Plan &P = h->plan;
+    const int n = h->nrhs_max;
+    const size_t es = sizeof(T);
+    const double2 *rcorr = h->mixed ? h->d_r : nullptr;
+    for (int k = 0; k < nsteps; ++k) {
+        const long long s = ++h->slot_global;
+        T *g = (T *)h->d_g;
+        HIPCHK((launch_transfer<T, T>(h, ring_at<T>(h, (int)(s - 1)), ring_at<T>(h, (int)(s - 2)),
+                                      ring_at<T>(h, (int)(s - 3)), g, n, rcorr)));
+        // slots at their first step: f restricted to the cores
+        for (int q = 0; q < n; ++q)
+            if (h->slot_steps[q] == 0)
+                HIPCHK((launch_restrict<double2, T>(h, h->d_fin + (size_t)q * P.nglob, g + (size_t)q * P.etot, 1)));
+        T *us = (T *)h->d_ring[s % P.ring];
+        HIPCHK(launch_local_solve<T>(h, g, us, n));
+        HIPCHK(launch_assemble<T>(h, us, h->d_uin, n, true, h->d_active));
+        HIPCHK(launch_residual(h, h->d_fin, h->d_uin, const_cast<double2 *>(rcorr), n, h->d_norm, h->d_norm + n));
+        for (int q = 0; q < n; ++q)
+            if (h->slot_steps[q] >= 0) ++h->slot_steps[q];
+    }
+    (void)es;
+}
+
+extern "C" {
+
+int ddm_slots_step(ddm_handle *h, int nsteps) {
+    if (!h || nsteps < 0) return DDM_EINVAL;
+    if (!h->factored) return fail(h, DDM_ESTATE, "ddm_slots_step before ddm_factor");
+    try {
+        int st = slots_init(h);
+        if (st) return st;
+        if (h->mixed) slots_step_impl<float2>(h, nsteps);
+        else slots_step_impl<double2>(h, nsteps);
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
+int ddm_slots_poll(ddm_handle *h, double *relres, int *steps) {
+    if (!h) return DDM_EINVAL;
+    const int n = h->nrhs_max;
+    try {
+        int st = slots_init(h);
+        if (st) return st;
+        std::vector<double> rel;
+        fetch_norms(h, n, rel);
+        for (int q = 0; q < n; ++q) {
+            bool occ = h->slot_steps[q] >= 0;
+            if (relres) relres[q] = occ && h->slot_steps[q] > 0 ? rel[q] : -1.0;
+            if (steps) steps[q] = h->slot_steps[q];
+        }
+        return check_abort(h);
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+}
+
+int ddm_slot_retire(ddm_handle *h, int slot, void *u) {
+    if (!h || slot < 0 || slot >= h->nrhs_max) return DDM_EINVAL;
+    const Plan &P = h->plan;
+    try {
+        int st = slots_init(h);
+        if (st) return st;
+        if (h->slot_steps[slot] < 0) return fail(h, DDM_EINVAL, "slot is free");
+        if (u)
+            HIPCHK(hipMemcpyAsync(u, h->d_uin + (size_t)slot * P.nglob, (size_t)P.nglob * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, h->stream));
+        int zero = 0;
+        HIPCHK(hipMemcpyAsync(h->d_active + slot, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
+        // a free slot iterates on zero data: clear its source and residual rows
+        HIPCHK(launch_fill_zero(h->d_fin + (size_t)slot * P.nglob, (long long)P.nglob * sizeof(double2), h->stream));
+        HIPCHK(launch_fill_zero(h->d_r + (size_t)slot * P.nglob, (long long)P.nglob * sizeof(double2), h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->slot_steps[slot] = -1;
+    } catch (const HipFail &e) {
+        return hip_fail(h, e);
+    }
+    return DDM_OK;
+}
+
 const char *ddm_version(void) { return "libddm 0.1 (gfx950, HIP)"; }
 
 const char *ddm_last_error(const ddm_handle *h) { return h ? h->err.c_str() : g_setup_error.c_str(); }
@@ -895,6 +1041,7 @@ int ddm_local_solve(ddm_handle *h, const void *g, void *uhat, int nrhs) {
 int ddm_iterate(ddm_handle *h, const void *f, void *u, int nrhs, int nsteps, double *relres) {
     int st = check_args(h, nrhs);
     if (st) return st;
+    if (slots_busy(h)) return fail(h, DDM_ESTATE, "slots are in use: retire them before a batch solve");
     if (!h->factored) return fail(h, DDM_ESTATE, "ddm_iterate before ddm_factor");
     if (nsteps < 0) return fail(h, DDM_EINVAL, "nsteps < 0");
     const Plan &P = h->plan;
@@ -921,6 +1068,7 @@ int ddm_iterate(ddm_handle *h, const void *f, void *u, int nrhs, int nsteps, dou
 int ddm_solve(ddm_handle *h, const void *f, void *u, int nrhs, const ddm_solve_opts *opts, ddm_rhs_info *info) {
     int st = check_args(h, nrhs);
     if (st) return st;
+    if (slots_busy(h)) return fail(h, DDM_ESTATE, "slots are in use: retire them before a batch solve");
     if (!opts) return fail(h, DDM_EINVAL, "opts is null");
     if (!h->factored) return fail(h, DDM_ESTATE, "ddm_solve before ddm_factor");
     if (!(opts->tol > 0) || opts->maxiter < 1) return fail(h, DDM_EINVAL, "tol must be > 0 and maxiter >= 1");

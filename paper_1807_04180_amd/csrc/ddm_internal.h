@@ -115,6 +115,11 @@ struct ddm_handle {
     int solve_variant = 0;
     int *d_sync = nullptr;          // 2 nsub meeting flags + 1 abort flag
     int spin_limit = 1 << 22;
+    // continuous batching: per-slot step counts (-1 = free), the handle's
+    // global step counter drives the ring phase
+    std::vector<int> slot_steps;
+    long long slot_global = 0;
+    bool slots_dirty = false;       // d_active needs an upload
     // hipGraph capture of the stationary DDM step (one graph per ring phase)
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;

@@ -214,6 +214,24 @@ class HelmholtzDDM:
     def set_spin_limit(self, limit: int):
         self._check(self.lib.ddm_set_spin_limit(self._h, int(limit)))
 
+    # -- continuous batching (slots) -------------------------------------
+    def slot_admit(self, slot: int, f: torch.Tensor):
+        if f.dtype != torch.complex128 or f.numel() != self.nglob:
+            raise ValueError("f must be one complex128 global vector")
+        self._check(self.lib.ddm_slot_admit(self._h, int(slot), _ptr(f.contiguous())))
+
+    def slots_step(self, nsteps: int = 1):
+        self._check(self.lib.ddm_slots_step(self._h, int(nsteps)))
+
+    def slots_poll(self):
+        rel = (ctypes.c_double * self.nrhs_max)()
+        st = (ctypes.c_int * self.nrhs_max)()
+        self._check(self.lib.ddm_slots_poll(self._h, rel, st))
+        return list(rel), list(st)
+
+    def slot_retire(self, slot: int, u: Optional[torch.Tensor] = None):
+        self._check(self.lib.ddm_slot_retire(self._h, int(slot), _ptr(u)))
+
     # -- observability -----------------------------------------------------
     def profile_enable(self, on: bool = True):
         self._check(self.lib.ddm_profile_enable(self._h, 1 if on else 0))
