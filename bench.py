@@ -37,6 +37,24 @@ METRIC = "Helmholtz solves/sec at rel.resid 1e-6 (mixed vs FP64 DDM); p50/p99 la
 HBM_PEAK_GBS = 8000.0
 
 
+def workloads():
+    """name -> (builder, stationary tolerance, description).  cfg2 is the
+    default (the headline configuration); the others are measured with
+    --workload and are not the bench line's `value`."""
+    import ddm_inputs as di
+    return {
+        "cfg2": (lambda: di.config2(nrhs=4), 1e-6,
+                 "2D constant medium, 1024^2 interior (h=1/1024, omega=2*pi*102.4, 10 ppw), 5-point FD, PML 16 "
+                 "(R=1e-6), 8x8 subdomains of 128^2 with overlap 8, 4 seeded Gaussian sources (std 2h)"),
+        "cfg1": (di.config1, 1e-8,
+                 "2D constant medium, 80^2 interior (omega=2*pi*8, 10 ppw), 5-point FD, PML 10 (R=1e-6), 2x2 "
+                 "subdomains, overlap 4, one Gaussian source (std 2h) at the centre"),
+        "cfg3": (lambda: di.config3(nrhs=16), 1e-6,
+                 "2D layered medium, 2048^2 interior (8 layers 1.5-4.5 plus 10% smoothed perturbation, 8 ppw at "
+                 "c=1.5), 5-point FD, PML 20 (R=1e-6), 16x16 subdomains, overlap 8, 16 seeded Gaussian sources"),
+    }
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -101,7 +119,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--workload", choices=["cfg2", "cfg1", "cfg3"], default="cfg2",
+                    help="cfg2 (default): 2D 1024^2 8x8, 4 RHS; cfg1: 2D 80^2 2x2; cfg3: 2D layered 2048^2 "
+                         "16x16, 16 RHS")
+    ap.add_argument("--tol", type=float, default=None, help="stationary/FGMRES tolerance (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FGMRES and mixed-precision legs")
     ap.add_argument("--probe", choices=["none", "traffic"], default="none",
@@ -121,7 +142,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    w = di.config2(nrhs=4)
+    build_w, tol_w, wdesc = workloads()[args.workload]
+    if args.tol is None:
+        args.tol = tol_w
+    if args.workload != "cfg2":
+        args.no_cpu_baseline = True  # the oracle baseline is sampled from the headline workload only
+    w = build_w()
     nrhs = w.nrhs
     log("bench: workload %s nglob=%d nrhs=%d on %s" % (w.name, int(np.prod(w.grid_shape)), nrhs,
                                                         torch.cuda.get_device_name(0)))
@@ -190,11 +216,8 @@ def main():
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": ("2D constant medium, 1024^2 interior (h=1/1024, omega=2*pi*102.4, 10 ppw), "
-                                "5-point FD, PML 16 (R=1e-6), 8x8 subdomains of 128^2 with overlap 8, "
-                                "4 seeded Gaussian sources (std 2h), complex128 stationary DDM to relres %.0e"
-                                % args.tol),
-                   "global_batch": nrhs, "grid": [1024, 1024], "subdomains": [8, 8], "method": "stationary",
+        "config": {"workload": wdesc + ", complex128 stationary DDM to relres %.0e" % args.tol,
+                   "global_batch": nrhs, "grid": list(w.M), "subdomains": list(w.N), "method": "stationary",
                    "precision": "fp64"},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "ddm_steps_per_solve": steps_full,
@@ -212,7 +235,8 @@ def main():
     avg_us = sub["ms"] / max(sub["launches"], 1) * 1e3
     achieved = sub["bytes"] / (sub["ms"] * 1e-3) / 1e9 if sub["ms"] > 0 else 0.0
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(s64.solve_variant()),
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": recorded_traffic(s64.solve_variant()) if args.workload == "cfg2" else None,
                        "kernel": ("k_solve_chain" if s64.solve_variant() == "chain" else "k_solve_line")
                                  + " (block substitution)",
                        "avg_launch_us": avg_us, "launches": sub["launches"],
@@ -234,7 +258,7 @@ def main():
         torch.cuda.synchronize()
         tf = time.perf_counter() - t0
         errf = (torch.linalg.vector_norm(uf - u64, dim=1) / torch.linalg.vector_norm(u64, dim=1)).tolist()
-        out["fgmres"] = {"solves_per_s": nrhs / tf, "ms_per_batch": tf * 1e3, "K": 16, "restart": 30,
+        out["fgmres"] = {"solves_per_s": nrhs / tf, "ms_per_batch": tf * 1e3, "K": int(sum(w.N)), "restart": 30,
                          "gmres_iters": [x["iters"] for x in infof],
                          "local_solves": [x["local_solves"] for x in infof],
                          "relres": [x["relres"] for x in infof], "rel_diff_vs_stationary": errf, "status": stf}
@@ -278,7 +302,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("bench: CPU baseline (oracle) ...")
-        out["cpu_baseline"] = run_cpu_baseline(nrhs, 64, steps_full, args.tol)
+        out["cpu_baseline"] = run_cpu_baseline(nrhs, int(np.prod(w.N)), steps_full, args.tol)
         log("bench: CPU baseline %.4f solves/s" % out["cpu_baseline"]["value"])
 
     print(json.dumps(out), flush=True)

@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
                                                            long long etot, int dim, int twisted, int *flags,
                                                            int *abort_flag, int spin_limit) {
     extern __shared__ unsigned char lds_raw[];
-    constexpr int kCBatch = ChainBatch<T2>::value;
+    constexpr int kCBatch = RT >= 16 ? 4 : ChainBatch<T2>::value;
     const int a = twisted ? (int)(blockIdx.x >> 1) : (int)blockIdx.x;
     const int chain = twisted ? (int)(blockIdx.x & 1) : 0;
     const SubDesc &s = subs[a];
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
             }
             // ---- prefetch the block-vector entries the reduction will need
             // (forward: g of the next block; backward: this block's y) ----
-            constexpr int kPre = 2;  // bsp * RT <= 2 * kCThreads
+            constexpr int kPre = (256 * RT + kCThreads - 1) / kCThreads;  // bsp * RT <= kPre * kCThreads
             const int tn = t + 1;
             const int lnv = tn < nsteps && tn != nf ? step_l(tn) : -1;
             T2 pre[kPre];
@@ -416,7 +416,8 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
         return run_chain<T, 4>(h, g, x, nrhs);
     } else {
         if (nrhs <= 4) return run_chain<T, 4>(h, g, x, nrhs);
-        return run_chain<T, 8>(h, g, x, nrhs);
+        if (nrhs <= 8) return run_chain<T, 8>(h, g, x, nrhs);
+        return run_chain<T, 16>(h, g, x, nrhs);
     }
 }
 

@@ -212,8 +212,8 @@ def test_iterate_layouts_match_oracle(pair, layout):
 
 def test_chain_mixed_matches_oracle():
     w = CASES["2d-3x3-layered"]()
-    o, g = make_pair(w, nrhs_max=9, mixed=True)
-    for nrhs in (3, 9):  # RHS tiles of 4 and 8
+    o, g = make_pair(w, nrhs_max=20, mixed=True)
+    for nrhs in (3, 6, 9, 20):  # RHS tiles of 4, 8, 16 and 16 + a ragged 4
         gin = di.random_field((nrhs, o.etot), seed=51)
         assert relerr(_n(g.local_solve(_t(gin))), o.local_solve(gin), axis=1) < 5e-5
     g.close()
