@@ -104,7 +104,7 @@ size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
     b += P.owner.size() * sizeof(int) + P.btab.size() * sizeof(double) + P.items.size() * sizeof(SolveItem);
     b += (size_t)P.nglob * sizeof(double);                         // k2
     b += (size_t)P.fel * es;                                       // factors
-    b += (size_t)2 * P.nsub * P.bs_max * P.bs_max * sizeof(double2);  // FP64 factor scratch (freed after factor)
+    b += factor_ws_bytes(P);                                       // factor workspace (freed after factor)
     b += (size_t)(1 + P.ring) * nrhs * P.etot * es;                // g + ring
     b += (size_t)nrhs * P.nglob * sizeof(double2);                 // residual / operator output
     if (mixed) b += (size_t)nrhs * P.etot * sizeof(double2);       // widening scratch
@@ -924,10 +924,10 @@ int ddm_factor(ddm_handle *h) {
     const Plan &P = h->plan;
     try {
         if (!h->d_scratch) {
-            HIPCHK(hipMalloc((void **)&h->d_scratch, (size_t)2 * P.nsub * P.bs_max * P.bs_max * sizeof(double2)));
+            HIPCHK(hipMalloc(&h->d_scratch, factor_ws_bytes(P)));
         }
-        if (h->mixed) HIPCHK(launch_factor<float2>(h));
-        else HIPCHK(launch_factor<double2>(h));
+        if (h->mixed) HIPCHK(launch_factor<float2>(h, h->d_scratch));
+        else HIPCHK(launch_factor<double2>(h, h->d_scratch));
         std::vector<int> flags(3 * P.nsub);
         HIPCHK(hipMemcpyAsync(flags.data(), h->d_flags, 3 * P.nsub * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));

@@ -7,15 +7,27 @@
 // coefficients of the last axis.  The factorisation is
 //     S_0 = D_0,   S_l = D_l - cm(l) cp(l-1) W_{l-1},   W_l = S_l^{-1},
 // and W_l is stored column-major (element (i, j) at j * bs + i), complex128
-// or complex64.  The inverse is formed by in-place Gauss-Jordan elimination
-// with partial (row) pivoting inside S_l, in FP64.
-//
+// or complex64.  Since C_l and B_l are multiples of the identity, the Schur
+// complement update is a scaled copy; the dense work is the inversion of
+// every S_l, done in FP64 by blocked Gauss-Jordan elimination with partial
+// pivoting:
+//   * panels of kPanel columns; a panel kernel (one workgroup per chain)
+//     picks the panel's pivot rows by unblocked elimination of a copy of the
+//     panel, inverts the kPanel x kPanel pivot block A11 and forms
+//     Y = A11^{-1} [pivot rows of S] and X = -[panel columns of S], pivot rows
+//     zeroed;
+//   * an update kernel applies S <- S + X Y (panel columns start from zero,
+//     pivot rows become Y) over 64 x 64 tiles with FP64 MFMA
+//     (v_mfma_f64_16x16x4, complex product as four real products); every
+//     chain's tiles go into one launch;
+//   * pivot rows are never swapped: row r chosen at step k is recorded
+//     (ppos[r] = k, piv[k] = r) and the inverse is read back as
+//     W(i, j) = N(piv[i], ppos[j]) when the block is stored.
 // The elimination runs from both ends of the subdomain towards a middle
 // block mid (a twisted factorisation; mid = nb - 1 is the one-directional
-// case): one workgroup (1024 threads) per chain and subdomain walks its
-// blocks in order, then one workgroup per subdomain inverts the middle block.
-// The current block lives in an FP64 scratch matrix (L2-resident for 2D block
-// sizes); row k / column k of each elimination step are staged in LDS.
+// case); all chains advance in lock step, one launch per panel step, then the
+// middle blocks are inverted the same way.  Each chain owns two FP64 block
+// buffers (the block being inverted and the next Schur complement).
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -25,9 +37,6 @@
 
 namespace ddm {
 
-constexpr int kFThreads = 1024;
-constexpr int kFWaves = kFThreads / 64;
-
 struct FactArgs {
     int dim;
     int G0, G1;
@@ -36,8 +45,9 @@ struct FactArgs {
     int nsub;
 };
 
-// block-wide argmax of (value, index); ties go to the smaller index
-__device__ inline void block_argmax(double &v, int &idx, double *sv, int *si) {
+// block-wide argmax of (value, index) over NW waves; ties go to the smaller index
+template <int NW>
+__device__ inline void block_argmax_n(double &v, int &idx, double *sv, int *si) {
     for (int o = 32; o > 0; o >>= 1) {
         double ov = __shfl_down(v, o, 64);
         int oi = __shfl_down(idx, o, 64);
@@ -47,7 +57,7 @@ __device__ inline void block_argmax(double &v, int &idx, double *sv, int *si) {
     if (lane == 0) { sv[w] = v; si[w] = idx; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < kFWaves; ++i)
+        for (int i = 1; i < NW; ++i)
             if (sv[i] > sv[0] || (sv[i] == sv[0] && si[i] < si[0])) { sv[0] = sv[i]; si[0] = si[i]; }
     }
     __syncthreads();
@@ -56,13 +66,14 @@ __device__ inline void block_argmax(double &v, int &idx, double *sv, int *si) {
     __syncthreads();
 }
 
-__device__ inline double block_max(double v, double *sv) {
+template <int NW>
+__device__ inline double block_max_n(double v, double *sv) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) sv[w] = v;
     __syncthreads();
     if (threadIdx.x == 0)
-        for (int i = 1; i < kFWaves; ++i) sv[0] = fmax(sv[0], sv[i]);
+        for (int i = 1; i < NW; ++i) sv[0] = fmax(sv[0], sv[i]);
     __syncthreads();
     v = sv[0];
     __syncthreads();
@@ -107,174 +118,377 @@ __device__ inline double2 block_entry(const SubDesc &s, const Coef *__restrict__
     return v;
 }
 
-// In-place Gauss-Jordan inversion of the bs x bs column-major FP64 matrix M
-// with partial (row) pivoting; returns a non-zero status (1 + column) in
-// every thread if a pivot falls below bs * eps * max|M|.
-__device__ int gj_invert(double2 *__restrict__ M, int bs, double2 *rowk, double2 *rs, double2 *colk, int *perm,
-                         double *sv, int *si) {
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    double mx = 0.0;
-    for (int j = ty; j < bs; j += kFWaves)
-        for (int i = tx; i < bs; i += 64) mx = fmax(mx, cabs2(M[(long long)j * bs + i]));
-    mx = block_max(mx, sv);
+
+constexpr int kPanel = 32;      // panel width (columns per elimination panel)
+constexpr int kPThreads = 512;  // panel kernel
+constexpr int kPWaves = kPThreads / 64;
+constexpr int kUTile = 64;      // update tile edge
+constexpr int kUThreads = 256;  // update kernel: 2 x 2 waves of 32 x 32
+constexpr int kEThreads = 256;  // form / store kernels
+constexpr int kEGroups = 64;    // max workgroups per chain for form / store
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Per-chain factor workspace (chain c = 2 * subdomain + direction).
+struct FactWs {
+    double2 *M;         // [chain][2][bs_max^2] FP64 block buffers
+    double *X, *Y;      // [chain][re, im][kPanel][bsp] panel operands
+    double2 *Pw;        // [chain][kPanel][bsp] panel work (when not in LDS)
+    int *ppos, *piv;    // [chain][bsp] pivot step of a row / row of a pivot step
+    double *mx;         // [chain] max |S_l|^2 of the block being inverted
+    long long mstride;  // bs_max^2
+    int bsp;            // bs_max rounded up to kUTile
+};
+
+size_t factor_ws_bytes(const Plan &P) {
+    const size_t bsp = (size_t)((P.bs_max + kUTile - 1) / kUTile) * kUTile;
+    const size_t nc = (size_t)2 * P.nsub;
+    size_t b = nc * 2 * (size_t)P.bs_max * P.bs_max * sizeof(double2);
+    b += nc * 4 * kPanel * bsp * sizeof(double);
+    b += nc * kPanel * bsp * sizeof(double2);
+    b += nc * 2 * bsp * sizeof(int) + nc * sizeof(double);
+    return b + 4096;
+}
+
+static FactWs carve_ws(const Plan &P, void *base) {
+    FactWs w;
+    w.bsp = ((P.bs_max + kUTile - 1) / kUTile) * kUTile;
+    w.mstride = (long long)P.bs_max * P.bs_max;
+    const size_t nc = (size_t)2 * P.nsub;
+    char *p = (char *)base;
+    w.M = (double2 *)p;  p += nc * 2 * w.mstride * sizeof(double2);
+    w.X = (double *)p;   p += nc * 2 * kPanel * w.bsp * sizeof(double);
+    w.Y = (double *)p;   p += nc * 2 * kPanel * w.bsp * sizeof(double);
+    w.Pw = (double2 *)p; p += nc * kPanel * w.bsp * sizeof(double2);
+    w.ppos = (int *)p;   p += nc * w.bsp * sizeof(int);
+    w.piv = (int *)p;    p += nc * w.bsp * sizeof(int);
+    p = (char *)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+    w.mx = (double *)p;
+    return w;
+}
+
+// Where chain c stands at lock-step s (mid == false), or at its subdomain's
+// middle block (mid == true; only even chains take part).
+struct ChainPos {
+    bool active;
+    int a, dir, l, bs, nb, cur, len, last;
+};
+
+__device__ inline ChainPos chain_pos(const SubDesc *__restrict__ subs, int c, int s, bool mid) {
+    ChainPos q;
+    q.a = c >> 1;
+    q.dir = c & 1;
+    const SubDesc &sd = subs[q.a];
+    q.bs = sd.bs;
+    q.nb = sd.nb;
+    const int len0 = sd.mid, len1 = sd.nb - 1 - sd.mid;
+    if (!mid) {
+        q.len = q.dir == 0 ? len0 : len1;
+        q.active = s < q.len;
+        q.l = q.dir == 0 ? s : sd.nb - 1 - s;
+        q.cur = s & 1;
+        q.last = s + 1 == q.len;
+    } else {
+        q.len = len0;
+        q.active = q.dir == 0;
+        q.l = sd.mid;
+        q.cur = (len0 & 1) ^ 1;
+        q.last = 1;
+    }
+    return q;
+}
+
+__device__ inline double2 *chain_M(const FactWs &w, int c, int buf) {
+    return w.M + ((long long)c * 2 + buf) * w.mstride;
+}
+
+// First block of every chain: M[c][0] = D_first.
+__global__ __launch_bounds__(kEThreads) void k_factor_form0(const SubDesc *__restrict__ subs,
+                                                            const Coef *__restrict__ coef,
+                                                            const double *__restrict__ k2, FactArgs A, FactWs w,
+                                                            int groups) {
+    const int c = blockIdx.x / groups, grp = blockIdx.x % groups;
+    const ChainPos q = chain_pos(subs, c, 0, false);
+    if (!q.active) return;
+    const SubDesc &s = subs[q.a];
+    const Coef cl = coef[s.coff[A.dim - 1] + q.l];
+    double2 *M = chain_M(w, c, 0);
+    const long long n2 = (long long)q.bs * q.bs;
+    for (long long e = (long long)grp * kEThreads + threadIdx.x; e < n2; e += (long long)groups * kEThreads) {
+        const int i = (int)(e % q.bs), j = (int)(e / q.bs);
+        M[e] = block_entry(s, coef, k2, A, q.l, i, j, cl);
+    }
+}
+
+// Middle block of every subdomain:
+// Z = D_mid - cm(mid) cp(mid-1) S_{mid-1}^{-1} - cp(mid) cm(mid+1) T_{mid+1}^{-1},
+// the two inverses being the chains' final buffers.
+__global__ __launch_bounds__(kEThreads) void k_factor_formmid(const SubDesc *__restrict__ subs,
+                                                              const Coef *__restrict__ coef,
+                                                              const double *__restrict__ k2, FactArgs A, FactWs w,
+                                                              int groups) {
+    const int a = blockIdx.x / groups, grp = blockIdx.x % groups;
+    const SubDesc &s = subs[a];
+    const int ax = A.dim - 1, l = s.mid, bs = s.bs;
+    const int len0 = s.mid, len1 = s.nb - 1 - s.mid;
+    const Coef cl = coef[s.coff[ax] + l];
+    const double2 c1 = len0 > 0 ? cmul(cl.cm, coef[s.coff[ax] + l - 1].cp) : make_double2(0, 0);
+    const double2 c2 = len1 > 0 ? cmul(cl.cp, coef[s.coff[ax] + l + 1].cm) : make_double2(0, 0);
+    const double2 *I0 = len0 > 0 ? chain_M(w, 2 * a, len0 & 1) : nullptr;
+    const double2 *I1 = len1 > 0 ? chain_M(w, 2 * a + 1, len1 & 1) : nullptr;
+    double2 *Z = chain_M(w, 2 * a, (len0 & 1) ^ 1);
+    const long long n2 = (long long)bs * bs;
+    for (long long e = (long long)grp * kEThreads + threadIdx.x; e < n2; e += (long long)groups * kEThreads) {
+        const int i = (int)(e % bs), j = (int)(e / bs);
+        double2 v = block_entry(s, coef, k2, A, l, i, j, cl);
+        if (I0) v = csub(v, cmul(c1, I0[e]));
+        if (I1) v = csub(v, cmul(c2, I1[e]));
+        Z[e] = v;
+    }
+}
+
+// Panel kernel: pivots, A11^{-1}, X and Y of panel p (columns k0 .. k0+bw-1)
+// of the block chain c is inverting.
+__global__ __launch_bounds__(kPThreads) void k_factor_panel(const SubDesc *__restrict__ subs, FactWs w, int s, int p,
+                                                            int mid, int pw_in_lds, int *__restrict__ flags,
+                                                            int nsub) {
+    extern __shared__ double2 lds[];
+    __shared__ double sv[kPWaves];
+    __shared__ int si[kPWaves];
+    const int c = blockIdx.x;
+    const ChainPos q = chain_pos(subs, c, s, mid != 0);
+    if (!q.active) return;
+    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
+    if (k0 >= bs) return;
+    const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
+    const double2 *M = chain_M(w, c, q.cur);
+    double *Xr = w.X + (long long)c * 2 * kPanel * bsp, *Xi = Xr + (long long)kPanel * bsp;
+    double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
+    int *ppos = w.ppos + (long long)c * bsp, *piv = w.piv + (long long)c * bsp;
+    double2 *Ainv = lds;                      // [kPanel][kPanel]
+    double2 *rowr = Ainv + kPanel * kPanel;   // [kPanel]
+    int *R1 = (int *)(rowr + kPanel);         // [kPanel]
+    int *ppos_s = R1 + kPanel;                // [bsp]
+    double2 *Pw = pw_in_lds ? (double2 *)(ppos_s + bsp) : w.Pw + (long long)c * kPanel * bsp;
+    const int tid = threadIdx.x;
+    double mx;
+    if (p == 0) {
+        for (int i = tid; i < bsp; i += kPThreads) ppos_s[i] = -1;
+        double m = 0.0;
+        for (long long e = tid; e < (long long)bs * bs; e += kPThreads) m = fmax(m, cabs2(M[e]));
+        mx = block_max_n<kPWaves>(m, sv);
+        if (tid == 0) w.mx[c] = mx;
+    } else {
+        for (int i = tid; i < bsp; i += kPThreads) ppos_s[i] = ppos[i];
+        mx = w.mx[c];
+    }
+    // working copy of the panel; X = -panel
+    for (int e = tid; e < kPanel * bsp; e += kPThreads) {
+        const int t = e / bsp, i = e % bsp;
+        const double2 v = (t < bw && i < bs) ? M[(long long)(k0 + t) * bs + i] : make_double2(0, 0);
+        Pw[e] = v;
+        Xr[e] = -v.x;
+        Xi[e] = -v.y;
+    }
+    __syncthreads();
     double tiny2 = (double)bs * DBL_EPSILON;
     tiny2 = tiny2 * tiny2 * mx;
     int status = 0;
-    for (int k = 0; k < bs; ++k) {
-        double pv = -1.0;
-        int pi = k;
-        for (int i = k + threadIdx.x; i < bs; i += kFThreads) {
-            double v = cabs2(M[(long long)k * bs + i]);
-            if (v > pv) { pv = v; pi = i; }
-        }
-        block_argmax(pv, pi, sv, si);
-        if (!(pv > tiny2) && status == 0) status = 1 + k;
-        if (threadIdx.x == 0) perm[k] = pi;
-        if (pi != k)
-            for (int j = threadIdx.x; j < bs; j += kFThreads) {
-                double2 t = M[(long long)j * bs + k];
-                M[(long long)j * bs + k] = M[(long long)j * bs + pi];
-                M[(long long)j * bs + pi] = t;
+    for (int t = 0; t < bw; ++t) {
+        double best = -1.0;
+        int bi = bs;
+        for (int i = tid; i < bs; i += kPThreads)
+            if (ppos_s[i] < 0) {
+                const double v = cabs2(Pw[t * bsp + i]);
+                if (v > best) { best = v; bi = i; }
             }
-        __syncthreads();
-        for (int j = threadIdx.x; j < bs; j += kFThreads) {
-            rowk[j] = M[(long long)j * bs + k];
-            colk[j] = M[(long long)k * bs + j];
+        block_argmax_n<kPWaves>(best, bi, sv, si);
+        const int r = bi;
+        if (!(best > tiny2) && status == 0) status = 1 + q.l * bs + k0 + t;
+        if (tid < bw) rowr[tid] = Pw[tid * bsp + r];
+        if (tid == 0) {
+            ppos_s[r] = k0 + t;
+            R1[t] = r;
         }
         __syncthreads();
-        double2 inv = cinv(rowk[k]);
-        for (int j = threadIdx.x; j < bs; j += kFThreads) rs[j] = j == k ? inv : cmul(rowk[j], inv);
+        const double2 inv = cinv(rowr[t]);
+        for (int i = tid; i < bs; i += kPThreads) {
+            if (i == r) {
+                for (int u = 0; u < bw; ++u) Pw[u * bsp + r] = u == t ? inv : cmul(rowr[u], inv);
+            } else {
+                const double2 f = cmul(Pw[t * bsp + i], inv);
+                for (int u = 0; u < bw; ++u)
+                    if (u != t) Pw[u * bsp + i] = csub(Pw[u * bsp + i], cmul(f, rowr[u]));
+                Pw[t * bsp + i] = make_double2(-f.x, -f.y);
+            }
+        }
         __syncthreads();
-        for (int j = ty; j < bs; j += kFWaves) {
-            double2 rj = rs[j];
-            for (int i = tx; i < bs; i += 64) {
-                long long o = (long long)j * bs + i;
-                if (i == k) {
-                    M[o] = rj;
-                } else if (j == k) {
-                    M[o] = make_double2(-(colk[i].x * inv.x - colk[i].y * inv.y),
-                                        -(colk[i].x * inv.y + colk[i].y * inv.x));
-                } else {
-                    double2 c = colk[i];
-                    double2 m = M[o];
-                    m.x -= c.x * rj.x - c.y * rj.y;
-                    m.y -= c.x * rj.y + c.y * rj.x;
-                    M[o] = m;
+    }
+    // A11^{-1}: the pivot rows of the eliminated panel, in pivot order
+    for (int e = tid; e < bw * bw; e += kPThreads) {
+        const int t = e / bw, u = e % bw;
+        Ainv[t * kPanel + u] = Pw[u * bsp + R1[t]];
+    }
+    __syncthreads();
+    // pivot rows of S (all columns) into the panel work area
+    for (int e = tid; e < kPanel * bsp; e += kPThreads) {
+        const int u = e / bsp, j = e % bsp;
+        Pw[e] = (u < bw && j < bs) ? M[(long long)j * bs + R1[u]] : make_double2(0, 0);
+    }
+    __syncthreads();
+    // Y = A11^{-1} [pivot rows], with A11^{-1} itself in the panel columns
+    for (int e = tid; e < kPanel * bsp; e += kPThreads) {
+        const int t = e / bsp, j = e % bsp;
+        double2 y = make_double2(0, 0);
+        if (t < bw && j < bs) {
+            if (j >= k0 && j < k0 + bw) {
+                y = Ainv[t * kPanel + (j - k0)];
+            } else {
+                for (int u = 0; u < bw; ++u) cfma(y, Ainv[t * kPanel + u], Pw[u * bsp + j]);
+            }
+        }
+        Yr[e] = y.x;
+        Yi[e] = y.y;
+    }
+    // pivot rows take no part in X
+    for (int e = tid; e < bw * kPanel; e += kPThreads) {
+        const int t = e / kPanel, u = e % kPanel;
+        Xr[(long long)u * bsp + R1[t]] = 0.0;
+        Xi[(long long)u * bsp + R1[t]] = 0.0;
+    }
+    for (int i = tid; i < bsp; i += kPThreads) ppos[i] = ppos_s[i];
+    if (tid < bw) piv[k0 + tid] = R1[tid];
+    if (tid == 0 && status) {
+        int *f = flags + (mid ? 2 * nsub + q.a : c);
+        if (*f == 0) *f = status;
+    }
+}
+
+// Update kernel: S <- S + X Y on the block of every active chain (panel
+// columns start from zero; pivot rows of the panel become Y).  Tile 64 x 64,
+// four waves of 32 x 32, each as 2 x 2 MFMA blocks of 16 x 16.  In an MFMA
+// block, the lane holding column q of row group g keeps rows 4 g .. 4 g + 3
+// (accumulator register r holds block row g + 4 r, so the A operand of
+// lane row i reads matrix row 4 (i % 4) + i / 4).
+__global__ __launch_bounds__(kUThreads) void k_factor_update(const SubDesc *__restrict__ subs, FactWs w, int s,
+                                                             int p, int mid, int tpd) {
+    const int ntile = tpd * tpd;
+    const int c = blockIdx.x / ntile, tile = blockIdx.x % ntile;
+    const ChainPos q = chain_pos(subs, c, s, mid != 0);
+    if (!q.active) return;
+    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
+    if (k0 >= bs) return;
+    const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
+    const int i0 = (tile % tpd) * kUTile, j0 = (tile / tpd) * kUTile;
+    if (i0 >= bs || j0 >= bs) return;
+    double2 *M = chain_M(w, c, q.cur);
+    const double *Xr = w.X + (long long)c * 2 * kPanel * bsp, *Xi = Xr + (long long)kPanel * bsp;
+    const double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
+    const int *ppos = w.ppos + (long long)c * bsp;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, qq = lane & 15;
+    const int rw = i0 + 32 * (wv & 1), cw = j0 + 32 * (wv >> 1);
+    const int arow = 4 * (qq & 3) + (qq >> 2);  // matrix row of this lane's A operand
+    dbl4 re[2][2], im[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int j = cw + 16 * bj + qq;
+            const bool keep = j < bs && !(j >= k0 && j < k0 + bw);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = rw + 16 * bi + 4 * g + r;
+                const double2 v = (keep && i < bs) ? M[(long long)j * bs + i] : make_double2(0, 0);
+                re[bi][bj][r] = v.x;
+                im[bi][bj][r] = v.y;
+            }
+        }
+    const int kend = (bw + 3) & ~3;
+    for (int t0 = 0; t0 < kend; t0 += 4) {
+        const long long ko = (long long)(t0 + g) * bsp;
+        double xr[2], xi[2], yr[2], yi[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            xr[b] = Xr[ko + rw + 16 * b + arow];
+            xi[b] = Xi[ko + rw + 16 * b + arow];
+            yr[b] = Yr[ko + cw + 16 * b + qq];
+            yi[b] = Yi[ko + cw + 16 * b + qq];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[bi], yr[bj], re[bi][bj], 0, 0, 0);
+                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[bi], yi[bj], im[bi][bj], 0, 0, 0);
+            }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi[bi], yi[bj], re[bi][bj], 0, 0, 0);
+                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[bi], yr[bj], im[bi][bj], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int j = cw + 16 * bj + qq;
+            if (j >= bs) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = rw + 16 * bi + 4 * g + r;
+                if (i >= bs) continue;
+                const int pr = ppos[i];
+                double2 v = make_double2(re[bi][bj][r], im[bi][bj][r]);
+                if (pr >= k0 && pr < k0 + bw) {
+                    const long long yo = (long long)(pr - k0) * bsp + j;
+                    v = make_double2(Yr[yo], Yi[yo]);
                 }
+                M[(long long)j * bs + i] = v;
             }
         }
-        __syncthreads();
-    }
-    // undo the row interchanges: swap columns in reverse order
-    for (int k = bs - 1; k >= 0; --k) {
-        int p = perm[k];
-        if (p != k)
-            for (int i = threadIdx.x; i < bs; i += kFThreads) {
-                double2 t = M[(long long)k * bs + i];
-                M[(long long)k * bs + i] = M[(long long)p * bs + i];
-                M[(long long)p * bs + i] = t;
-            }
-        __syncthreads();
-    }
-    return status;
 }
 
-// M = D_l - c1 * A1 - c2 * A2 (A1 / A2 may be null), in place over A1 == M
-__device__ void form_block(const SubDesc &s, const Coef *__restrict__ coef, const double *__restrict__ k2,
-                           const FactArgs &A, int l, double2 *__restrict__ M, double2 c1, const double2 *A1,
-                           double2 c2, const double2 *A2) {
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int bs = s.bs;
-    Coef cl = coef[s.coff[A.dim - 1] + l];
-    for (int j = ty; j < bs; j += kFWaves)
-        for (int i = tx; i < bs; i += 64) {
-            long long o = (long long)j * bs + i;
-            double2 v = block_entry(s, coef, k2, A, l, i, j, cl);
-            if (A1) v = csub(v, cmul(c1, A1[o]));
-            if (A2) v = csub(v, cmul(c2, A2[o]));
-            M[o] = v;
-        }
-    __syncthreads();
-}
-
+// Store the inverse of the chain's block, W_l(i, j) = N(piv[i], ppos[j]), and
+// form the chain's next Schur complement in the other buffer (the inverse
+// itself after the chain's last block, for the middle block).
 template <typename T2>
-__device__ void store_block(const SubDesc &s, int l, const double2 *__restrict__ M, T2 *__restrict__ W) {
-    const int bs = s.bs;
-    T2 *Wl = W + s.foff + (long long)l * bs * bs;
-    for (long long o = threadIdx.x; o < (long long)bs * bs; o += kFThreads) Wl[o] = from_d2<T2>(M[o]);
-    __syncthreads();
-}
-
-// Chains of the block elimination.  Block l couples to l-1 through
-// C_l = cm(l) I and to l+1 through B_l = cp(l) I (1D coefficients of the last
-// axis).  Chain 0 eliminates from the first block:
-//     S_0 = D_0,  S_l = D_l - cm(l) cp(l-1) S_{l-1}^{-1},  l < mid;
-// chain 1 from the last block:
-//     T_{nb-1} = D_{nb-1},  T_l = D_l - cp(l) cm(l+1) T_{l+1}^{-1},  l > mid.
-// Each chain keeps its last inverse in FP64 scratch for the middle block.
-template <typename T2>
-__global__ __launch_bounds__(kFThreads) void k_factor_chain(const SubDesc *__restrict__ subs,
+__global__ __launch_bounds__(kEThreads) void k_factor_store(const SubDesc *__restrict__ subs,
                                                             const Coef *__restrict__ coef,
-                                                            const double *__restrict__ k2, FactArgs A,
-                                                            double2 *__restrict__ scratch, long long sstride,
-                                                            T2 *__restrict__ W, int *__restrict__ flags) {
-    extern __shared__ double2 lds[];
-    double2 *rowk = lds, *rs = lds + A.bs_max, *colk = lds + 2 * A.bs_max;
-    int *perm = (int *)(lds + 3 * A.bs_max);
-    __shared__ double sv[kFWaves];
-    __shared__ int si[kFWaves];
-    const int a = blockIdx.x >> 1, chain = blockIdx.x & 1;
-    const SubDesc &s = subs[a];
-    const int bs = s.bs, nb = s.nb, mid = s.mid, ax = A.dim - 1;
-    double2 *M = scratch + (long long)blockIdx.x * sstride;
-    int status = 0;
-    if (chain == 0) {
-        for (int l = 0; l < mid; ++l) {
-            double2 c = l > 0 ? cmul(coef[s.coff[ax] + l].cm, coef[s.coff[ax] + l - 1].cp) : make_double2(0, 0);
-            form_block(s, coef, k2, A, l, M, c, l > 0 ? M : nullptr, c, nullptr);
-            int st = gj_invert(M, bs, rowk, rs, colk, perm, sv, si);
-            if (st && !status) status = 1 + l * bs + (st - 1);
-            store_block<T2>(s, l, M, W);
-        }
-    } else {
-        for (int l = nb - 1; l > mid; --l) {
-            double2 c = l < nb - 1 ? cmul(coef[s.coff[ax] + l].cp, coef[s.coff[ax] + l + 1].cm) : make_double2(0, 0);
-            form_block(s, coef, k2, A, l, M, c, l < nb - 1 ? M : nullptr, c, nullptr);
-            int st = gj_invert(M, bs, rowk, rs, colk, perm, sv, si);
-            if (st && !status) status = 1 + l * bs + (st - 1);
-            store_block<T2>(s, l, M, W);
-        }
+                                                            const double *__restrict__ k2, FactArgs A, FactWs w,
+                                                            int s, int mid, int groups, T2 *__restrict__ W) {
+    const int c = blockIdx.x / groups, grp = blockIdx.x % groups;
+    const ChainPos q = chain_pos(subs, c, s, mid != 0);
+    if (!q.active) return;
+    const SubDesc &sd = subs[q.a];
+    const int bs = q.bs, ax = A.dim - 1;
+    const double2 *N = chain_M(w, c, q.cur);
+    double2 *Mn = chain_M(w, c, q.cur ^ 1);
+    const int *ppos = w.ppos + (long long)c * w.bsp, *piv = w.piv + (long long)c * w.bsp;
+    T2 *Wl = W + sd.foff + (long long)q.l * bs * bs;
+    const bool next = !mid && !q.last;
+    const int ln = q.dir == 0 ? q.l + 1 : q.l - 1;
+    Coef cln = coef[sd.coff[ax] + (next ? ln : q.l)];
+    double2 cc = make_double2(0, 0);
+    if (next) cc = q.dir == 0 ? cmul(cln.cm, coef[sd.coff[ax] + q.l].cp) : cmul(cln.cp, coef[sd.coff[ax] + q.l].cm);
+    const long long n2 = (long long)bs * bs;
+    for (long long e = (long long)grp * kEThreads + threadIdx.x; e < n2; e += (long long)groups * kEThreads) {
+        const int i = (int)(e % bs), j = (int)(e / bs);
+        const double2 v = N[(long long)ppos[j] * bs + piv[i]];
+        Wl[e] = from_d2<T2>(v);
+        if (!mid) Mn[e] = next ? csub(block_entry(sd, coef, k2, A, ln, i, j, cln), cmul(cc, v)) : v;
     }
-    if (threadIdx.x == 0) flags[blockIdx.x] = status;
 }
 
-// Middle block: Z = D_mid - cm(mid) cp(mid-1) S_{mid-1}^{-1} - cp(mid) cm(mid+1) T_{mid+1}^{-1}
-template <typename T2>
-__global__ __launch_bounds__(kFThreads) void k_factor_mid(const SubDesc *__restrict__ subs,
-                                                          const Coef *__restrict__ coef,
-                                                          const double *__restrict__ k2, FactArgs A,
-                                                          double2 *__restrict__ scratch, long long sstride,
-                                                          T2 *__restrict__ W, int *__restrict__ flags) {
-    extern __shared__ double2 lds[];
-    double2 *rowk = lds, *rs = lds + A.bs_max, *colk = lds + 2 * A.bs_max;
-    int *perm = (int *)(lds + 3 * A.bs_max);
-    __shared__ double sv[kFWaves];
-    __shared__ int si[kFWaves];
-    const int a = blockIdx.x;
-    const SubDesc &s = subs[a];
-    const int bs = s.bs, nb = s.nb, l = s.mid, ax = A.dim - 1;
-    double2 *Mtop = scratch + (long long)(2 * a) * sstride;
-    double2 *Mbot = scratch + (long long)(2 * a + 1) * sstride;
-    double2 c1 = l > 0 ? cmul(coef[s.coff[ax] + l].cm, coef[s.coff[ax] + l - 1].cp) : make_double2(0, 0);
-    double2 c2 = l < nb - 1 ? cmul(coef[s.coff[ax] + l].cp, coef[s.coff[ax] + l + 1].cm) : make_double2(0, 0);
-    form_block(s, coef, k2, A, l, Mtop, c1, l > 0 ? Mtop : nullptr, c2, l < nb - 1 ? Mbot : nullptr);
-    int st = gj_invert(Mtop, bs, rowk, rs, colk, perm, sv, si);
-    store_block<T2>(s, l, Mtop, W);
-    if (threadIdx.x == 0) flags[2 * A.nsub + a] = st ? 1 + l * bs + (st - 1) : 0;
+static int groups_for(long long n2) {
+    long long g = (n2 + kEThreads - 1) / kEThreads;
+    return (int)(g < kEGroups ? g : kEGroups);
 }
 
 template <typename T>
-hipError_t launch_factor(ddm_handle *h) {
+hipError_t launch_factor(ddm_handle *h, void *ws_base) {
     const Plan &P = h->plan;
     FactArgs A;
     A.dim = P.dim;
@@ -282,16 +496,48 @@ hipError_t launch_factor(ddm_handle *h) {
     A.glo0 = P.glo[0]; A.glo1 = P.glo[1]; A.glo2 = P.glo[2];
     A.bs_max = P.bs_max;
     A.nsub = P.nsub;
-    size_t lds = (size_t)P.bs_max * (3 * sizeof(double2) + sizeof(int));
-    long long sstride = (long long)P.bs_max * P.bs_max;
-    k_factor_chain<T><<<2 * P.nsub, kFThreads, lds, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, h->d_scratch,
-                                                                 sstride, (T *)h->d_W, h->d_flags);
-    k_factor_mid<T><<<P.nsub, kFThreads, lds, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, h->d_scratch, sstride,
-                                                           (T *)h->d_W, h->d_flags);
-    return hipGetLastError();
+    const FactWs w = carve_ws(P, ws_base);
+    const int nc = 2 * P.nsub;
+    const int groups = groups_for((long long)P.bs_max * P.bs_max);
+    const int npan = (P.bs_max + kPanel - 1) / kPanel;
+    const int tpd = w.bsp / kUTile;
+    int maxlen = 0;
+    for (const SubDesc &sd : P.subs) {
+        maxlen = std::max(maxlen, sd.mid);
+        maxlen = std::max(maxlen, sd.nb - 1 - sd.mid);
+    }
+    size_t lds = (size_t)kPanel * kPanel * sizeof(double2) + kPanel * sizeof(double2) + kPanel * sizeof(int) +
+                 (size_t)w.bsp * sizeof(int);
+    lds = (lds + 15) & ~(size_t)15;
+    const size_t lds_pw = lds + (size_t)kPanel * w.bsp * sizeof(double2);
+    const int pw_in_lds = lds_pw <= 150 * 1024;
+    if (pw_in_lds) lds = lds_pw;
+    hipError_t e = hipFuncSetAttribute((const void *)k_factor_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    e = launch_fill_zero(h->d_flags, (long long)3 * P.nsub * sizeof(int), h->stream);
+    if (e != hipSuccess) return e;
+    k_factor_form0<<<nc * groups, kEThreads, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, w, groups);
+    for (int s = 0; s <= maxlen; ++s) {
+        const int mid = s == maxlen;  // the last round inverts the middle blocks
+        if (mid)
+            k_factor_formmid<<<P.nsub * groups, kEThreads, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, w,
+                                                                          groups);
+        const int ss = mid ? 0 : s;
+        for (int p = 0; p < npan; ++p) {
+            k_factor_panel<<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, pw_in_lds, h->d_flags,
+                                                              P.nsub);
+            k_factor_update<<<nc * tpd * tpd, kUThreads, 0, h->stream>>>(h->d_subs, w, ss, p, mid, tpd);
+        }
+        k_factor_store<T><<<nc * groups, kEThreads, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, w, ss, mid,
+                                                                    groups, (T *)h->d_W);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-template hipError_t launch_factor<double2>(ddm_handle *);
-template hipError_t launch_factor<float2>(ddm_handle *);
+template hipError_t launch_factor<double2>(ddm_handle *, void *);
+template hipError_t launch_factor<float2>(ddm_handle *, void *);
 
 }  // namespace ddm

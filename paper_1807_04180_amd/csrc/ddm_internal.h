@@ -90,7 +90,7 @@ struct ddm_handle {
     ddm::SolveItem *d_items = nullptr;
     // factors: complex128 (FP64) or complex64 (MIXED), column-major blocks
     void *d_W = nullptr;
-    double2 *d_scratch = nullptr;   // per-subdomain FP64 block during factorisation
+    void *d_scratch = nullptr;      // factorisation workspace (freed after ddm_factor)
     int *d_flags = nullptr;         // per-subdomain status flags
     // step workspaces, element type T (double2 or float2), nrhs_max * etot each
     void *d_g = nullptr;
@@ -162,7 +162,9 @@ hipError_t launch_assemble(ddm_handle *h, const TIN *U, double2 *u, int nrhs, bo
                            const int *d_active);
 
 template <typename T>
-hipError_t launch_factor(ddm_handle *h);
+hipError_t launch_factor(ddm_handle *h, void *ws);
+// device workspace of the factorisation (allocated for ddm_factor only)
+size_t factor_ws_bytes(const Plan &P);
 template <typename T>
 hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs);
 
