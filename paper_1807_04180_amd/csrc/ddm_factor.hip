@@ -135,7 +135,7 @@ struct FactWs {
     double *X, *Y;      // [chain][re, im][kPanel][bsp] panel operands
     double2 *Pw;        // [chain][kPanel][bsp] panel work (when not in LDS)
     int *ppos, *piv;    // [chain][bsp] pivot step of a row / row of a pivot step
-    double *mx;         // [chain] max |S_l|^2 of the block being inverted
+    unsigned long long *mxb;  // [chain][buffer] max |entry|^2 of a block buffer (FP64 bits)
     long long mstride;  // bs_max^2
     int bsp;            // bs_max rounded up to kUTile
 };
@@ -146,7 +146,7 @@ size_t factor_ws_bytes(const Plan &P) {
     size_t b = nc * 2 * (size_t)P.bs_max * P.bs_max * sizeof(double2);
     b += nc * 4 * kPanel * bsp * sizeof(double);
     b += nc * kPanel * bsp * sizeof(double2);
-    b += nc * 2 * bsp * sizeof(int) + nc * sizeof(double);
+    b += nc * 2 * bsp * sizeof(int) + nc * 2 * sizeof(double);
     return b + 4096;
 }
 
@@ -163,7 +163,7 @@ static FactWs carve_ws(const Plan &P, void *base) {
     w.ppos = (int *)p;   p += nc * w.bsp * sizeof(int);
     w.piv = (int *)p;    p += nc * w.bsp * sizeof(int);
     p = (char *)(((uintptr_t)p + 15) & ~(uintptr_t)15);
-    w.mx = (double *)p;
+    w.mxb = (unsigned long long *)p;
     return w;
 }
 
@@ -202,6 +202,18 @@ __device__ inline double2 *chain_M(const FactWs &w, int c, int buf) {
     return w.M + ((long long)c * 2 + buf) * w.mstride;
 }
 
+// fold a workgroup's max |entry|^2 into a buffer's slot (non-negative
+// doubles order like their bit patterns)
+__device__ inline void slot_max(unsigned long long *slot, double v) {
+    __shared__ double sv[kEThreads / 64];
+    v = block_max_n<kEThreads / 64>(v, sv);
+    if (threadIdx.x == 0) atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline double slot_read(const unsigned long long *slot) {
+    return __longlong_as_double((long long)*slot);
+}
+
 // First block of every chain: M[c][0] = D_first.
 __global__ __launch_bounds__(kEThreads) void k_factor_form0(const SubDesc *__restrict__ subs,
                                                             const Coef *__restrict__ coef,
@@ -214,10 +226,14 @@ __global__ __launch_bounds__(kEThreads) void k_factor_form0(const SubDesc *__res
     const Coef cl = coef[s.coff[A.dim - 1] + q.l];
     double2 *M = chain_M(w, c, 0);
     const long long n2 = (long long)q.bs * q.bs;
+    double m = 0.0;
     for (long long e = (long long)grp * kEThreads + threadIdx.x; e < n2; e += (long long)groups * kEThreads) {
         const int i = (int)(e % q.bs), j = (int)(e / q.bs);
-        M[e] = block_entry(s, coef, k2, A, q.l, i, j, cl);
+        const double2 v = block_entry(s, coef, k2, A, q.l, i, j, cl);
+        M[e] = v;
+        m = fmax(m, cabs2(v));
     }
+    slot_max(w.mxb + 2 * c, m);
 }
 
 // Middle block of every subdomain:
@@ -238,20 +254,24 @@ __global__ __launch_bounds__(kEThreads) void k_factor_formmid(const SubDesc *__r
     const double2 *I1 = len1 > 0 ? chain_M(w, 2 * a + 1, len1 & 1) : nullptr;
     double2 *Z = chain_M(w, 2 * a, (len0 & 1) ^ 1);
     const long long n2 = (long long)bs * bs;
+    double m = 0.0;
     for (long long e = (long long)grp * kEThreads + threadIdx.x; e < n2; e += (long long)groups * kEThreads) {
         const int i = (int)(e % bs), j = (int)(e / bs);
         double2 v = block_entry(s, coef, k2, A, l, i, j, cl);
         if (I0) v = csub(v, cmul(c1, I0[e]));
         if (I1) v = csub(v, cmul(c2, I1[e]));
         Z[e] = v;
+        m = fmax(m, cabs2(v));
     }
+    slot_max(w.mxb + 2 * (2 * a) + ((len0 & 1) ^ 1), m);
 }
 
 // Panel kernel: pivots, A11^{-1}, X and Y of panel p (columns k0 .. k0+bw-1)
-// of the block chain c is inverting.
+// of the block chain c is inverting; the eliminated copy of the panel lives
+// in LDS (PW_LDS) or in the chain's workspace (blocks of thousands of rows).
+template <bool PW_LDS>
 __global__ __launch_bounds__(kPThreads) void k_factor_panel(const SubDesc *__restrict__ subs, FactWs w, int s, int p,
-                                                            int mid, int pw_in_lds, int *__restrict__ flags,
-                                                            int nsub) {
+                                                            int mid, int *__restrict__ flags, int nsub) {
     extern __shared__ double2 lds[];
     __shared__ double sv[kPWaves];
     __shared__ int si[kPWaves];
@@ -269,18 +289,16 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel(const SubDesc *__res
     double2 *rowr = Ainv + kPanel * kPanel;   // [kPanel]
     int *R1 = (int *)(rowr + kPanel);         // [kPanel]
     int *ppos_s = R1 + kPanel;                // [bsp]
-    double2 *Pw = pw_in_lds ? (double2 *)(ppos_s + bsp) : w.Pw + (long long)c * kPanel * bsp;
+    double2 *Pw;
+    if constexpr (PW_LDS) Pw = (double2 *)(ppos_s + bsp);
+    else Pw = w.Pw + (long long)c * kPanel * bsp;
     const int tid = threadIdx.x;
-    double mx;
+    const double mx = slot_read(w.mxb + 2 * c + q.cur);
     if (p == 0) {
         for (int i = tid; i < bsp; i += kPThreads) ppos_s[i] = -1;
-        double m = 0.0;
-        for (long long e = tid; e < (long long)bs * bs; e += kPThreads) m = fmax(m, cabs2(M[e]));
-        mx = block_max_n<kPWaves>(m, sv);
-        if (tid == 0) w.mx[c] = mx;
+        if (tid == 0) w.mxb[2 * c + (q.cur ^ 1)] = 0ull;  // the store of this step fills it
     } else {
         for (int i = tid; i < bsp; i += kPThreads) ppos_s[i] = ppos[i];
-        mx = w.mx[c];
     }
     // working copy of the panel; X = -panel
     for (int e = tid; e < kPanel * bsp; e += kPThreads) {
@@ -358,6 +376,164 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel(const SubDesc *__res
     }
     for (int i = tid; i < bsp; i += kPThreads) ppos[i] = ppos_s[i];
     if (tid < bw) piv[k0 + tid] = R1[tid];
+    if (tid == 0 && status) {
+        int *f = flags + (mid ? 2 * nsub + q.a : c);
+        if (*f == 0) *f = status;
+    }
+}
+
+// Pivot key of a candidate row: |value|^2 rounded to float, the low 10 bits
+// replaced by 1023 - row (ties and near-ties, to 1e-4 relative, go to the
+// smaller row); non-candidates have key 0.
+__device__ inline unsigned pivot_key(double v2, int row) {
+    return (__float_as_uint((float)v2) & ~1023u) | (unsigned)(1023 - row);
+}
+
+// Max of a 32-bit value over the wave (DPP within rows of 16 lanes, then the
+// four row results), returned to every lane.
+__device__ inline unsigned wave_max_u32(unsigned v) {
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x124, 0xF, 0xF, false));  // row_ror 4
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x128, 0xF, 0xF, false));  // row_ror 8
+    const unsigned r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const unsigned r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
+
+// Panel kernel for blocks of at most NT rows: thread i keeps row i of the
+// panel in registers through the elimination.  Per column: a wave-level max
+// of the candidates' pivot keys, each wave's best row staged in LDS, one
+// barrier, then every thread takes the best of the waves' candidates.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_factor_panel_r(const SubDesc *__restrict__ subs, FactWs w, int s, int p,
+                                                       int mid, int *__restrict__ flags, int nsub) {
+    static_assert(NT <= 512, "pivot keys hold row indices below 1024");
+    constexpr int NW = NT / 64;
+    __shared__ double2 Ainv[kPanel * kPanel];
+    __shared__ double2 rowc[2][NW][kPanel];
+    __shared__ unsigned wkey[2][NW];
+    __shared__ int R1[kPanel];
+    const int c = blockIdx.x;
+    const ChainPos q = chain_pos(subs, c, s, mid != 0);
+    if (!q.active) return;
+    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
+    if (k0 >= bs) return;
+    const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
+    const double2 *M = chain_M(w, c, q.cur);
+    double *Xr = w.X + (long long)c * 2 * kPanel * bsp, *Xi = Xr + (long long)kPanel * bsp;
+    double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
+    int *ppos = w.ppos + (long long)c * bsp, *piv = w.piv + (long long)c * bsp;
+    const int tid = threadIdx.x;
+    const bool own = tid < bs;
+    int myp = (p > 0 && own) ? ppos[tid] : -1;
+    const double mx = slot_read(w.mxb + 2 * c + q.cur);
+    if (p == 0 && tid == 0) w.mxb[2 * c + (q.cur ^ 1)] = 0ull;  // the store of this step fills it
+    for (int e = tid; e < kPanel * kPanel; e += NT) Ainv[e] = make_double2(0, 0);
+    const int wv = tid >> 6;
+    // branch-free loads (clamped in-bounds addresses, then zeroed) so that all
+    // of them are in flight together
+    double2 pr[kPanel];
+    const int rowc_ = own ? tid : bs - 1;
+#pragma unroll
+    for (int u = 0; u < kPanel; ++u) {
+        const double2 v = M[(long long)(k0 + (u < bw ? u : bw - 1)) * bs + rowc_];
+        pr[u] = (own && u < bw) ? v : make_double2(0, 0);
+    }
+    if (tid < bsp) {
+#pragma unroll
+        for (int u = 0; u < kPanel; ++u) {
+            Xr[(long long)u * bsp + tid] = -pr[u].x;
+            Xi[(long long)u * bsp + tid] = -pr[u].y;
+        }
+    }
+    double tiny2 = (double)bs * DBL_EPSILON;
+    tiny2 = tiny2 * tiny2 * mx;
+    int status = 0;
+    __syncthreads();
+    // fully unrolled: the row stays in registers (static indices)
+#pragma clang loop unroll(full)
+    for (int t = 0; t < kPanel; ++t) {
+        if (t < bw) {
+            const int b = t & 1;
+            const unsigned key = (own && myp < 0) ? pivot_key(cabs2(pr[t]), tid) : 0u;
+            const unsigned wmax = wave_max_u32(key);
+            if (key != 0u && key == wmax) {  // keys are unique: one lane per wave
+#pragma unroll
+                for (int u = 0; u < kPanel; ++u) rowc[b][wv][u] = pr[u];
+            }
+            if ((tid & 63) == 0) wkey[b][wv] = wmax;
+            __syncthreads();  // rowc / wkey[b] are next written two columns later
+            unsigned best = wkey[b][0];
+            int wb = 0;
+#pragma unroll
+            for (int k = 1; k < NW; ++k)
+                if (wkey[b][k] > best) { best = wkey[b][k]; wb = k; }
+            int r = 1023 - (int)(best & 1023u);
+            r = r < 0 ? 0 : (r >= bs ? bs - 1 : r);
+            if (tid == r) {
+                myp = k0 + t;
+                R1[t] = r;
+            }
+            const double2 *rowr = rowc[b][wb];
+            const double2 piv_v = rowr[t];
+            if (!(cabs2(piv_v) > tiny2) && status == 0) status = 1 + q.l * bs + k0 + t;
+            const double rd = 1.0 / cabs2(piv_v);
+            const double2 inv = make_double2(piv_v.x * rd, -piv_v.y * rd);
+            if (tid == r) {
+#pragma unroll
+                for (int u = 0; u < kPanel; ++u) pr[u] = u == t ? inv : cmul(rowr[u], inv);
+            } else {
+                const double2 f = cmul(pr[t], inv);
+#pragma unroll
+                for (int u = 0; u < kPanel; ++u)
+                    if (u != t) pr[u] = csub(pr[u], cmul(f, rowr[u]));
+                pr[t] = make_double2(-f.x, -f.y);
+            }
+        }
+    }
+    __syncthreads();  // R1 complete
+    // pivot rows of this panel: rows of A11^{-1}; they take no part in X
+    if (own && myp >= k0 && myp < k0 + bw) {
+#pragma unroll
+        for (int u = 0; u < kPanel; ++u) {
+            Ainv[(myp - k0) * kPanel + u] = pr[u];
+            Xr[(long long)u * bsp + tid] = 0.0;
+            Xi[(long long)u * bsp + tid] = 0.0;
+        }
+    }
+    if (own) ppos[tid] = myp;
+    __syncthreads();
+    if (tid < bw) piv[k0 + tid] = R1[tid];
+    // Y = A11^{-1} [pivot rows of S], with A11^{-1} itself in the panel
+    // columns; H thread groups split the kPanel rows of Y
+    int H = 1;
+    while (2 * H * bsp <= NT && 2 * H <= kPanel) H *= 2;
+    const int j = tid % bsp, h = tid / bsp, th = kPanel / H;
+    if (h < H) {
+        double2 g[kPanel];
+        const int jc = j < bs ? j : bs - 1;
+#pragma unroll
+        for (int u = 0; u < kPanel; ++u) {
+            const int ru = R1[u < bw ? u : bw - 1];
+            const double2 v = M[(long long)jc * bs + ru];
+            g[u] = (u < bw && j < bs) ? v : make_double2(0, 0);
+        }
+        const bool inpanel = j >= k0 && j < k0 + bw;
+        for (int t = h * th; t < (h + 1) * th; ++t) {
+            double2 y = make_double2(0, 0);
+            if (j < bs) {
+                if (inpanel) {
+                    y = Ainv[t * kPanel + (j - k0)];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kPanel; ++u) cfma(y, Ainv[t * kPanel + u], g[u]);
+                }
+            }
+            Yr[(long long)t * bsp + j] = y.x;
+            Yi[(long long)t * bsp + j] = y.y;
+        }
+    }
     if (tid == 0 && status) {
         int *f = flags + (mid ? 2 * nsub + q.a : c);
         if (*f == 0) *f = status;
@@ -474,11 +650,21 @@ __global__ __launch_bounds__(kEThreads) void k_factor_store(const SubDesc *__res
     double2 cc = make_double2(0, 0);
     if (next) cc = q.dir == 0 ? cmul(cln.cm, coef[sd.coff[ax] + q.l].cp) : cmul(cln.cp, coef[sd.coff[ax] + q.l].cm);
     const long long n2 = (long long)bs * bs;
+    double m = 0.0;
     for (long long e = (long long)grp * kEThreads + threadIdx.x; e < n2; e += (long long)groups * kEThreads) {
         const int i = (int)(e % bs), j = (int)(e / bs);
         const double2 v = N[(long long)ppos[j] * bs + piv[i]];
         Wl[e] = from_d2<T2>(v);
-        if (!mid) Mn[e] = next ? csub(block_entry(sd, coef, k2, A, ln, i, j, cln), cmul(cc, v)) : v;
+        if (!mid) {
+            const double2 mv = next ? csub(block_entry(sd, coef, k2, A, ln, i, j, cln), cmul(cc, v)) : v;
+            Mn[e] = mv;
+            m = fmax(m, cabs2(mv));
+        }
+    }
+    if (!mid) {
+        slot_max(w.mxb + 2 * c + (q.cur ^ 1), m);
+        // the middle block of this subdomain is formed in this buffer next
+        if (q.last && q.dir == 0 && grp == 0 && threadIdx.x == 0) w.mxb[2 * c + q.cur] = 0ull;
     }
 }
 
@@ -506,14 +692,19 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
         maxlen = std::max(maxlen, sd.mid);
         maxlen = std::max(maxlen, sd.nb - 1 - sd.mid);
     }
+    // panel kernel: registers for blocks of at most kPThreads rows, else
+    // the generic kernel with its working panel in LDS when it fits
+    const int panel_kind = P.bs_max <= 256 ? 0 : (P.bs_max <= 512 ? 1 : 2);
     size_t lds = (size_t)kPanel * kPanel * sizeof(double2) + kPanel * sizeof(double2) + kPanel * sizeof(int) +
                  (size_t)w.bsp * sizeof(int);
     lds = (lds + 15) & ~(size_t)15;
     const size_t lds_pw = lds + (size_t)kPanel * w.bsp * sizeof(double2);
-    const int pw_in_lds = lds_pw <= 150 * 1024;
+    const bool pw_in_lds = lds_pw <= 150 * 1024;
     if (pw_in_lds) lds = lds_pw;
-    hipError_t e = hipFuncSetAttribute((const void *)k_factor_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    hipError_t e = hipFuncSetAttribute(pw_in_lds ? (const void *)k_factor_panel<true> : (const void *)k_factor_panel<false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    e = launch_fill_zero(w.mxb, (long long)2 * nc * sizeof(unsigned long long), h->stream);
     if (e != hipSuccess) return e;
     e = launch_fill_zero(h->d_flags, (long long)3 * P.nsub * sizeof(int), h->stream);
     if (e != hipSuccess) return e;
@@ -525,8 +716,15 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
                                                                           groups);
         const int ss = mid ? 0 : s;
         for (int p = 0; p < npan; ++p) {
-            k_factor_panel<<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, pw_in_lds, h->d_flags,
-                                                              P.nsub);
+            if (panel_kind == 0)
+                k_factor_panel_r<256><<<nc, 256, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
+            else if (panel_kind == 1)
+                k_factor_panel_r<512><<<nc, 512, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
+            else if (pw_in_lds)
+                k_factor_panel<true><<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
+            else
+                k_factor_panel<false><<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags,
+                                                                         P.nsub);
             k_factor_update<<<nc * tpd * tpd, kUThreads, 0, h->stream>>>(h->d_subs, w, ss, p, mid, tpd);
         }
         k_factor_store<T><<<nc * groups, kEThreads, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, w, ss, mid,

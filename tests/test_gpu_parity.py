@@ -308,6 +308,20 @@ def test_3d_large_planes_perline():
     g.close()
 
 
+def test_3d_planes_above_512():
+    """Plane blocks of 576 unknowns: the factorisation's panel elimination
+    runs from the workspace instead of registers or LDS; FP64 and mixed
+    local solves vs oracle."""
+    w = di.small_3d(M=34, N=(2, 2, 2), n_pml=3, n_ov=2, nrhs=2, seed=5)
+    o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
+    gin = di.random_field((2, o.etot), seed=81)
+    xo = o.local_solve(gin)
+    for mixed, tol in ((False, 1e-10), (True, 5e-5)):
+        g = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=mixed), _t(w.k2.reshape(-1)), 2)
+        assert relerr(_n(g.local_solve(_t(gin))), xo, axis=1) < tol, mixed
+        g.close()
+
+
 @pytest.mark.parametrize("case,mixed", [("2d-3x3-layered", False), ("2d-3x3-layered", True), ("3d-2x2x2", False)])
 def test_step_graph_replays_match_eager(case, mixed):
     """The stationary solve replays captured step graphs (one per ring
