@@ -213,6 +213,73 @@ def config3(nrhs: int = 16, M: int = 2048, N: int = 16) -> Workload:
                     k2, f, c_min=float(c.min()), c_max=float(c.max()))
 
 
+def _gaussian_2d_window(M: int, n_pml: int, h: float, centre, s: float, width: float = 12.0) -> np.ndarray:
+    """The unit-mass 2D Gaussian of gaussian_source for a centre well inside
+    the physical square, evaluated only within `width` standard deviations of
+    the centre (outside, its value is below exp(-72) of the peak and is set to
+    zero)."""
+    n = M + 2 * n_pml - 1
+    x = node_coords(M, n_pml, h)
+    f = np.zeros((n, n), dtype=np.complex128)
+    lo = [int(np.searchsorted(x, c - width * s)) for c in centre]
+    hi = [int(np.searchsorted(x, c + width * s, side="right")) for c in centre]
+    X, Y = np.meshgrid(x[lo[0]:hi[0]], x[lo[1]:hi[1]], indexing="xy")
+    r2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2
+    f[lo[1]:hi[1], lo[0]:hi[0]] = (2 * math.pi * s * s) ** -1.0 * np.exp(-r2 / (2 * s * s))
+    return f
+
+
+@dataclasses.dataclass
+class StreamRequest:
+    """One request of the serving stream: arrival time (s), problem key
+    (grid, medium, layout) and the full problem data with its sources."""
+    rid: int
+    t_arrival: float
+    key: Tuple
+    workload: Workload
+
+
+def config4_stream(n_requests: int = 48, rate: float = 4.0, grids=(256, 512, 1024), max_rhs: int = 32,
+                   n_pml: int = 16, n_ov: int = 8, core: int = 128) -> List[StreamRequest]:
+    """Serving stream: Poisson arrivals (exponential gaps of mean 1/rate s);
+    each request draws a grid M from `grids`, a medium (constant c = 1, or the
+    grid's seeded layered medium of config 3's recipe), 1..max_rhs Gaussian
+    sources (std 2h, centres uniform in [0.1, 0.9]^2).  omega gives 10 points
+    per wavelength at the slowest velocity; the layout has cores of `core`
+    cells (2x2 for 256, 4x4 for 512, 8x8 for 1024).  Requests of the same
+    (M, medium) share the problem -- the factorisation cache key."""
+    rng = np.random.default_rng(BASE_SEED + 4)
+    media = {}
+    out = []
+    t = 0.0
+    for rid in range(n_requests):
+        t += float(rng.exponential(1.0 / rate))
+        M = int(grids[rng.integers(len(grids))])
+        kind = "layered" if rng.integers(2) else "constant"
+        key = (M, kind)
+        if key not in media:
+            L = 1.0
+            h = L / M
+            if kind == "constant":
+                c = np.ones(tuple(m + 2 * n_pml - 1 for m in (M, M)))
+            else:
+                c = layered_velocity(2, (M, M), n_pml, h, L, np.random.default_rng(BASE_SEED + 40 + M),
+                                     smooth_cells=16.0 * M / 2048)
+            c_min, c_max = float(c.min()), float(c.max())
+            omega = 2 * math.pi * c_min / (10 * h)
+            s0 = sigma0_for_reflection(1e-6, omega / c_max, n_pml * h)
+            media[key] = (L, h, omega, s0, (omega / c) ** 2, c_min, c_max)
+        L, h, omega, s0, k2, c_min, c_max = media[key]
+        nrhs = int(rng.integers(1, max_rhs + 1))
+        centres = rng.uniform(0.1, 0.9, size=(nrhs, 2))
+        f = np.stack([_gaussian_2d_window(M, n_pml, h, tuple(cc), 2 * h) for cc in centres])
+        N = max(M // core, 1)
+        w = Workload("cfg4-%d-%s" % (M, kind), 2, (M, M), L, omega, n_pml, n_ov, (N, N), s0, k2, f,
+                     c_min=c_min, c_max=c_max)
+        out.append(StreamRequest(rid, t, key + ((N, N),), w))
+    return out
+
+
 def config5(M: int = 96, N: int = 3, n_pml: int = 6, n_ov: int = 2) -> Workload:
     """3D constant medium, M = 96 (10 ppw, omega = 2 pi 9.6), PML 6, 3x3x3
     subdomains, overlap 2, Gaussian (s = 2h) at the centre."""

@@ -1,0 +1,38 @@
+"""Seeded input generators: determinism and the serving stream's recipe."""
+import numpy as np
+
+import ddm_inputs as di
+
+
+def test_gaussian_window_matches_full_evaluation():
+    M, n_pml = 256, 16
+    h = 1.0 / M
+    for c in [(0.37, 0.61), (0.1, 0.9), (0.5, 0.5)]:
+        full = di.gaussian_source(2, (M, M), n_pml, h, 1.0, c, 2 * h)
+        win = di._gaussian_2d_window(M, n_pml, h, c, 2 * h)
+        assert np.abs(full - win).max() <= 1e-25 * np.abs(full).max()
+        assert abs(full.sum().real * h * h - 1.0) < 1e-6  # unit mass
+
+
+def test_serving_stream_is_seeded_and_follows_the_recipe():
+    a = di.config4_stream(n_requests=12, rate=4.0, grids=(256, 512))
+    b = di.config4_stream(n_requests=12, rate=4.0, grids=(256, 512))
+    assert [r.key for r in a] == [r.key for r in b]
+    assert [r.t_arrival for r in a] == [r.t_arrival for r in b]
+    assert all(np.array_equal(x.workload.f, y.workload.f) for x, y in zip(a, b))
+    t = [r.t_arrival for r in a]
+    assert all(t1 > t0 for t0, t1 in zip(t, t[1:]))
+    for r in a:
+        w = r.workload
+        M, kind, N = r.key
+        assert w.M == (M, M) and w.N == N and N[0] * 128 == M
+        assert 1 <= w.nrhs <= 32
+        assert w.f.shape == (w.nrhs,) + w.grid_shape
+        # 10 points per wavelength at the slowest velocity
+        k_max = np.sqrt(w.k2.max())
+        assert abs(2 * np.pi / k_max / w.h - 10.0) < 1e-9
+    # one problem per key: requests with the same key share the medium
+    by_key = {}
+    for r in a:
+        by_key.setdefault(r.key, r.workload.k2)
+        assert by_key[r.key] is r.workload.k2
