@@ -38,21 +38,21 @@ HBM_PEAK_GBS = 8000.0
 
 
 def workloads():
-    """name -> (builder, stationary tolerance, description).  cfg2 is the
+    """name -> (builder, stationary tolerance, description).  2d-1024 is the
     default (the headline configuration); the others are measured with
     --workload and are not the bench line's `value`."""
     import ddm_inputs as di
     return {
-        "cfg2": (lambda: di.config2(nrhs=4), 1e-6,
+        "2d-1024": (lambda: di.const_2d_1024(nrhs=4), 1e-6,
                  "2D constant medium, 1024^2 interior (h=1/1024, omega=2*pi*102.4, 10 ppw), 5-point FD, PML 16 "
                  "(R=1e-6), 8x8 subdomains of 128^2 with overlap 8, 4 seeded Gaussian sources (std 2h)"),
-        "cfg1": (di.config1, 1e-8,
+        "2d-80": (di.const_2d_80, 1e-8,
                  "2D constant medium, 80^2 interior (omega=2*pi*8, 10 ppw), 5-point FD, PML 10 (R=1e-6), 2x2 "
                  "subdomains, overlap 4, one Gaussian source (std 2h) at the centre"),
-        "cfg3": (lambda: di.config3(nrhs=16), 1e-6,
+        "2d-2048-layered": (lambda: di.layered_2d_2048(nrhs=16), 1e-6,
                  "2D layered medium, 2048^2 interior (8 layers 1.5-4.5 plus 10% smoothed perturbation, 8 ppw at "
                  "c=1.5), 5-point FD, PML 20 (R=1e-6), 16x16 subdomains, overlap 8, 16 seeded Gaussian sources"),
-        "cfg5": (di.config5, 1e-6,
+        "3d-96": (di.const_3d_96, 1e-6,
                  "3D constant medium, 96^3 interior (omega=2*pi*9.6, 10 ppw), 7-point FD, PML 6 (R=1e-6), 3x3x3 "
                  "subdomains, overlap 2, plane blocks of up to 46^2, one Gaussian source (std 2h) at the centre"),
     }
@@ -71,7 +71,7 @@ def recorded_traffic(kernel_variant):
     """HBM traffic per launch of the substitution kernel from the committed
     rocprofv3 counter summary, only if the kernel source is unchanged since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_solve_chain_cfg2_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_solve_chain_2d1024_traffic.json")
     src = os.path.join(ROOT, "paper_1807_04180_amd", "csrc", "ddm_solve.hip")
     if kernel_variant != "chain" or not os.path.exists(path):
         return None
@@ -91,7 +91,7 @@ def run_cpu_baseline(nrhs_full, nsub_full, steps_full, tol):
     import ddm_inputs as di
     from oracle import Oracle
 
-    w = di.config2_cut(4, nrhs=nrhs_full)
+    w = di.const_2d_1024_cut(4, nrhs=nrhs_full)
     o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
     t0 = time.perf_counter()
     o.factor()
@@ -131,7 +131,7 @@ def run_serving(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = di.config4_stream(n_requests=args.requests, rate=args.rate)
+    stream = di.serving_stream(n_requests=args.requests, rate=args.rate)
     log("bench: serving stream of %d requests, %d right-hand sides, %d problem keys, last arrival %.2f s"
         % (len(stream), sum(r.workload.nrhs for r in stream), len(set(r.key for r in stream)),
            stream[-1].t_arrival))
@@ -191,14 +191,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cfg2", "cfg1", "cfg3", "cfg4", "cfg5"], default="cfg2",
-                    help="cfg2 (default): 2D 1024^2 8x8, 4 RHS; cfg1: 2D 80^2 2x2; cfg3: 2D layered 2048^2 "
-                         "16x16, 16 RHS; cfg4: serving stream; cfg5: 3D 96^3 3x3x3")
-    ap.add_argument("--requests", type=int, default=48, help="cfg4: requests in the stream")
-    ap.add_argument("--rate", type=float, default=4.0, help="cfg4: mean arrival rate (1/s)")
-    ap.add_argument("--budget-gb", type=float, default=32.0, help="cfg4: HBM budget for cached problems (GiB)")
-    ap.add_argument("--poll-steps", type=int, default=2, help="cfg4: DDM steps enqueued per handle between polls")
-    ap.add_argument("--slots", type=int, default=16, help="cfg4: RHS slots per cached problem")
+    ap.add_argument("--workload", choices=["2d-1024", "2d-80", "2d-2048-layered", "serve", "3d-96"], default="2d-1024",
+                    help="2d-1024 (default): 2D 1024^2 8x8, 4 RHS; 2d-80: 2D 80^2 2x2; 2d-2048-layered: 2D layered "
+                         "2048^2 16x16, 16 RHS; serve: serving stream; 3d-96: 3D 96^3 3x3x3")
+    ap.add_argument("--requests", type=int, default=48, help="serve: requests in the stream")
+    ap.add_argument("--rate", type=float, default=4.0, help="serve: mean arrival rate (1/s)")
+    ap.add_argument("--budget-gb", type=float, default=32.0, help="serve: HBM budget for cached problems (GiB)")
+    ap.add_argument("--poll-steps", type=int, default=2, help="serve: DDM steps enqueued per handle between polls")
+    ap.add_argument("--slots", type=int, default=16, help="serve: RHS slots per cached problem")
     ap.add_argument("--tol", type=float, default=None, help="stationary/FGMRES tolerance (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FGMRES and mixed-precision legs")
@@ -207,11 +207,11 @@ def main():
                          "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the DDM step has no multi-GPU path here); "
+        print("bench.py: the DDM step here runs on one GPU (there is no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "cfg4":
+    if args.workload == "serve":
         if args.tol is None:
             args.tol = 1e-6
         run_serving(args)
@@ -228,7 +228,7 @@ def main():
     build_w, tol_w, wdesc = workloads()[args.workload]
     if args.tol is None:
         args.tol = tol_w
-    if args.workload != "cfg2":
+    if args.workload != "2d-1024":
         args.no_cpu_baseline = True  # the oracle baseline is sampled from the headline workload only
     w = build_w()
     nrhs = w.nrhs
@@ -313,7 +313,7 @@ def main():
     achieved = sub["bytes"] / (sub["ms"] * 1e-3) / 1e9 if sub["ms"] > 0 else 0.0
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": recorded_traffic(s64.solve_variant()) if args.workload == "cfg2" else None,
+                       "traffic": recorded_traffic(s64.solve_variant()) if args.workload == "2d-1024" else None,
                        "kernel": ("k_solve_chain" if s64.solve_variant() == "chain" else "k_solve_line")
                                  + " (block substitution)",
                        "avg_launch_us": avg_us, "launches": sub["launches"],

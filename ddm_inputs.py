@@ -147,10 +147,10 @@ def layered_velocity(dim: int, M, n_pml: int, h: float, L: float, rng: np.random
 
 
 # ---------------------------------------------------------------------------
-# The five benchmark configurations (seed = BASE_SEED + config index).
+# The benchmark workloads (seed = BASE_SEED + a fixed per-workload offset).
 # ---------------------------------------------------------------------------
 
-def config1() -> Workload:
+def const_2d_80() -> Workload:
     """2D constant medium, omega = 2 pi 8 (10 ppw), M = 80, PML 10 cells,
     R = 1e-6, 2x2 subdomains, overlap 4, one Gaussian (s = 2h) at the centre."""
     M, n_pml, L = 80, 10, 1.0
@@ -160,10 +160,10 @@ def config1() -> Workload:
     s0 = sigma0_for_reflection(1e-6, k, n_pml * h)
     k2 = constant_k2(2, (M, M), n_pml, k)
     f = gaussian_source(2, (M, M), n_pml, h, L, (0.5, 0.5), 2 * h)[None]
-    return Workload("cfg1-2d-80-2x2", 2, (M, M), L, omega, n_pml, 4, (2, 2), s0, k2, f)
+    return Workload("2d-const-80-2x2", 2, (M, M), L, omega, n_pml, 4, (2, 2), s0, k2, f)
 
 
-def config2(nrhs: int = 4) -> Workload:
+def const_2d_1024(nrhs: int = 4) -> Workload:
     """2D constant medium, M = 1024 (10 ppw, omega = 2 pi 102.4), PML 16,
     8x8 subdomains of 128^2, overlap 8, nrhs seeded Gaussians (s = 2h) with
     centres uniform in [0.1, 0.9]^2."""
@@ -176,14 +176,14 @@ def config2(nrhs: int = 4) -> Workload:
     rng = np.random.default_rng(BASE_SEED + 2)
     centres = rng.uniform(0.1, 0.9, size=(nrhs, 2))
     f = np.stack([gaussian_source(2, (M, M), n_pml, h, L, tuple(c), 2 * h) for c in centres])
-    return Workload("cfg2-2d-1024-8x8", 2, (M, M), L, omega, n_pml, 8, (8, 8), s0, k2, f,
+    return Workload("2d-const-1024-8x8", 2, (M, M), L, omega, n_pml, 8, (8, 8), s0, k2, f,
                     notes="centres=%s" % np.round(centres, 4).tolist())
 
 
-def config2_cut(Ncut: int = 2, nrhs: int = 4) -> Workload:
-    """A Ncut x Ncut block of the config-2 workload: same mesh size h = 1/1024,
+def const_2d_1024_cut(Ncut: int = 2, nrhs: int = 4) -> Workload:
+    """A Ncut x Ncut block of the 2D 1024^2 workload: same mesh size h = 1/1024,
     frequency, PML, overlap and 128^2 cores (M = 128 Ncut cells), nrhs seeded
-    Gaussians inside it.  Used as a bounded sample of config 2."""
+    Gaussians inside it.  Used as a bounded sample of that workload."""
     M, n_pml = 128 * Ncut, 16
     h = 1.0 / 1024
     L = M * h
@@ -194,10 +194,10 @@ def config2_cut(Ncut: int = 2, nrhs: int = 4) -> Workload:
     rng = np.random.default_rng(BASE_SEED + 20 + Ncut)
     centres = rng.uniform(0.1 * L, 0.9 * L, size=(nrhs, 2))
     f = np.stack([gaussian_source(2, (M, M), n_pml, h, L, tuple(c), 2 * h) for c in centres])
-    return Workload("cfg2-cut-%dx%d" % (Ncut, Ncut), 2, (M, M), L, omega, n_pml, 8, (Ncut, Ncut), s0, k2, f)
+    return Workload("2d-const-1024-cut-%dx%d" % (Ncut, Ncut), 2, (M, M), L, omega, n_pml, 8, (Ncut, Ncut), s0, k2, f)
 
 
-def config3(nrhs: int = 16, M: int = 2048, N: int = 16) -> Workload:
+def layered_2d_2048(nrhs: int = 16, M: int = 2048, N: int = 16) -> Workload:
     """2D layered medium (8 layers, 1.5-4.5, 10% smoothed perturbation),
     8 ppw at c = 1.5, PML 20, 16x16 subdomains, overlap 8, nrhs Gaussians."""
     n_pml, L = 20, 1.0
@@ -209,7 +209,7 @@ def config3(nrhs: int = 16, M: int = 2048, N: int = 16) -> Workload:
     s0 = sigma0_for_reflection(1e-6, omega / 4.5, n_pml * h)
     centres = rng.uniform(0.1, 0.9, size=(nrhs, 2))
     f = np.stack([gaussian_source(2, (M, M), n_pml, h, L, tuple(cc), 2 * h) for cc in centres])
-    return Workload("cfg3-2d-%d-%dx%d-layered" % (M, N, N), 2, (M, M), L, omega, n_pml, 8, (N, N), s0,
+    return Workload("2d-layered-%d-%dx%d" % (M, N, N), 2, (M, M), L, omega, n_pml, 8, (N, N), s0,
                     k2, f, c_min=float(c.min()), c_max=float(c.max()))
 
 
@@ -239,11 +239,11 @@ class StreamRequest:
     workload: Workload
 
 
-def config4_stream(n_requests: int = 48, rate: float = 4.0, grids=(256, 512, 1024), max_rhs: int = 32,
+def serving_stream(n_requests: int = 48, rate: float = 4.0, grids=(256, 512, 1024), max_rhs: int = 32,
                    n_pml: int = 16, n_ov: int = 8, core: int = 128) -> List[StreamRequest]:
     """Serving stream: Poisson arrivals (exponential gaps of mean 1/rate s);
     each request draws a grid M from `grids`, a medium (constant c = 1, or the
-    grid's seeded layered medium of config 3's recipe), 1..max_rhs Gaussian
+    grid's seeded layered medium of the 2048^2 recipe), 1..max_rhs Gaussian
     sources (std 2h, centres uniform in [0.1, 0.9]^2).  omega gives 10 points
     per wavelength at the slowest velocity; the layout has cores of `core`
     cells (2x2 for 256, 4x4 for 512, 8x8 for 1024).  Requests of the same
@@ -274,13 +274,13 @@ def config4_stream(n_requests: int = 48, rate: float = 4.0, grids=(256, 512, 102
         centres = rng.uniform(0.1, 0.9, size=(nrhs, 2))
         f = np.stack([_gaussian_2d_window(M, n_pml, h, tuple(cc), 2 * h) for cc in centres])
         N = max(M // core, 1)
-        w = Workload("cfg4-%d-%s" % (M, kind), 2, (M, M), L, omega, n_pml, n_ov, (N, N), s0, k2, f,
+        w = Workload("serve-%d-%s" % (M, kind), 2, (M, M), L, omega, n_pml, n_ov, (N, N), s0, k2, f,
                      c_min=c_min, c_max=c_max)
         out.append(StreamRequest(rid, t, key + ((N, N),), w))
     return out
 
 
-def config5(M: int = 96, N: int = 3, n_pml: int = 6, n_ov: int = 2) -> Workload:
+def const_3d_96(M: int = 96, N: int = 3, n_pml: int = 6, n_ov: int = 2) -> Workload:
     """3D constant medium, M = 96 (10 ppw, omega = 2 pi 9.6), PML 6, 3x3x3
     subdomains, overlap 2, Gaussian (s = 2h) at the centre."""
     L = 1.0
@@ -290,7 +290,7 @@ def config5(M: int = 96, N: int = 3, n_pml: int = 6, n_ov: int = 2) -> Workload:
     s0 = sigma0_for_reflection(1e-6, k, n_pml * h)
     k2 = constant_k2(3, (M, M, M), n_pml, k)
     f = gaussian_source(3, (M, M, M), n_pml, h, L, (0.5, 0.5, 0.5), 2 * h)[None]
-    return Workload("cfg5-3d-%d-%dx%dx%d" % (M, N, N, N), 3, (M, M, M), L, omega, n_pml, n_ov, (N, N, N),
+    return Workload("3d-const-%d-%dx%dx%d" % (M, N, N, N), 3, (M, M, M), L, omega, n_pml, n_ov, (N, N, N),
                     s0, k2, f)
 
 

@@ -9,7 +9,7 @@ boxes of different sizes in one launch.
 Tolerances (relative, max-abs or L2 per RHS as stated):
   operator, restriction, transfer, assembly : 1e-13 (same FP64 formula, only
       rounding order differs)
-  FP64 local solves and DDM iterates         : 1e-10 (spec bound for the
+  FP64 local solves and DDM iterates         : 1e-10 (the stated bound for the
       FP64 path; block inverses vs banded LU differ by rounding amplified by
       the local condition number)
   mixed (complex64) local solves            : 5e-5 (c64 unit roundoff 6e-8

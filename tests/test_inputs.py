@@ -15,8 +15,8 @@ def test_gaussian_window_matches_full_evaluation():
 
 
 def test_serving_stream_is_seeded_and_follows_the_recipe():
-    a = di.config4_stream(n_requests=12, rate=4.0, grids=(256, 512))
-    b = di.config4_stream(n_requests=12, rate=4.0, grids=(256, 512))
+    a = di.serving_stream(n_requests=12, rate=4.0, grids=(256, 512))
+    b = di.serving_stream(n_requests=12, rate=4.0, grids=(256, 512))
     assert [r.key for r in a] == [r.key for r in b]
     assert [r.t_arrival for r in a] == [r.t_arrival for r in b]
     assert all(np.array_equal(x.workload.f, y.workload.f) for x, y in zip(a, b))
