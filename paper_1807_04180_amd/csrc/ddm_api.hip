@@ -101,7 +101,7 @@ size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
     size_t es = elem_size(mixed);
     size_t b = 0;
     b += P.subs.size() * sizeof(SubDesc) + (P.coef.size() + P.gcoef.size()) * sizeof(Coef);
-    b += P.owner.size() * sizeof(int) + P.btab.size() * sizeof(double) + P.items.size() * sizeof(SolveItem);
+    b += P.aown.size() * sizeof(AxisOwn) + P.btab.size() * sizeof(double) + P.items.size() * sizeof(SolveItem);
     b += (size_t)P.nglob * sizeof(double);                         // k2
     b += (size_t)P.fel * es;                                       // factors
     b += factor_ws_bytes(P);                                       // factor workspace (freed after factor)
@@ -114,7 +114,7 @@ size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
 }
 
 void free_all(ddm_handle *h) {
-    void *ptrs[] = {h->d_subs, h->d_coef, h->d_gcoef, h->d_owner, h->d_btab, h->d_k2, h->d_items, h->d_W,
+    void *ptrs[] = {h->d_subs, h->d_coef, h->d_gcoef, h->d_aown, h->d_btab, h->d_k2, h->d_items, h->d_W,
                     h->d_scratch, h->d_flags, h->d_g, h->d_ring[0], h->d_ring[1], h->d_ring[2], h->d_ring[3],
                     h->d_r, h->d_wide, h->d_part, h->d_norm, h->d_active, h->d_V, h->d_Z, h->d_dots,
                     h->d_coef_y, h->d_sync};
@@ -848,7 +848,7 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         dalloc(h, &h->d_subs, P.subs.size());
         dalloc(h, &h->d_coef, P.coef.size());
         dalloc(h, &h->d_gcoef, P.gcoef.size());
-        dalloc(h, &h->d_owner, P.owner.size());
+        dalloc(h, &h->d_aown, P.aown.size());
         dalloc(h, &h->d_btab, P.btab.size());
         dalloc(h, &h->d_items, P.items.size());
         dalloc(h, &h->d_k2, (size_t)P.nglob);
@@ -856,7 +856,7 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         HIPCHK(hipMemcpy(h->d_subs, P.subs.data(), P.subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_coef, P.coef.data(), P.coef.size() * sizeof(Coef), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_gcoef, P.gcoef.data(), P.gcoef.size() * sizeof(Coef), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(h->d_owner, P.owner.data(), P.owner.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(h->d_aown, P.aown.data(), P.aown.size() * sizeof(AxisOwn), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_btab, P.btab.data(), P.btab.size() * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_items, P.items.data(), P.items.size() * sizeof(SolveItem), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_k2, hk2.data(), P.nglob * sizeof(double), hipMemcpyHostToDevice));

@@ -43,6 +43,18 @@ struct SolveItem {
     int a, r0;
 };
 
+// Per axis and global index: the (at most two) subdomain coordinates along
+// the axis whose box holds the index with a non-zero cut-off factor b(m), in
+// increasing order, with the local coordinate and the box extent.
+struct AxisOwn {
+    double beta[2];
+    int i[2];
+    int lc[2];
+    int n[2];
+    int cnt;
+    int pad;
+};
+
 struct Plan {
     int dim = 2;
     int M[3] = {0, 0, 0}, N[3] = {1, 1, 1}, C[3] = {1, 1, 1};
@@ -58,8 +70,8 @@ struct Plan {
     std::vector<Coef> coef;     // local tables (per subdomain, per axis)
     std::vector<Coef> gcoef;    // global tables per axis (offsets gcoff)
     int gcoff[3] = {0, 0, 0};
-    std::vector<int> owner;     // per axis, per global index: owning core index
-    int ooff[3] = {0, 0, 0};
+    std::vector<AxisOwn> aown;  // per axis, per global index: boxes with a non-zero cut-off
+    int aoff[3] = {0, 0, 0};
     std::vector<double> btab;   // side cut-off factor b(m), m = 0 .. n_ov
     std::vector<SolveItem> items;
     bool twisted = false;           // factor layout: both-ends elimination
@@ -84,7 +96,7 @@ struct ddm_handle {
     // device tables
     ddm::SubDesc *d_subs = nullptr;
     ddm::Coef *d_coef = nullptr, *d_gcoef = nullptr;
-    int *d_owner = nullptr;
+    ddm::AxisOwn *d_aown = nullptr;
     double *d_btab = nullptr;
     double *d_k2 = nullptr;
     ddm::SolveItem *d_items = nullptr;

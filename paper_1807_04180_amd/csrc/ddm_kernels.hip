@@ -326,53 +326,38 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Assembly u(p) (+)= sum_a beta_{0;a}(p) U_a(p) (eq. tsum).  At most 2 owners
-// per axis have a non-zero cut-off at p.  active[rhs] == 0 skips the RHS.
+// Assembly u(p) (+)= sum_a beta_{0;a}(p) U_a(p) (eq. tsum).  beta_{0;a} is the
+// product over axes of the boxes' cut-off factors; per axis at most two boxes
+// have a non-zero factor at p (the AxisOwn tables), visited in increasing
+// subdomain order.  active[rhs] == 0 skips the RHS.
 // ---------------------------------------------------------------------------
 template <typename TIN>
-__global__ __launch_bounds__(kBlock) void k_assemble(const SubDesc *__restrict__ subs, const int *__restrict__ owner,
-                                                     int o0, int o1, int o2, int N0, int N1, int N2,
-                                                     const double *__restrict__ btab, const TIN *__restrict__ U,
+__global__ __launch_bounds__(kBlock) void k_assemble(const SubDesc *__restrict__ subs,
+                                                     const AxisOwn *__restrict__ aown, int o0, int o1, int o2,
+                                                     int N0, int N1, const TIN *__restrict__ U,
                                                      double2 *__restrict__ u, PackArgs A, int accumulate,
                                                      const int *__restrict__ active) {
     const int rhs = blockIdx.y;
     if (active && !active[rhs]) return;
     const int rowi = blockIdx.x;  // gy + G1 * gz
     const int gy = rowi % A.G1, gz = rowi / A.G1;
-    for (int gx = threadIdx.x; gx < A.G0; gx += kBlock) {
-    const long long idx = (long long)rowi * A.G0 + gx;
-    int p[3] = {gx + A.glo0, gy + A.glo1, gz + A.glo2};
-    int own[3] = {owner[o0 + gx], owner[o1 + gy], owner[o2 + gz]};
-    int Nn[3] = {N0, N1, N2};
-    double2 acc = make_double2(0, 0);
+    const AxisOwn ey = aown[o1 + gy], ez = aown[o2 + gz];
     const TIN *Ur = U + rhs * A.etot;
-    for (int dz = -1; dz <= 1; ++dz) {
-        int iz = own[2] + dz;
-        if (iz < 0 || iz >= Nn[2]) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            int iy = own[1] + dy;
-            if (iy < 0 || iy >= Nn[1]) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                int ix = own[0] + dx;
-                if (ix < 0 || ix >= Nn[0]) continue;
-                const SubDesc &s = subs[ix + N0 * (iy + N1 * iz)];
-                double bz = 1.0;
-                bool inside = true;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    if (p[d] < s.lo[d] || p[d] > s.hi[d]) inside = false;
-                    else if (p[d] > s.chi[d]) bz *= side_factor(btab, A.n_ov, p[d] - s.chi[d]);
-                    else if (p[d] < s.clo[d]) bz *= side_factor(btab, A.n_ov, s.clo[d] - p[d]);
+    double2 *ur = u + rhs * A.nglob + (long long)rowi * A.G0;
+    for (int gx = threadIdx.x; gx < A.G0; gx += kBlock) {
+        const AxisOwn ex = aown[o0 + gx];
+        double2 acc = make_double2(0, 0);
+        for (int c2 = 0; c2 < ez.cnt; ++c2)
+            for (int c1 = 0; c1 < ey.cnt; ++c1) {
+                const int ayz = N0 * (ey.i[c1] + N1 * ez.i[c2]);
+                const long long lyz = (long long)ey.lc[c1] + (long long)ey.n[c1] * ez.lc[c2];
+                for (int c0 = 0; c0 < ex.cnt; ++c0) {
+                    const double bz = ex.beta[c0] * ey.beta[c1] * ez.beta[c2];
+                    const long long li = (long long)ex.lc[c0] + (long long)ex.n[c0] * lyz;
+                    acc = cadd(acc, cscale(to_d2(Ur[subs[ex.i[c0] + ayz].off + li]), bz));
                 }
-                if (!inside || bz == 0.0) continue;
-                long long li = (long long)(p[0] - s.lo[0]) +
-                               (long long)s.n[0] * ((long long)(p[1] - s.lo[1]) + (long long)s.n[1] * (p[2] - s.lo[2]));
-                acc = cadd(acc, cscale(to_d2(Ur[s.off + li]), bz));
             }
-        }
-    }
-    double2 *ur = u + rhs * A.nglob + idx;
-    *ur = accumulate ? cadd(*ur, acc) : acc;
+        ur[gx] = accumulate ? cadd(ur[gx], acc) : acc;
     }
 }
 
@@ -420,9 +405,8 @@ hipError_t launch_assemble(ddm_handle *h, const TIN *U, double2 *u, int nrhs, bo
     dim3 grid((unsigned)(P.G[1] * P.G[2]), nrhs);
     // local solutions read once per global node, u read (if accumulating) and written
     ProfScope ps(h, DDM_K_ASSEMBLE, (double)P.nglob * nrhs * (sizeof(TIN) + (accumulate ? 32.0 : 16.0)));
-    k_assemble<TIN><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_owner, P.ooff[0], P.ooff[1], P.ooff[2], P.N[0],
-                                                    P.N[1], P.N[2], h->d_btab, U, u, pack_args(P),
-                                                    accumulate ? 1 : 0, d_active);
+    k_assemble<TIN><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_aown, P.aoff[0], P.aoff[1], P.aoff[2], P.N[0],
+                                                    P.N[1], U, u, pack_args(P), accumulate ? 1 : 0, d_active);
     return hipGetLastError();
 }
 

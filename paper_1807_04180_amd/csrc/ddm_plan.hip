@@ -112,10 +112,9 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
     P.nglob = (long long)P.G[0] * P.G[1] * P.G[2];
     P.ring = p->dim == 2 ? 3 : 4;
 
-    // global coefficient tables and owner maps
+    // global coefficient tables
     for (int d = 0; d < 3; ++d) {
         P.gcoff[d] = (int)P.gcoef.size();
-        P.ooff[d] = (int)P.owner.size();
         for (int gi = 0; gi < P.G[d]; ++gi) {
             double x = P.glo[d] + gi;
             if (d < p->dim)
@@ -123,11 +122,6 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
                                             ax[d].sigma_global(x - 0.5), p->h));
             else
                 P.gcoef.push_back(Coef{make_double2(0, 0), make_double2(0, 0)});
-            int own = 0;
-            if (d < p->dim)
-                for (int i = 0; i < P.N[d]; ++i)
-                    if (x >= ax[d].clo(i) && x <= ax[d].chi(i)) own = i;
-            P.owner.push_back(own);
         }
     }
 
@@ -202,6 +196,39 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
     P.btab.resize(p->n_ov + 1);
     for (int m = 0; m <= p->n_ov; ++m)
         P.btab[m] = m <= 1 ? 1.0 : (m >= p->n_ov ? 0.0 : beta0((double)(m - 1) / (double)(p->n_ov - 1)));
+    // assembly tables: per axis and global index, the boxes whose cut-off
+    // b(m) is non-zero there (the factor of eq. tsum along that axis)
+    auto side = [&](int m) { return m <= 1 ? 1.0 : (m >= p->n_ov ? 0.0 : P.btab[m]); };
+    for (int d = 0; d < 3; ++d) {
+        P.aoff[d] = (int)P.aown.size();
+        for (int gi = 0; gi < P.G[d]; ++gi) {
+            AxisOwn e{};
+            if (d >= p->dim) {
+                e.beta[0] = 1.0;
+                e.n[0] = 1;
+                e.cnt = 1;
+            } else {
+                const int x = P.glo[d] + gi;
+                for (int i = 0; i < P.N[d]; ++i) {
+                    if (x < ax[d].lo(i) || x > ax[d].hi(i)) continue;
+                    double b = 1.0;
+                    if (x > ax[d].chi(i)) b = side(x - ax[d].chi(i));
+                    else if (x < ax[d].clo(i)) b = side(ax[d].clo(i) - x);
+                    if (b == 0.0) continue;
+                    if (e.cnt == 2) {
+                        *err = "more than two boxes with a non-zero cut-off at one node";
+                        return DDM_EINVAL;
+                    }
+                    e.beta[e.cnt] = b;
+                    e.i[e.cnt] = i;
+                    e.lc[e.cnt] = x - ax[d].lo(i);
+                    e.n[e.cnt] = ax[d].hi(i) - ax[d].lo(i) + 1;
+                    ++e.cnt;
+                }
+            }
+            P.aown.push_back(e);
+        }
+    }
     return DDM_OK;
 }
 
