@@ -102,6 +102,7 @@ size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
     size_t b = 0;
     b += P.subs.size() * sizeof(SubDesc) + (P.coef.size() + P.gcoef.size()) * sizeof(Coef);
     b += P.aown.size() * sizeof(AxisOwn) + P.btab.size() * sizeof(double) + P.items.size() * sizeof(SolveItem);
+    b += P.strip.size() * sizeof(int2);
     b += (size_t)P.nglob * sizeof(double);                         // k2
     b += (size_t)P.fel * es;                                       // factors
     b += factor_ws_bytes(P);                                       // factor workspace (freed after factor)
@@ -114,7 +115,7 @@ size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
 }
 
 void free_all(ddm_handle *h) {
-    void *ptrs[] = {h->d_subs, h->d_coef, h->d_gcoef, h->d_aown, h->d_btab, h->d_k2, h->d_items, h->d_W,
+    void *ptrs[] = {h->d_subs, h->d_coef, h->d_gcoef, h->d_aown, h->d_strip, h->d_btab, h->d_k2, h->d_items, h->d_W,
                     h->d_scratch, h->d_flags, h->d_g, h->d_ring[0], h->d_ring[1], h->d_ring[2], h->d_ring[3],
                     h->d_r, h->d_wide, h->d_part, h->d_norm, h->d_active, h->d_V, h->d_Z, h->d_dots,
                     h->d_coef_y, h->d_sync};
@@ -849,6 +850,7 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         dalloc(h, &h->d_coef, P.coef.size());
         dalloc(h, &h->d_gcoef, P.gcoef.size());
         dalloc(h, &h->d_aown, P.aown.size());
+        dalloc(h, &h->d_strip, P.strip.size() > 0 ? P.strip.size() : 1);
         dalloc(h, &h->d_btab, P.btab.size());
         dalloc(h, &h->d_items, P.items.size());
         dalloc(h, &h->d_k2, (size_t)P.nglob);
@@ -857,6 +859,8 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         HIPCHK(hipMemcpy(h->d_coef, P.coef.data(), P.coef.size() * sizeof(Coef), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_gcoef, P.gcoef.data(), P.gcoef.size() * sizeof(Coef), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_aown, P.aown.data(), P.aown.size() * sizeof(AxisOwn), hipMemcpyHostToDevice));
+        if (!P.strip.empty())
+            HIPCHK(hipMemcpy(h->d_strip, P.strip.data(), P.strip.size() * sizeof(int2), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_btab, P.btab.data(), P.btab.size() * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_items, P.items.data(), P.items.size() * sizeof(SolveItem), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_k2, hk2.data(), P.nglob * sizeof(double), hipMemcpyHostToDevice));

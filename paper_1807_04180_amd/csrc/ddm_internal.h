@@ -70,6 +70,7 @@ struct Plan {
     std::vector<Coef> coef;     // local tables (per subdomain, per axis)
     std::vector<Coef> gcoef;    // global tables per axis (offsets gcoff)
     int gcoff[3] = {0, 0, 0};
+    std::vector<int2> strip;    // (subdomain, local node) of every node in a transfer strip
     std::vector<AxisOwn> aown;  // per axis, per global index: boxes with a non-zero cut-off
     int aoff[3] = {0, 0, 0};
     std::vector<double> btab;   // side cut-off factor b(m), m = 0 .. n_ov
@@ -97,6 +98,7 @@ struct ddm_handle {
     ddm::SubDesc *d_subs = nullptr;
     ddm::Coef *d_coef = nullptr, *d_gcoef = nullptr;
     ddm::AxisOwn *d_aown = nullptr;
+    int2 *d_strip = nullptr;
     double *d_btab = nullptr;
     double *d_k2 = nullptr;
     ddm::SolveItem *d_items = nullptr;

@@ -235,19 +235,27 @@ __device__ inline double2 weighted(const SubDesc &b, const int *dd, const TIN *_
 // which equals the plain transfer in exact arithmetic (discrete residual
 // identity) and feeds the rounding errors of the local solves back as
 // sources.  Rows outside the core keep the plain transfer.
+//
+// The launch first writes every node's value without neighbour terms (0, or
+// r on the core in the corrected form: the restriction kernel), then one
+// thread per node of the strip list (the nodes within n_ov core layers of
+// a box side) adds the neighbour terms, so that no lane idles on the many
+// nodes far from every interface.
 template <typename TIN, typename TOUT>
 __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__ subs, const Coef *__restrict__ coef,
                                                      const double *__restrict__ k2, const double *__restrict__ btab,
                                                      const TIN *__restrict__ l1, const TIN *__restrict__ l2,
                                                      const TIN *__restrict__ l3, TOUT *__restrict__ g, PackArgs A,
-                                                     const double2 *__restrict__ rcorr) {
-    const int a = blockIdx.y, rhs = blockIdx.z;
+                                                     const double2 *__restrict__ rcorr, const int2 *__restrict__ strip,
+                                                     long long nstrip) {
+    const int rhs = blockIdx.y;
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nstrip) return;
+    const int2 se = strip[t];
+    const int a = se.x;
+    const long long e = se.y;
     const SubDesc &s = subs[a];
-    const int rowi = blockIdx.x;  // ly + n1 * lz
-    if (rowi >= s.n[1] * s.n[2]) return;
-    const int ly = rowi % s.n[1], lz = rowi / s.n[1];
-    for (int lx = threadIdx.x; lx < s.n[0]; lx += kBlock) {
-    const long long e = (long long)rowi * s.n[0] + lx;
+    const int lx = (int)(e % s.n[0]), ly = (int)((e / s.n[0]) % s.n[1]), lz = (int)(e / ((long long)s.n[0] * s.n[1]));
     int p[3] = {s.lo[0] + lx, s.lo[1] + ly, s.lo[2] + lz};
     int l[3] = {lx, ly, lz};
     double2 acc = make_double2(0, 0);
@@ -260,69 +268,65 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
         inlo[d] = d < A.dim && p[d] >= s.clo[d] && p[d] <= s.clo[d] + A.n_ov - 1;
         inhi[d] = d < A.dim && p[d] <= s.chi[d] && p[d] >= s.chi[d] - A.n_ov + 1;
     }
-    bool any = inlo[0] || inhi[0] || inlo[1] || inhi[1] || inlo[2] || inhi[2];
     const bool corrected = rcorr && p[0] >= s.clo[0] && p[0] <= s.chi[0] && p[1] >= s.clo[1] &&
                            p[1] <= s.chi[1] && p[2] >= s.clo[2] && p[2] <= s.chi[2];
     if (corrected) acc = rcorr[rhs * A.nglob + glob_index(A, p[0], p[1], p[2])];
-    if (any) {
-        double kk = k2[glob_index(A, p[0], p[1], p[2])];
-        Coef cf[3];
+    double kk = k2[glob_index(A, p[0], p[1], p[2])];
+    Coef cf[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) cf[d] = coef[s.coff[d] + l[d]];
-        int k = 0;
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    if (dx == 0 && dy == 0 && dz == 0) continue;
-                    int slot = k++;
-                    int bidx = s.nbr[slot];
-                    if (bidx < 0) continue;
-                    int dd[3] = {dx, dy, dz};
-                    // every differing axis must put p in the strip facing b
-                    bool ok = true;
+    for (int d = 0; d < 3; ++d) cf[d] = coef[s.coff[d] + l[d]];
+    int k = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0 && dz == 0) continue;
+                int slot = k++;
+                int bidx = s.nbr[slot];
+                if (bidx < 0) continue;
+                int dd[3] = {dx, dy, dz};
+                // every differing axis must put p in the strip facing b
+                bool ok = true;
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        if (dd[d] < 0 && !inlo[d]) ok = false;
-                        if (dd[d] > 0 && !inhi[d]) ok = false;
-                    }
-                    if (!ok) continue;
-                    int lag = s.lag[slot];
-                    const TIN *src = lag == 1 ? l1 : (lag == 2 ? l2 : l3);
-                    const TIN *src2 = nullptr;
-                    if (corrected) {
-                        // edge / face terms are inside r; lag >= 2 terms use the
-                        // newer solutions: uhat^s (+ uhat^{s-1} for lag 3)
-                        if (lag == 1) continue;
-                        src = l1;
-                        src2 = lag == 3 ? l2 : nullptr;
-                    }
-                    if (!src) continue;
-                    src += rhs * A.etot;
-                    if (src2) src2 += rhs * A.etot;
-                    const SubDesc &b = subs[bidx];
-                    auto wsum = [&](int q0, int q1, int q2) {
-                        double2 v = weighted(b, dd, src, btab, A.n_ov, q0, q1, q2);
-                        if (src2) v = cadd(v, weighted(b, dd, src2, btab, A.n_ov, q0, q1, q2));
-                        return v;
-                    };
-                    double2 w0 = wsum(p[0], p[1], p[2]);
-                    double2 Lw = cscale(w0, kk);
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        if (d >= A.dim) continue;
-                        int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
-                        qp[d] += 1;
-                        qm[d] -= 1;
-                        double2 wp = p[d] < s.hi[d] ? wsum(qp[0], qp[1], qp[2]) : make_double2(0, 0);
-                        double2 wm = p[d] > s.lo[d] ? wsum(qm[0], qm[1], qm[2]) : make_double2(0, 0);
-                        Lw = cadd(Lw, csub(cmul(cf[d].cp, csub(wp, w0)), cmul(cf[d].cm, csub(w0, wm))));
-                    }
-                    // plain: acc += Psi = -L(beta v); corrected: acc -= Psi
-                    acc = corrected ? cadd(acc, Lw) : csub(acc, Lw);
+                for (int d = 0; d < 3; ++d) {
+                    if (dd[d] < 0 && !inlo[d]) ok = false;
+                    if (dd[d] > 0 && !inhi[d]) ok = false;
                 }
-    }
+                if (!ok) continue;
+                int lag = s.lag[slot];
+                const TIN *src = lag == 1 ? l1 : (lag == 2 ? l2 : l3);
+                const TIN *src2 = nullptr;
+                if (corrected) {
+                    // edge / face terms are inside r; lag >= 2 terms use the
+                    // newer solutions: uhat^s (+ uhat^{s-1} for lag 3)
+                    if (lag == 1) continue;
+                    src = l1;
+                    src2 = lag == 3 ? l2 : nullptr;
+                }
+                if (!src) continue;
+                src += rhs * A.etot;
+                if (src2) src2 += rhs * A.etot;
+                const SubDesc &b = subs[bidx];
+                auto wsum = [&](int q0, int q1, int q2) {
+                    double2 v = weighted(b, dd, src, btab, A.n_ov, q0, q1, q2);
+                    if (src2) v = cadd(v, weighted(b, dd, src2, btab, A.n_ov, q0, q1, q2));
+                    return v;
+                };
+                double2 w0 = wsum(p[0], p[1], p[2]);
+                double2 Lw = cscale(w0, kk);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (d >= A.dim) continue;
+                    int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
+                    qp[d] += 1;
+                    qm[d] -= 1;
+                    double2 wp = p[d] < s.hi[d] ? wsum(qp[0], qp[1], qp[2]) : make_double2(0, 0);
+                    double2 wm = p[d] > s.lo[d] ? wsum(qm[0], qm[1], qm[2]) : make_double2(0, 0);
+                    Lw = cadd(Lw, csub(cmul(cf[d].cp, csub(wp, w0)), cmul(cf[d].cm, csub(w0, wm))));
+                }
+                // plain: acc += Psi = -L(beta v); corrected: acc -= Psi
+                acc = corrected ? cadd(acc, Lw) : csub(acc, Lw);
+            }
     g[rhs * A.etot + s.off + e] = from_d2<TOUT>(acc);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -388,14 +392,24 @@ template <typename TIN, typename TOUT>
 hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TIN *l3, TOUT *g, int nrhs,
                            const double2 *rcorr) {
     const Plan &P = h->plan;
-    dim3 grid((unsigned)max_rows(P), P.nsub, nrhs);
     // packed g written; neighbour strips (n_ov + 1 layers) read
     double strip = 0.0;
     for (const SubDesc &sd : P.subs)
         for (int d = 0; d < P.dim; ++d) strip += 2.0 * (P.n_ov + 1) * (double)sd.nloc / sd.n[d];
     ProfScope ps(h, DDM_K_TRANSFER, (double)nrhs * ((double)P.etot * sizeof(TOUT) + strip * sizeof(TIN)));
-    k_transfer<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g,
-                                                          pack_args(P), rcorr);
+    if (rcorr) {
+        dim3 rg((unsigned)max_rows(P), P.nsub, nrhs);
+        k_restrict<double2, TOUT><<<rg, kBlock, 0, h->stream>>>(h->d_subs, rcorr, g, pack_args(P));
+    } else {
+        hipError_t e = launch_fill_zero(g, (long long)nrhs * P.etot * sizeof(TOUT), h->stream);
+        if (e != hipSuccess) return e;
+    }
+    const long long ns = (long long)P.strip.size();
+    if (ns > 0) {
+        dim3 grid((unsigned)((ns + kBlock - 1) / kBlock), nrhs);
+        k_transfer<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g,
+                                                              pack_args(P), rcorr, h->d_strip, ns);
+    }
     return hipGetLastError();
 }
 

@@ -196,6 +196,22 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
     P.btab.resize(p->n_ov + 1);
     for (int m = 0; m <= p->n_ov; ++m)
         P.btab[m] = m <= 1 ? 1.0 : (m >= p->n_ov ? 0.0 : beta0((double)(m - 1) / (double)(p->n_ov - 1)));
+    // transfer strips: nodes of a box within the first or last n_ov core
+    // layers along some axis (only there can a neighbour's transfer be
+    // non-zero)
+    for (int a = 0; a < P.nsub; ++a) {
+        const SubDesc &sd = P.subs[a];
+        for (long long e = 0; e < sd.nloc; ++e) {
+            const int l[3] = {(int)(e % sd.n[0]), (int)((e / sd.n[0]) % sd.n[1]), (int)(e / ((long long)sd.n[0] * sd.n[1]))};
+            bool in = false;
+            for (int d = 0; d < p->dim; ++d) {
+                const int x = sd.lo[d] + l[d];
+                if (x >= sd.clo[d] && x <= sd.clo[d] + p->n_ov - 1) in = true;
+                if (x <= sd.chi[d] && x >= sd.chi[d] - p->n_ov + 1) in = true;
+            }
+            if (in) P.strip.push_back(make_int2(a, (int)e));
+        }
+    }
     // assembly tables: per axis and global index, the boxes whose cut-off
     // b(m) is non-zero there (the factor of eq. tsum along that axis)
     auto side = [&](int m) { return m <= 1 ? 1.0 : (m >= p->n_ov ? 0.0 : P.btab[m]); };
