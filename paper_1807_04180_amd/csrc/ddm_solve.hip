@@ -155,6 +155,34 @@ __device__ inline void wait_flag(int *f, int target, int *abort_flag, int spin_l
 template <typename T2> struct ChainBatch { static constexpr int value = 8; };
 template <> struct ChainBatch<double2> { static constexpr int value = 4; };
 
+// Columns per wave staged in LDS ahead of each block step (direct
+// global->LDS 16-byte loads: complex128 only).
+template <typename T2> struct kLdsCols { static constexpr int value = 0; };
+template <> struct kLdsCols<double2> { static constexpr int value = 4; };
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
+constexpr int kWaitVm0 = 0x0F70;
+
+// Copy this wave's columns j = cg + CG u (u < PF) of the column-major block
+// Wl to LDS: lane i of the wave lands at dst[u * 64 + i] (the hardware
+// places 16 bytes per lane consecutively from the wave-uniform base).  Rows
+// past the block (lanes of a ragged row tile) copy the clamped last row.
+template <typename T2, int PF>
+__device__ inline void lds_prefetch(const T2 *Wl, T2 *dst, int cg, int CG, int bs, int rowc, bool gemv) {
+    if constexpr (PF > 0) {
+        static_assert(sizeof(T2) == 16, "direct LDS loads of 16 bytes per lane");
+        if (!gemv) return;
+#pragma unroll 1
+        for (int u = 0; u < PF; ++u) {
+            const int j = cg + CG * u;
+            if (j < bs)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(Wl + (long long)j * bs + rowc),
+                    (__attribute__((address_space(3))) void *)(dst + u * 64), 16, 0, 0);
+        }
+    }
+}
+
 template <typename T2, int RT>
 __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__restrict__ subs,
                                                            const Coef *__restrict__ coef, const T2 *__restrict__ W,
@@ -178,6 +206,12 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
     const int bsp = R * 64;
     T2 *vs = (T2 *)lds_raw;                 // [bsp][RT]  current v
     T2 *red = vs + (size_t)bsp * RT;        // [CG][RT][bsp] partial sums
+    // complex128: each wave's first kLdsCols columns of the next block are
+    // copied to LDS by direct global->LDS loads while the block step
+    // reduces, synchronises and forms the next v (the column stream would
+    // otherwise idle there); the register stream starts after them
+    constexpr int PF = kLdsCols<T2>::value;
+    T2 *mypf = red + (size_t)CG * RT * bsp + (size_t)wv * PF * 64;  // [PF][64]
     // this chain's block sequence: forward blocks, the middle, backward blocks
     const int nf = chain == 0 ? mid : nb - 1 - mid;
     if (twisted == 0 && chain == 1) return;
@@ -206,12 +240,14 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
         const long long bs2 = (long long)bs * bs;
         // W streaming, double-buffered in batches of kCBatch columns; the
         // batch after a block's last is the next block's first
+        const int rowc = row < bs ? row : bs - 1;  // clamped row for the LDS copies
         T2 wb[kCBatch];
         {
             const T2 *Wl = Wbase + (long long)step_l(0) * bs2;
+            lds_prefetch<T2, PF>(Wl, mypf, cg, CG, bs, rowc, gemv);
 #pragma unroll
             for (int u = 0; u < kCBatch; ++u) {
-                const int j = cg + CG * u;
+                const int j = cg + CG * (PF + u);
                 wb[u] = (rowok && j < bs) ? Wl[(long long)j * bs + row] : czero<T2>();
             }
         }
@@ -267,10 +303,22 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
             for (int q = 0; q < RT; ++q) acc[q] = czero<T2>();
             const int kmax = gemv ? (bs - cg + CG - 1) / CG : 0;  // columns of this wave
             const int lnext = t + 1 < nsteps ? step_l(t + 1) : -1;
-            for (int k0 = 0; k0 < kmax; k0 += kCBatch) {
+            if constexpr (PF > 0) {
+                __builtin_amdgcn_s_waitcnt(kWaitVm0);  // this wave's LDS copies have landed
+#pragma unroll 1
+                for (int u = 0; u < PF; ++u) {
+                    if (u < kmax) {
+                        const int j = cg + CG * u;
+                        const T2 w = mypf[u * 64 + lane];
+#pragma unroll
+                        for (int q = 0; q < RT; ++q) cfma(acc[q], w, vs[j * RT + q]);
+                    }
+                }
+            }
+            for (int k0 = PF; k0 < kmax; k0 += kCBatch) {
                 const bool more = k0 + kCBatch < kmax;
                 const int ln = more ? l : lnext;
-                const int kn = more ? k0 + kCBatch : 0;
+                const int kn = more ? k0 + kCBatch : PF;
                 T2 wn[kCBatch];
                 const T2 *Wn = Wbase + (long long)(ln >= 0 ? ln : 0) * bs2;
 #pragma unroll
@@ -293,6 +341,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
 #pragma unroll
                 for (int q = 0; q < RT; ++q) red[((size_t)cg * RT + q) * bsp + row] = acc[q];
             }
+            if (lnext >= 0) lds_prefetch<T2, PF>(Wbase + (long long)lnext * bs2, mypf, cg, CG, bs, rowc, gemv);
             __syncthreads();
             // ---- reduce over column groups; update x; build the next v ----
 #pragma unroll
@@ -380,7 +429,7 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     ProfScope ps(h, DDM_K_SUBST, es * (2.0 * (double)P.fel * ntile + 4.0 * nrhs * vb));
     const int R = (P.bs_max + 63) / 64;
     const int CG = kCWaves / R;
-    size_t lds = (size_t)R * 64 * RT * (1 + CG) * sizeof(T2);
+    size_t lds = (size_t)R * 64 * RT * (1 + CG) * sizeof(T2) + (size_t)kCWaves * kLdsCols<T2>::value * 64 * sizeof(T2);
     hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain<T2, RT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
