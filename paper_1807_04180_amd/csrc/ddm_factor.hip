@@ -6,7 +6,8 @@
 // l only to l-1 and l+1, through C_l = cm(l) I and B_l = cp(l) I, the 1D
 // coefficients of the last axis.  The factorisation is
 //     S_0 = D_0,   S_l = D_l - cm(l) cp(l-1) W_{l-1},   W_l = S_l^{-1},
-// and W_l is stored column-major (element (i, j) at j * bs + i), complex128
+// and W_l is stored column-major (element (i, j) at j * ld + i, ld = bs or the
+// next even number for complex64), complex128
 // or complex64.  Since C_l and B_l are multiples of the identity, the Schur
 // complement update is a scaled copy; the dense work is the inversion of
 // every S_l, done in FP64 by blocked Gauss-Jordan elimination with partial
@@ -643,7 +644,8 @@ __global__ __launch_bounds__(kEThreads) void k_factor_store(const SubDesc *__res
     const double2 *N = chain_M(w, c, q.cur);
     double2 *Mn = chain_M(w, c, q.cur ^ 1);
     const int *ppos = w.ppos + (long long)c * w.bsp, *piv = w.piv + (long long)c * w.bsp;
-    T2 *Wl = W + sd.foff + (long long)q.l * bs * bs;
+    const int ld = sd.ld;
+    T2 *Wl = W + sd.foff + (long long)q.l * bs * ld;
     const bool next = !mid && !q.last;
     const int ln = q.dir == 0 ? q.l + 1 : q.l - 1;
     Coef cln = coef[sd.coff[ax] + (next ? ln : q.l)];
@@ -654,7 +656,8 @@ __global__ __launch_bounds__(kEThreads) void k_factor_store(const SubDesc *__res
     for (long long e = (long long)grp * kEThreads + threadIdx.x; e < n2; e += (long long)groups * kEThreads) {
         const int i = (int)(e % bs), j = (int)(e / bs);
         const double2 v = N[(long long)ppos[j] * bs + piv[i]];
-        Wl[e] = from_d2<T2>(v);
+        Wl[(long long)j * ld + i] = from_d2<T2>(v);
+        if (ld > bs && i == bs - 1) Wl[(long long)j * ld + bs] = czero<T2>();  // padding row
         if (!mid) {
             const double2 mv = next ? csub(block_entry(sd, coef, k2, A, ln, i, j, cln), cmul(cc, v)) : v;
             Mn[e] = mv;

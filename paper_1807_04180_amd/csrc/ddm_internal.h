@@ -24,6 +24,8 @@ struct SubDesc {
                            // on, blocks > mid from the last block on; mid = nb - 1 gives
                            // the one-directional factorisation
     int bs;                // block size (n[0] in 2D, n[0]*n[1] in 3D)
+    int ld;                // column stride of the stored block inverses: bs, or bs + 1 for
+                           // odd complex64 blocks (16-byte aligned pairs of rows)
     long long foff;        // factor offset (elements)
     int coff[3];           // offsets of this box's per-axis coefficient tables
     int nbr[26];           // neighbour ids for the 26 offsets (-1: none)

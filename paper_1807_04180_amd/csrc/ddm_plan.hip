@@ -150,8 +150,9 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
         off += cnt;
         s.nb = s.n[p->dim - 1];
         s.bs = (int)(cnt / s.nb);
+        s.ld = (p->precision == DDM_MIXED && (s.bs & 1)) ? s.bs + 1 : s.bs;
         s.foff = foff;
-        foff += (long long)s.nb * s.bs * s.bs;
+        foff += (long long)s.nb * s.bs * s.ld;
         if (s.bs > P.bs_max) P.bs_max = s.bs;
         if (s.nb > P.nb_max) P.nb_max = s.nb;
         for (int d = 0; d < 3; ++d) {

@@ -37,7 +37,8 @@ __global__ __launch_bounds__(kSThreads) void k_solve_line(const SubDesc *__restr
     const int l = BACKWARD ? nb - 2 - step : step;
     if (l < 0 || l >= nb) return;
     const long long off = s.off;
-    const T2 *Wl = W + s.foff + (long long)l * bs * bs;
+    const int ld = s.ld;
+    const T2 *Wl = W + s.foff + (long long)l * bs * ld;
     const Coef c = coef[s.coff[dim - 1] + l];
     const double2 cpl = BACKWARD ? c.cp : c.cm;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -67,13 +68,13 @@ __global__ __launch_bounds__(kSThreads) void k_solve_line(const SubDesc *__restr
             }
             __syncthreads();
             if (row < bs) {
-                const T2 *col = Wl + (long long)j0 * bs + row;
+                const T2 *col = Wl + (long long)j0 * ld + row;
                 int jj = wv;
                 for (; jj + 3 * kSWaves < jn; jj += 4 * kSWaves) {
-                    T2 w0 = col[(long long)jj * bs];
-                    T2 w1 = col[(long long)(jj + kSWaves) * bs];
-                    T2 w2 = col[(long long)(jj + 2 * kSWaves) * bs];
-                    T2 w3 = col[(long long)(jj + 3 * kSWaves) * bs];
+                    T2 w0 = col[(long long)jj * ld];
+                    T2 w1 = col[(long long)(jj + kSWaves) * ld];
+                    T2 w2 = col[(long long)(jj + 2 * kSWaves) * ld];
+                    T2 w3 = col[(long long)(jj + 3 * kSWaves) * ld];
 #pragma unroll
                     for (int q = 0; q < RT; ++q) {
                         cfma(acc[q], w0, vs[jj * RT + q]);
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(kSThreads) void k_solve_line(const SubDesc *__restr
                     }
                 }
                 for (; jj < jn; jj += kSWaves) {
-                    T2 w0 = col[(long long)jj * bs];
+                    T2 w0 = col[(long long)jj * ld];
 #pragma unroll
                     for (int q = 0; q < RT; ++q) cfma(acc[q], w0, vs[jj * RT + q]);
                 }
@@ -151,67 +152,89 @@ __device__ inline void wait_flag(int *f, int target, int *abort_flag, int spin_l
     __syncthreads();
 }
 
+// Rows per lane: complex64 lanes take two consecutive rows so that every
+// load is 16 bytes (8-byte lane loads stream at about 60% of the per-CU
+// rate of 16-byte ones); LT is the per-lane load type.
+template <typename T2, int ROWS> struct LaneT;
+template <> struct LaneT<double2, 1> { using type = double2; };
+template <> struct LaneT<float2, 1> { using type = float2; };
+template <> struct LaneT<float2, 2> { using type = float4; };
+
+__device__ inline double2 lane_row(double2 v, int) { return v; }
+__device__ inline float2 lane_row(float2 v, int) { return v; }
+__device__ inline float2 lane_row(float4 v, int r) { return r == 0 ? make_float2(v.x, v.y) : make_float2(v.z, v.w); }
+
+template <typename LT> __device__ inline LT lane_zero();
+template <> __device__ inline double2 lane_zero<double2>() { return make_double2(0, 0); }
+template <> __device__ inline float2 lane_zero<float2>() { return make_float2(0.f, 0.f); }
+template <> __device__ inline float4 lane_zero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+
 // columns per W batch (two batches in flight per wave)
-template <typename T2> struct ChainBatch { static constexpr int value = 8; };
-template <> struct ChainBatch<double2> { static constexpr int value = 4; };
+template <typename T2, int ROWS> struct ChainBatch { static constexpr int value = 8; };
+template <> struct ChainBatch<double2, 1> { static constexpr int value = 4; };
+template <> struct ChainBatch<float2, 2> { static constexpr int value = 4; };
 
 // Columns per wave staged in LDS ahead of each block step (direct
-// global->LDS 16-byte loads: complex128 only).
-template <typename T2> struct kLdsCols { static constexpr int value = 0; };
-template <> struct kLdsCols<double2> { static constexpr int value = 4; };
+// global->LDS loads of 16 bytes per lane).
+template <typename T2, int ROWS> struct kLdsCols { static constexpr int value = 0; };
+template <> struct kLdsCols<double2, 1> { static constexpr int value = 4; };
+template <> struct kLdsCols<float2, 2> { static constexpr int value = 4; };
 
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
 constexpr int kWaitVm0 = 0x0F70;
 
 // Copy this wave's columns j = cg + CG u (u < PF) of the column-major block
-// Wl to LDS: lane i of the wave lands at dst[u * 64 + i] (the hardware
-// places 16 bytes per lane consecutively from the wave-uniform base).  Rows
-// past the block (lanes of a ragged row tile) copy the clamped last row.
-template <typename T2, int PF>
-__device__ inline void lds_prefetch(const T2 *Wl, T2 *dst, int cg, int CG, int bs, int rowc, bool gemv) {
+// Wl (column stride ld) to LDS: lane i of the wave lands at 16-byte slot
+// u * 64 + i of dst (the hardware places 16 bytes per lane consecutively
+// from the wave-uniform base).  Lanes past the block copy the clamped last
+// row (pair).
+template <typename T2, int PF, int ROWS>
+__device__ inline void lds_prefetch(const T2 *Wl, T2 *dst, int cg, int CG, int bs, int ld, int rowc, bool gemv) {
     if constexpr (PF > 0) {
-        static_assert(sizeof(T2) == 16, "direct LDS loads of 16 bytes per lane");
+        static_assert(sizeof(T2) * ROWS == 16, "direct LDS loads of 16 bytes per lane");
         if (!gemv) return;
 #pragma unroll 1
         for (int u = 0; u < PF; ++u) {
             const int j = cg + CG * u;
             if (j < bs)
                 __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void *)(Wl + (long long)j * bs + rowc),
-                    (__attribute__((address_space(3))) void *)(dst + u * 64), 16, 0, 0);
+                    (const __attribute__((address_space(1))) void *)(Wl + (long long)j * ld + rowc),
+                    (__attribute__((address_space(3))) void *)(dst + u * 64 * ROWS), 16, 0, 0);
         }
     }
 }
 
-template <typename T2, int RT>
+template <typename T2, int RT, int ROWS>
 __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__restrict__ subs,
                                                            const Coef *__restrict__ coef, const T2 *__restrict__ W,
                                                            const T2 *__restrict__ g, T2 *__restrict__ x, int nrhs,
                                                            long long etot, int dim, int twisted, int *flags,
                                                            int *abort_flag, int spin_limit) {
     extern __shared__ unsigned char lds_raw[];
-    constexpr int kCBatch = RT >= 16 ? 4 : ChainBatch<T2>::value;
+    using LT = typename LaneT<T2, ROWS>::type;
+    constexpr int kCBatch = RT >= 16 ? 4 : ChainBatch<T2, ROWS>::value;
     const int a = twisted ? (int)(blockIdx.x >> 1) : (int)blockIdx.x;
     const int chain = twisted ? (int)(blockIdx.x & 1) : 0;
     const SubDesc &s = subs[a];
     const int nb = s.nb, bs = s.bs, mid = s.mid, ax = dim - 1;
     const long long off = s.off;
-    const int R = (bs + 63) >> 6;
+    const int ld = s.ld;
+    const int R = (bs + 64 * ROWS - 1) / (64 * ROWS);
     const int CG = kCWaves / R;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int rt = wv % R, cg = wv / R;
     const bool gemv = cg < CG;
-    const int row = rt * 64 + lane;
+    const int row = (rt * 64 + lane) * ROWS;  // this lane's first row
     const bool rowok = gemv && row < bs;
-    const int bsp = R * 64;
+    const int bsp = R * 64 * ROWS;
     T2 *vs = (T2 *)lds_raw;                 // [bsp][RT]  current v
     T2 *red = vs + (size_t)bsp * RT;        // [CG][RT][bsp] partial sums
     // complex128: each wave's first kLdsCols columns of the next block are
     // copied to LDS by direct global->LDS loads while the block step
     // reduces, synchronises and forms the next v (the column stream would
     // otherwise idle there); the register stream starts after them
-    constexpr int PF = kLdsCols<T2>::value;
-    T2 *mypf = red + (size_t)CG * RT * bsp + (size_t)wv * PF * 64;  // [PF][64]
+    constexpr int PF = kLdsCols<T2, ROWS>::value;
+    T2 *mypf = red + (size_t)CG * RT * bsp + (size_t)wv * PF * 64 * ROWS;  // [PF][64 lanes][ROWS]
     // this chain's block sequence: forward blocks, the middle, backward blocks
     const int nf = chain == 0 ? mid : nb - 1 - mid;
     if (twisted == 0 && chain == 1) return;
@@ -237,18 +260,18 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
             return mid - dirf * (t - nf);
         };
         const T2 *Wbase = W + s.foff;
-        const long long bs2 = (long long)bs * bs;
+        const long long bs2 = (long long)bs * ld;  // block stride
         // W streaming, double-buffered in batches of kCBatch columns; the
         // batch after a block's last is the next block's first
-        const int rowc = row < bs ? row : bs - 1;  // clamped row for the LDS copies
-        T2 wb[kCBatch];
+        const int rowc = row < bs ? row : (bs - 1) / ROWS * ROWS;  // clamped row for the LDS copies
+        LT wb[kCBatch];
         {
             const T2 *Wl = Wbase + (long long)step_l(0) * bs2;
-            lds_prefetch<T2, PF>(Wl, mypf, cg, CG, bs, rowc, gemv);
+            lds_prefetch<T2, PF, ROWS>(Wl, mypf, cg, CG, bs, ld, rowc, gemv);
 #pragma unroll
             for (int u = 0; u < kCBatch; ++u) {
                 const int j = cg + CG * (PF + u);
-                wb[u] = (rowok && j < bs) ? Wl[(long long)j * bs + row] : czero<T2>();
+                wb[u] = (rowok && j < bs) ? *(const LT *)(Wl + (long long)j * ld + row) : lane_zero<LT>();
             }
         }
         for (int t = 0; t < nsteps; ++t) {
@@ -298,9 +321,11 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
                 else pre[u] = czero<T2>();
             }
             // ---- GEMV: acc = W_l v ----
-            T2 acc[RT];
+            T2 acc[ROWS][RT];
 #pragma unroll
-            for (int q = 0; q < RT; ++q) acc[q] = czero<T2>();
+            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                for (int q = 0; q < RT; ++q) acc[r][q] = czero<T2>();
             const int kmax = gemv ? (bs - cg + CG - 1) / CG : 0;  // columns of this wave
             const int lnext = t + 1 < nsteps ? step_l(t + 1) : -1;
             if constexpr (PF > 0) {
@@ -309,9 +334,11 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
                 for (int u = 0; u < PF; ++u) {
                     if (u < kmax) {
                         const int j = cg + CG * u;
-                        const T2 w = mypf[u * 64 + lane];
+                        const LT w = ((const LT *)mypf)[u * 64 + lane];
 #pragma unroll
-                        for (int q = 0; q < RT; ++q) cfma(acc[q], w, vs[j * RT + q]);
+                        for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                            for (int q = 0; q < RT; ++q) cfma(acc[r][q], lane_row(w, r), vs[j * RT + q]);
                     }
                 }
             }
@@ -319,19 +346,21 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
                 const bool more = k0 + kCBatch < kmax;
                 const int ln = more ? l : lnext;
                 const int kn = more ? k0 + kCBatch : PF;
-                T2 wn[kCBatch];
+                LT wn[kCBatch];
                 const T2 *Wn = Wbase + (long long)(ln >= 0 ? ln : 0) * bs2;
 #pragma unroll
                 for (int u = 0; u < kCBatch; ++u) {
                     const int j = cg + CG * (kn + u);
-                    wn[u] = (ln >= 0 && rowok && j < bs) ? Wn[(long long)j * bs + row] : czero<T2>();
+                    wn[u] = (ln >= 0 && rowok && j < bs) ? *(const LT *)(Wn + (long long)j * ld + row) : lane_zero<LT>();
                 }
 #pragma unroll
                 for (int u = 0; u < kCBatch; ++u) {
                     const int j = cg + CG * (k0 + u);
                     if (j < bs) {
 #pragma unroll
-                        for (int q = 0; q < RT; ++q) cfma(acc[q], wb[u], vs[j * RT + q]);
+                        for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                            for (int q = 0; q < RT; ++q) cfma(acc[r][q], lane_row(wb[u], r), vs[j * RT + q]);
                     }
                 }
 #pragma unroll
@@ -339,9 +368,12 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
             }
             if (gemv) {
 #pragma unroll
-                for (int q = 0; q < RT; ++q) red[((size_t)cg * RT + q) * bsp + row] = acc[q];
+                for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                    for (int q = 0; q < RT; ++q) red[((size_t)cg * RT + q) * bsp + row + r] = acc[r][q];
             }
-            if (lnext >= 0) lds_prefetch<T2, PF>(Wbase + (long long)lnext * bs2, mypf, cg, CG, bs, rowc, gemv);
+            if (lnext >= 0)
+                lds_prefetch<T2, PF, ROWS>(Wbase + (long long)lnext * bs2, mypf, cg, CG, bs, ld, rowc, gemv);
             __syncthreads();
             // ---- reduce over column groups; update x; build the next v ----
 #pragma unroll
@@ -417,7 +449,7 @@ static hipError_t run_perline(ddm_handle *h, const T *g, T *x, int nrhs) {
     return run_sweeps<T, 8>(h, g, x, nrhs);
 }
 
-template <typename T2, int RT>
+template <typename T2, int RT, int ROWS>
 static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     const Plan &P = h->plan;
     const double es = sizeof(T2);
@@ -427,10 +459,11 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     // W read once per sweep and RHS tile; block vectors: g read, y written,
     // y read back and x written
     ProfScope ps(h, DDM_K_SUBST, es * (2.0 * (double)P.fel * ntile + 4.0 * nrhs * vb));
-    const int R = (P.bs_max + 63) / 64;
+    const int R = (P.bs_max + 64 * ROWS - 1) / (64 * ROWS);
     const int CG = kCWaves / R;
-    size_t lds = (size_t)R * 64 * RT * (1 + CG) * sizeof(T2) + (size_t)kCWaves * kLdsCols<T2>::value * 64 * sizeof(T2);
-    hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain<T2, RT>,
+    size_t lds = (size_t)R * 64 * ROWS * RT * (1 + CG) * sizeof(T2) +
+                 (size_t)kCWaves * kLdsCols<T2, ROWS>::value * 64 * ROWS * sizeof(T2);
+    hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain<T2, RT, ROWS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (P.twisted) {
@@ -448,10 +481,10 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
         int a11 = h->spin_limit;
         void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11};
         // the two chains of a subdomain meet once: they must be co-resident
-        return hipLaunchCooperativeKernel((const void *)k_solve_chain<T2, RT>, dim3(2 * P.nsub), dim3(kCThreads),
+        return hipLaunchCooperativeKernel((const void *)k_solve_chain<T2, RT, ROWS>, dim3(2 * P.nsub), dim3(kCThreads),
                                           args, lds, h->stream);
     }
-    k_solve_chain<T2, RT><<<P.nsub, kCThreads, lds, h->stream>>>(h->d_subs, h->d_coef, (const T2 *)h->d_W, g, x,
+    k_solve_chain<T2, RT, ROWS><<<P.nsub, kCThreads, lds, h->stream>>>(h->d_subs, h->d_coef, (const T2 *)h->d_W, g, x,
                                                                  nrhs, P.etot, P.dim, 0, h->d_sync,
                                                                  h->d_sync + 2 * P.nsub, h->spin_limit);
     return hipGetLastError();
@@ -459,14 +492,16 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
 
 template <typename T>
 static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
-    if (nrhs <= 1) return run_chain<T, 1>(h, g, x, nrhs);
-    if (nrhs <= 2) return run_chain<T, 2>(h, g, x, nrhs);
     if constexpr (sizeof(T) == sizeof(double2)) {
-        return run_chain<T, 4>(h, g, x, nrhs);
+        if (nrhs <= 1) return run_chain<T, 1, 1>(h, g, x, nrhs);
+        if (nrhs <= 2) return run_chain<T, 2, 1>(h, g, x, nrhs);
+        return run_chain<T, 4, 1>(h, g, x, nrhs);
     } else {
-        if (nrhs <= 4) return run_chain<T, 4>(h, g, x, nrhs);
-        if (nrhs <= 8) return run_chain<T, 8>(h, g, x, nrhs);
-        return run_chain<T, 16>(h, g, x, nrhs);
+        if (nrhs <= 1) return run_chain<T, 1, 2>(h, g, x, nrhs);
+        if (nrhs <= 2) return run_chain<T, 2, 2>(h, g, x, nrhs);
+        if (nrhs <= 4) return run_chain<T, 4, 2>(h, g, x, nrhs);
+        if (nrhs <= 8) return run_chain<T, 8, 1>(h, g, x, nrhs);
+        return run_chain<T, 16, 1>(h, g, x, nrhs);
     }
 }
 
