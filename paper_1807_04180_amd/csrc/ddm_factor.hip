@@ -481,14 +481,32 @@ __global__ __launch_bounds__(NT) void k_factor_panel_r(const SubDesc *__restrict
             if (!(cabs2(piv_v) > tiny2) && status == 0) status = 1 + q.l * bs + k0 + t;
             const double rd = 1.0 / cabs2(piv_v);
             const double2 inv = make_double2(piv_v.x * rd, -piv_v.y * rd);
+            // the pivot row is read from LDS in two halves of 16, each half's
+            // reads issued together (sched_barrier keeps the compiler from
+            // interleaving them with the arithmetic one wait at a time)
+            constexpr int kH = kPanel / 2;
             if (tid == r) {
 #pragma unroll
-                for (int u = 0; u < kPanel; ++u) pr[u] = u == t ? inv : cmul(rowr[u], inv);
+                for (int h = 0; h < kPanel; h += kH) {
+                    double2 rr[kH];
+#pragma unroll
+                    for (int u = 0; u < kH; ++u) rr[u] = rowr[h + u];
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int u = 0; u < kH; ++u) pr[h + u] = h + u == t ? inv : cmul(rr[u], inv);
+                }
             } else {
                 const double2 f = cmul(pr[t], inv);
 #pragma unroll
-                for (int u = 0; u < kPanel; ++u)
-                    if (u != t) pr[u] = csub(pr[u], cmul(f, rowr[u]));
+                for (int h = 0; h < kPanel; h += kH) {
+                    double2 rr[kH];
+#pragma unroll
+                    for (int u = 0; u < kH; ++u) rr[u] = rowr[h + u];
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int u = 0; u < kH; ++u)
+                        if (h + u != t) pr[h + u] = csub(pr[h + u], cmul(f, rr[u]));
+                }
                 pr[t] = make_double2(-f.x, -f.y);
             }
         }

@@ -221,7 +221,8 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
     const int ld = s.ld;
     const int R = (bs + 64 * ROWS - 1) / (64 * ROWS);
     const int CG = kCWaves / R;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wave index is uniform: keep it (and what derives from it) scalar
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int rt = wv % R, cg = wv / R;
     const bool gemv = cg < CG;
     const int row = (rt * 64 + lane) * ROWS;  // this lane's first row

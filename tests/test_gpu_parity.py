@@ -213,6 +213,10 @@ def test_iterate_layouts_match_oracle(pair, layout):
 def test_chain_mixed_matches_oracle():
     w = CASES["2d-3x3-layered"]()
     o, g = make_pair(w, nrhs_max=20, mixed=True)
+    # block sizes (x extents) include odd ones: complex64 inverses are stored
+    # with an even column stride and read two rows per lane
+    bsz = [g.geometry(a)["ext_hi"][0] - g.geometry(a)["ext_lo"][0] + 1 for a in range(9)]
+    assert any(b % 2 for b in bsz) and any(b % 2 == 0 for b in bsz), bsz
     for nrhs in (3, 6, 9, 20):  # RHS tiles of 4, 8, 16 and 16 + a ragged 4
         gin = di.random_field((nrhs, o.etot), seed=51)
         assert relerr(_n(g.local_solve(_t(gin))), o.local_solve(gin), axis=1) < 5e-5
