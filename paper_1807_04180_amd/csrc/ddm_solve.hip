@@ -136,6 +136,7 @@ __global__ __launch_bounds__(kSThreads) void k_solve_line(const SubDesc *__restr
 // ---------------------------------------------------------------------------
 constexpr int kCThreads = 1024;
 constexpr int kCWaves = 16;
+constexpr size_t kLdsMax = 160 * 1024;  // LDS per workgroup on gfx950
 
 __device__ inline void wait_flag(int *f, int target, int *abort_flag, int spin_limit) {
     if (threadIdx.x == 0) {
@@ -204,15 +205,15 @@ __device__ inline void lds_prefetch(const T2 *Wl, T2 *dst, int cg, int CG, int b
     }
 }
 
-template <typename T2, int RT, int ROWS>
-__global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__restrict__ subs,
+template <typename T2, int RT, int ROWS, int NT>
+__global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ subs,
                                                            const Coef *__restrict__ coef, const T2 *__restrict__ W,
                                                            const T2 *__restrict__ g, T2 *__restrict__ x, int nrhs,
                                                            long long etot, int dim, int twisted, int *flags,
                                                            int *abort_flag, int spin_limit) {
     extern __shared__ unsigned char lds_raw[];
     using LT = typename LaneT<T2, ROWS>::type;
-    constexpr int kCBatch = RT >= 16 ? 4 : ChainBatch<T2, ROWS>::value;
+    constexpr int kCBatch = NT < kCThreads ? (RT >= 16 ? 4 : 8) : (RT >= 16 ? 4 : ChainBatch<T2, ROWS>::value);
     const int a = twisted ? (int)(blockIdx.x >> 1) : (int)blockIdx.x;
     const int chain = twisted ? (int)(blockIdx.x & 1) : 0;
     const SubDesc &s = subs[a];
@@ -220,12 +221,20 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
     const long long off = s.off;
     const int ld = s.ld;
     const int R = (bs + 64 * ROWS - 1) / (64 * ROWS);
+    // GEMV work units: (row tile rt, column group cg) pairs p = rt + R cg of
+    // a fixed partition into CG = 16 / R column groups, whatever the wave
+    // count, so that every variant adds the same partial sums in the same
+    // order; wave w takes pairs w, w + NW, ... (one pair with 16 waves, two
+    // with 8)
+    constexpr int NW = NT / 64;          // waves
+    constexpr int NP = kCWaves / NW;     // pairs per wave
     const int CG = kCWaves / R;
+    const int npair = R * CG;
     // the wave index is uniform: keep it (and what derives from it) scalar
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int rt = wv % R, cg = wv / R;
+    const int rt = wv % R, cg = wv / R;  // the wave's first pair
     const bool gemv = cg < CG;
-    const int row = (rt * 64 + lane) * ROWS;  // this lane's first row
+    const int row = (rt * 64 + lane) * ROWS;  // this lane's first row (first pair)
     const bool rowok = gemv && row < bs;
     const int bsp = R * 64 * ROWS;
     T2 *vs = (T2 *)lds_raw;                 // [bsp][RT]  current v
@@ -234,7 +243,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
     // copied to LDS by direct global->LDS loads while the block step
     // reduces, synchronises and forms the next v (the column stream would
     // otherwise idle there); the register stream starts after them
-    constexpr int PF = kLdsCols<T2, ROWS>::value;
+    constexpr int PF = NT == kCThreads ? kLdsCols<T2, ROWS>::value : 0;
     T2 *mypf = red + (size_t)CG * RT * bsp + (size_t)wv * PF * 64 * ROWS;  // [PF][64 lanes][ROWS]
     // this chain's block sequence: forward blocks, the middle, backward blocks
     const int nf = chain == 0 ? mid : nb - 1 - mid;
@@ -248,7 +257,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
         // initial v = g_{lfirst} (the middle step builds its own v)
         if (nf > 0) {
             const int l0 = lfirst;
-            for (int e = threadIdx.x; e < bsp * RT; e += kCThreads) {
+            for (int e = threadIdx.x; e < bsp * RT; e += NT) {
                 const int i = e / RT, q = e % RT;
                 vs[e] = (i < bs && q < nr) ? g[(long long)(r0 + q) * etot + off + (long long)l0 * bs + i]
                                            : czero<T2>();
@@ -292,7 +301,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
                         __hip_atomic_store(flags + 2 * a + chain, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                     wait_flag(flags + 2 * a + (1 - chain), epoch, abort_flag, spin_limit);
                 }
-                for (int e = threadIdx.x; e < bsp * RT; e += kCThreads) {
+                for (int e = threadIdx.x; e < bsp * RT; e += NT) {
                     const int i = e / RT, q = e % RT;
                     double2 v = make_double2(0, 0);
                     if (i < bs && q < nr) {
@@ -307,13 +316,13 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
             }
             // ---- prefetch the block-vector entries the reduction will need
             // (forward: g of the next block; backward: this block's y) ----
-            constexpr int kPre = (256 * RT + kCThreads - 1) / kCThreads;  // bsp * RT <= kPre * kCThreads
+            constexpr int kPre = (256 * RT + NT - 1) / NT;  // bsp * RT <= kPre * NT
             const int tn = t + 1;
             const int lnv = tn < nsteps && tn != nf ? step_l(tn) : -1;
             T2 pre[kPre];
 #pragma unroll
             for (int u = 0; u < kPre; ++u) {
-                const int e = threadIdx.x + u * kCThreads;
+                const int e = threadIdx.x + u * NT;
                 const int i = e / RT, q = e % RT;
                 const bool ok = e < bsp * RT && i < bs && q < nr;
                 const long long base = (long long)(ok ? r0 + q : 0) * etot + off;
@@ -321,57 +330,75 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
                 else if (kind == 0 && lnv >= 0) pre[u] = ok ? g[base + (long long)lnv * bs + i] : czero<T2>();
                 else pre[u] = czero<T2>();
             }
-            // ---- GEMV: acc = W_l v ----
-            T2 acc[ROWS][RT];
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r)
-#pragma unroll
-                for (int q = 0; q < RT; ++q) acc[r][q] = czero<T2>();
-            const int kmax = gemv ? (bs - cg + CG - 1) / CG : 0;  // columns of this wave
+            // ---- GEMV: acc = W_l v, per work pair of this wave ----
             const int lnext = t + 1 < nsteps ? step_l(t + 1) : -1;
-            if constexpr (PF > 0) {
-                __builtin_amdgcn_s_waitcnt(kWaitVm0);  // this wave's LDS copies have landed
-#pragma unroll 1
-                for (int u = 0; u < PF; ++u) {
-                    if (u < kmax) {
-                        const int j = cg + CG * u;
-                        const LT w = ((const LT *)mypf)[u * 64 + lane];
 #pragma unroll
-                        for (int r = 0; r < ROWS; ++r)
-#pragma unroll
-                            for (int q = 0; q < RT; ++q) cfma(acc[r][q], lane_row(w, r), vs[j * RT + q]);
-                    }
-                }
-            }
-            for (int k0 = PF; k0 < kmax; k0 += kCBatch) {
-                const bool more = k0 + kCBatch < kmax;
-                const int ln = more ? l : lnext;
-                const int kn = more ? k0 + kCBatch : PF;
-                LT wn[kCBatch];
-                const T2 *Wn = Wbase + (long long)(ln >= 0 ? ln : 0) * bs2;
-#pragma unroll
-                for (int u = 0; u < kCBatch; ++u) {
-                    const int j = cg + CG * (kn + u);
-                    wn[u] = (ln >= 0 && rowok && j < bs) ? *(const LT *)(Wn + (long long)j * ld + row) : lane_zero<LT>();
-                }
-#pragma unroll
-                for (int u = 0; u < kCBatch; ++u) {
-                    const int j = cg + CG * (k0 + u);
-                    if (j < bs) {
-#pragma unroll
-                        for (int r = 0; r < ROWS; ++r)
-#pragma unroll
-                            for (int q = 0; q < RT; ++q) cfma(acc[r][q], lane_row(wb[u], r), vs[j * RT + q]);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kCBatch; ++u) wb[u] = wn[u];
-            }
-            if (gemv) {
+            for (int pi = 0; pi < NP; ++pi) {
+                const int pp = wv + pi * NW;
+                if (pp >= npair) break;  // uniform
+                const int prt = pp % R, pcg = pp / R;
+                const int prow = (prt * 64 + lane) * ROWS;
+                const bool prowok = prow < bs;
+                // after this pair's last batch the stream continues with the
+                // wave's next pair of this block, else its first pair of the
+                // next block
+                const int pq = pp + NW;
+                const bool nextpair = pi + 1 < NP && pq < npair && pq / R < bs;  // next pair has columns
+                const int qrow = nextpair ? ((pq % R) * 64 + lane) * ROWS : row;
+                const int qcg = nextpair ? pq / R : cg;
+                const bool qrowok = nextpair ? qrow < bs : rowok;
+                T2 acc[ROWS][RT];
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-                    for (int q = 0; q < RT; ++q) red[((size_t)cg * RT + q) * bsp + row + r] = acc[r][q];
+                    for (int q = 0; q < RT; ++q) acc[r][q] = czero<T2>();
+                const int kmax = (bs - pcg + CG - 1) / CG;  // columns of this pair
+                if constexpr (PF > 0) {
+                    __builtin_amdgcn_s_waitcnt(kWaitVm0);  // this wave's LDS copies have landed
+#pragma unroll 1
+                    for (int u = 0; u < PF; ++u) {
+                        if (u < kmax) {
+                            const int j = pcg + CG * u;
+                            const LT w = ((const LT *)mypf)[u * 64 + lane];
+#pragma unroll
+                            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                                for (int q = 0; q < RT; ++q) cfma(acc[r][q], lane_row(w, r), vs[j * RT + q]);
+                        }
+                    }
+                }
+                for (int k0 = PF; k0 < kmax; k0 += kCBatch) {
+                    const bool more = k0 + kCBatch < kmax;
+                    const int ln = more || nextpair ? l : lnext;
+                    const int kn = more ? k0 + kCBatch : PF;
+                    const int ncg = more ? pcg : qcg;
+                    const int nrow = more ? prow : qrow;
+                    const bool nrowok = more ? prowok : qrowok;
+                    LT wn[kCBatch];
+                    const T2 *Wn = Wbase + (long long)(ln >= 0 ? ln : 0) * bs2;
+#pragma unroll
+                    for (int u = 0; u < kCBatch; ++u) {
+                        const int j = ncg + CG * (kn + u);
+                        wn[u] = (ln >= 0 && nrowok && j < bs) ? *(const LT *)(Wn + (long long)j * ld + nrow)
+                                                               : lane_zero<LT>();
+                    }
+#pragma unroll
+                    for (int u = 0; u < kCBatch; ++u) {
+                        const int j = pcg + CG * (k0 + u);
+                        if (j < bs) {
+#pragma unroll
+                            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                                for (int q = 0; q < RT; ++q) cfma(acc[r][q], lane_row(wb[u], r), vs[j * RT + q]);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kCBatch; ++u) wb[u] = wn[u];
+                }
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                    for (int q = 0; q < RT; ++q) red[((size_t)pcg * RT + q) * bsp + prow + r] = acc[r][q];
             }
             if (lnext >= 0)
                 lds_prefetch<T2, PF, ROWS>(Wbase + (long long)lnext * bs2, mypf, cg, CG, bs, ld, rowc, gemv);
@@ -379,7 +406,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain(const SubDesc *__rest
             // ---- reduce over column groups; update x; build the next v ----
 #pragma unroll
             for (int u = 0; u < kPre; ++u) {
-                const int e = threadIdx.x + u * kCThreads;
+                const int e = threadIdx.x + u * NT;
                 if (e >= bsp * RT) continue;
                 const int i = e / RT, q = e % RT;
                 if (i >= bs) continue;
@@ -450,7 +477,17 @@ static hipError_t run_perline(ddm_handle *h, const T *g, T *x, int nrhs) {
     return run_sweeps<T, 8>(h, g, x, nrhs);
 }
 
-template <typename T2, int RT, int ROWS>
+// dynamic LDS of the chain kernel: v, the column groups' partial sums and
+// the per-wave LDS column copies
+template <typename T2, int RT, int ROWS, int NT>
+static size_t chain_lds(int bs_max) {
+    const int R = (bs_max + 64 * ROWS - 1) / (64 * ROWS);
+    const int CG = kCWaves / R;
+    const int PF = NT == kCThreads ? kLdsCols<T2, ROWS>::value : 0;
+    return (size_t)R * 64 * ROWS * RT * (1 + CG) * sizeof(T2) + (size_t)(NT / 64) * PF * 64 * ROWS * sizeof(T2);
+}
+
+template <typename T2, int RT, int ROWS, int NT = kCThreads>
 static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     const Plan &P = h->plan;
     const double es = sizeof(T2);
@@ -461,10 +498,8 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     // y read back and x written
     ProfScope ps(h, DDM_K_SUBST, es * (2.0 * (double)P.fel * ntile + 4.0 * nrhs * vb));
     const int R = (P.bs_max + 64 * ROWS - 1) / (64 * ROWS);
-    const int CG = kCWaves / R;
-    size_t lds = (size_t)R * 64 * ROWS * RT * (1 + CG) * sizeof(T2) +
-                 (size_t)kCWaves * kLdsCols<T2, ROWS>::value * 64 * ROWS * sizeof(T2);
-    hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain<T2, RT, ROWS>,
+    const size_t lds = chain_lds<T2, RT, ROWS, NT>(P.bs_max);
+    hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain<T2, RT, ROWS, NT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (P.twisted) {
@@ -482,10 +517,10 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
         int a11 = h->spin_limit;
         void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11};
         // the two chains of a subdomain meet once: they must be co-resident
-        return hipLaunchCooperativeKernel((const void *)k_solve_chain<T2, RT, ROWS>, dim3(2 * P.nsub), dim3(kCThreads),
+        return hipLaunchCooperativeKernel((const void *)k_solve_chain<T2, RT, ROWS, NT>, dim3(2 * P.nsub), dim3(NT),
                                           args, lds, h->stream);
     }
-    k_solve_chain<T2, RT, ROWS><<<P.nsub, kCThreads, lds, h->stream>>>(h->d_subs, h->d_coef, (const T2 *)h->d_W, g, x,
+    k_solve_chain<T2, RT, ROWS, NT><<<P.nsub, NT, lds, h->stream>>>(h->d_subs, h->d_coef, (const T2 *)h->d_W, g, x,
                                                                  nrhs, P.etot, P.dim, 0, h->d_sync,
                                                                  h->d_sync + 2 * P.nsub, h->spin_limit);
     return hipGetLastError();
@@ -496,6 +531,14 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
     if constexpr (sizeof(T) == sizeof(double2)) {
         if (nrhs <= 1) return run_chain<T, 1, 1>(h, g, x, nrhs);
         if (nrhs <= 2) return run_chain<T, 2, 1>(h, g, x, nrhs);
+        if (nrhs <= 4) return run_chain<T, 4, 1>(h, g, x, nrhs);
+        // more RHS: 512-thread workgroups (256 VGPRs per lane) hold 8 or 16
+        // RHS per tile, so each inverse is streamed once per tile of 16;
+        // a twisted launch needs every workgroup resident (one per CU here)
+        const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= 256;
+        if (coop_ok && nrhs > 8 && chain_lds<T, 16, 1, 512>(h->plan.bs_max) <= kLdsMax)
+            return run_chain<T, 16, 1, 512>(h, g, x, nrhs);
+        if (coop_ok && chain_lds<T, 8, 1, 512>(h->plan.bs_max) <= kLdsMax) return run_chain<T, 8, 1, 512>(h, g, x, nrhs);
         return run_chain<T, 4, 1>(h, g, x, nrhs);
     } else {
         if (nrhs <= 1) return run_chain<T, 1, 2>(h, g, x, nrhs);
