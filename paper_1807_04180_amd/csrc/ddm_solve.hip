@@ -205,7 +205,7 @@ __device__ inline void lds_prefetch(const T2 *Wl, T2 *dst, int cg, int CG, int b
     }
 }
 
-template <typename T2, int RT, int ROWS, int NT>
+template <typename T2, int RT, int ROWS, int NT, int NPAIR>
 __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ subs,
                                                            const Coef *__restrict__ coef, const T2 *__restrict__ W,
                                                            const T2 *__restrict__ g, T2 *__restrict__ x, int nrhs,
@@ -222,13 +222,12 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
     const int ld = s.ld;
     const int R = (bs + 64 * ROWS - 1) / (64 * ROWS);
     // GEMV work units: (row tile rt, column group cg) pairs p = rt + R cg of
-    // a fixed partition into CG = 16 / R column groups, whatever the wave
-    // count, so that every variant adds the same partial sums in the same
-    // order; wave w takes pairs w, w + NW, ... (one pair with 16 waves, two
-    // with 8)
+    // a partition into CG = NPAIR / R column groups; NPAIR = 16 whatever the
+    // wave count for complex128, so that every variant adds the same partial
+    // sums in the same order; wave w takes pairs w, w + NW, ...
     constexpr int NW = NT / 64;          // waves
-    constexpr int NP = kCWaves / NW;     // pairs per wave
-    const int CG = kCWaves / R;
+    constexpr int NP = NPAIR / NW;      // pairs per wave
+    const int CG = NPAIR / R;
     const int npair = R * CG;
     // the wave index is uniform: keep it (and what derives from it) scalar
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -479,15 +478,15 @@ static hipError_t run_perline(ddm_handle *h, const T *g, T *x, int nrhs) {
 
 // dynamic LDS of the chain kernel: v, the column groups' partial sums and
 // the per-wave LDS column copies
-template <typename T2, int RT, int ROWS, int NT>
+template <typename T2, int RT, int ROWS, int NT, int NPAIR = kCWaves>
 static size_t chain_lds(int bs_max) {
     const int R = (bs_max + 64 * ROWS - 1) / (64 * ROWS);
-    const int CG = kCWaves / R;
+    const int CG = NPAIR / R;
     const int PF = NT == kCThreads ? kLdsCols<T2, ROWS>::value : 0;
     return (size_t)R * 64 * ROWS * RT * (1 + CG) * sizeof(T2) + (size_t)(NT / 64) * PF * 64 * ROWS * sizeof(T2);
 }
 
-template <typename T2, int RT, int ROWS, int NT = kCThreads>
+template <typename T2, int RT, int ROWS, int NT = kCThreads, int NPAIR = kCWaves>
 static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     const Plan &P = h->plan;
     const double es = sizeof(T2);
@@ -498,8 +497,8 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     // y read back and x written
     ProfScope ps(h, DDM_K_SUBST, es * (2.0 * (double)P.fel * ntile + 4.0 * nrhs * vb));
     const int R = (P.bs_max + 64 * ROWS - 1) / (64 * ROWS);
-    const size_t lds = chain_lds<T2, RT, ROWS, NT>(P.bs_max);
-    hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain<T2, RT, ROWS, NT>,
+    const size_t lds = chain_lds<T2, RT, ROWS, NT, NPAIR>(P.bs_max);
+    hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain<T2, RT, ROWS, NT, NPAIR>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (P.twisted) {
@@ -517,10 +516,10 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
         int a11 = h->spin_limit;
         void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11};
         // the two chains of a subdomain meet once: they must be co-resident
-        return hipLaunchCooperativeKernel((const void *)k_solve_chain<T2, RT, ROWS, NT>, dim3(2 * P.nsub), dim3(NT),
+        return hipLaunchCooperativeKernel((const void *)k_solve_chain<T2, RT, ROWS, NT, NPAIR>, dim3(2 * P.nsub), dim3(NT),
                                           args, lds, h->stream);
     }
-    k_solve_chain<T2, RT, ROWS, NT><<<P.nsub, NT, lds, h->stream>>>(h->d_subs, h->d_coef, (const T2 *)h->d_W, g, x,
+    k_solve_chain<T2, RT, ROWS, NT, NPAIR><<<P.nsub, NT, lds, h->stream>>>(h->d_subs, h->d_coef, (const T2 *)h->d_W, g, x,
                                                                  nrhs, P.etot, P.dim, 0, h->d_sync,
                                                                  h->d_sync + 2 * P.nsub, h->spin_limit);
     return hipGetLastError();
@@ -545,6 +544,11 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
         if (nrhs <= 2) return run_chain<T, 2, 2>(h, g, x, nrhs);
         if (nrhs <= 4) return run_chain<T, 4, 2>(h, g, x, nrhs);
         if (nrhs <= 8) return run_chain<T, 8, 1>(h, g, x, nrhs);
+        // 16 RHS with 16-byte loads needs the 256-VGPR budget of 512-thread
+        // workgroups (and 8 work pairs to fit the partial sums in LDS)
+        const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= 256;
+        if (coop_ok && chain_lds<T, 16, 2, 512, 8>(h->plan.bs_max) <= kLdsMax)
+            return run_chain<T, 16, 2, 512, 8>(h, g, x, nrhs);
         return run_chain<T, 16, 1>(h, g, x, nrhs);
     }
 }
