@@ -186,6 +186,88 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def run_study(args):
+    """Studies beyond the benchmark line (one JSON line with a table):
+    k-sweep: FGMRES(30) with K DDM steps per preconditioner application,
+        K in {1, 2, 3, 5, 10, 15, 20, 32}, on the 16x16 layouts of 2048^2
+        (constant and layered media, 4 RHS), FP64 and mixed, to relres 1e-6
+        (the preconditioner experiments of Sec. 4.2.2);
+    weak: the DDM as iterative solver on N x N subdomains of 300^2 cells with
+        30 PML cells, omega growing with N, a delta shot in the first
+        subdomain, to relres 1e-8 (the iterative-solver experiments of
+        Sec. 4.2.1), N in {2, 4, 8, 16}; FP64 where its factors fit (N <= 8),
+        mixed for every N."""
+    import numpy as np
+    import torch
+
+    import ddm_inputs as di
+    import paper_1807_04180_amd as ddm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rows = []
+
+    def run(w, mixed, fn):
+        k2 = torch.from_numpy(w.k2.reshape(-1)).to(dev)
+        f = torch.from_numpy(w.f.reshape(w.nrhs, -1)).to(dev)
+        t0 = time.perf_counter()
+        s = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=mixed), k2, w.nrhs)
+        torch.cuda.synchronize()
+        t_fac = time.perf_counter() - t0
+        try:
+            fn(s, f, t_fac)
+        finally:
+            s.close()
+            del k2, f
+            torch.cuda.empty_cache()
+
+    if args.study == "k-sweep":
+        for medium, build in (("constant", di.const_2d_2048), ("layered", lambda: di.layered_2d_2048(nrhs=4))):
+            w = build()
+            for mixed in (False, True):
+                def sweep(s, f, t_fac):
+                    u = torch.empty_like(f)
+                    s.solve(f, method="fgmres", tol=1e-6, maxiter=2000, restart=30, K=1, u=u)  # warm-up
+                    for K in (1, 2, 3, 5, 10, 15, 20, 32):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        _, info, st = s.solve(f, method="fgmres", tol=1e-6, maxiter=2000, restart=30, K=K, u=u)
+                        torch.cuda.synchronize()
+                        dt = time.perf_counter() - t0
+                        r = {"medium": medium, "precision": "mixed" if mixed else "fp64", "K": K,
+                             "gmres_iters": max(x["iters"] for x in info),
+                             "local_solves": max(x["local_solves"] for x in info),
+                             "relres_max": max(x["relres"] for x in info), "seconds": dt,
+                             "solves_per_s": w.nrhs / dt, "status": st}
+                        rows.append(r)
+                        log("study: %s %s K=%2d: %3d FGMRES iterations, %4d local solves, %.2f s, relres %.1e"
+                            % (medium, r["precision"], K, r["gmres_iters"], r["local_solves"], dt, r["relres_max"]))
+                run(w, mixed, sweep)
+    else:
+        for medium in ("constant", "layered"):
+            for N in (2, 4, 8, 16):
+                w = di.paper_weak(N, medium)
+                for mixed in ((False, True) if N <= 8 else (True,)):
+                    def it(s, f, t_fac):
+                        u = torch.empty_like(f)
+                        s.solve(f, method="stationary", tol=1e-8, maxiter=2000, u=u)  # warm-up
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        _, info, st = s.solve(f, method="stationary", tol=1e-8, maxiter=2000, u=u)
+                        torch.cuda.synchronize()
+                        dt = time.perf_counter() - t0
+                        steps = info[0]["iters"]
+                        r = {"medium": medium, "precision": "mixed" if mixed else "fp64", "N": N, "M": w.M[0],
+                             "n_ddm_iter": steps, "n_ddm_solve": steps / (2.0 * N), "relres": info[0]["relres"],
+                             "seconds": dt, "factor_s": t_fac, "status": st}
+                        rows.append(r)
+                        log("study: %s %s N=%2d (M=%d): %4d steps, n_DDM_Solve %.2f, %.2f s (factor %.2f s), "
+                            "relres %.1e" % (medium, r["precision"], N, w.M[0], steps, r["n_ddm_solve"], dt, t_fac,
+                                              r["relres"]))
+                    run(w, mixed, it)
+    print(json.dumps({"study": args.study, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +284,9 @@ def main():
     ap.add_argument("--tol", type=float, default=None, help="stationary/FGMRES tolerance (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FGMRES and mixed-precision legs")
+    ap.add_argument("--study", choices=["none", "k-sweep", "weak"], default="none",
+                    help="k-sweep: FGMRES preconditioner K sweep on 16x16 layouts; weak: iterative solver on "
+                         "N x N subdomains of 300^2 cells (prints one JSON line with the table)")
     ap.add_argument("--probe", choices=["none", "traffic"], default="none",
                     help="traffic: run 3 FP64 local solves of the workload and a 1 GiB device copy "
                          "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print nothing else")
@@ -210,6 +295,10 @@ def main():
         print("bench.py: the DDM step here runs on one GPU (there is no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.study != "none":
+        run_study(args)
+        return
 
     if args.workload == "serve":
         if args.tol is None:

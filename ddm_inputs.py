@@ -280,6 +280,49 @@ def serving_stream(n_requests: int = 48, rate: float = 4.0, grids=(256, 512, 102
     return out
 
 
+def const_2d_2048(nrhs: int = 4, M: int = 2048, N: int = 16) -> Workload:
+    """2D constant medium on the 16x16 layout of layered_2d_2048 (PML 20,
+    overlap 8): omega for 10 points per wavelength, nrhs seeded Gaussians
+    (s = 2h) with centres uniform in [0.1, 0.9]^2."""
+    n_pml, L = 20, 1.0
+    h = L / M
+    omega = 2 * math.pi * M / 10.0
+    s0 = sigma0_for_reflection(1e-6, omega, n_pml * h)
+    k2 = constant_k2(2, (M, M), n_pml, omega)
+    rng = np.random.default_rng(BASE_SEED + 6)
+    centres = rng.uniform(0.1, 0.9, size=(nrhs, 2))
+    f = np.stack([_gaussian_2d_window(M, n_pml, h, tuple(cc), 2 * h) for cc in centres])
+    return Workload("2d-const-%d-%dx%d" % (M, N, N), 2, (M, M), L, omega, n_pml, 8, (N, N), s0, k2, f)
+
+
+def paper_weak(N: int, medium: str = "constant", core: int = 300, n_pml: int = 30, n_ov: int = 8) -> Workload:
+    """Weak-scaling workload shaped like the iterative-solver experiments
+    (Sec. 4.2.1): N x N subdomains with core^2 cells each and n_pml PML
+    cells, a delta shot (1/h^2 at one node) a quarter and a third of a core
+    into the first subdomain; constant medium with omega/2pi = 25 N + 5, or
+    a seeded layered medium (layered_velocity, 1.5-4.5) with
+    omega/2pi = 12.5 N + 2.5.  The paper's overlap width is not stated:
+    n_ov cells here."""
+    M = core * N
+    L = 1.0
+    h = L / M
+    if medium == "constant":
+        omega = 2 * math.pi * (25 * N + 5)
+        c = None
+        k2 = constant_k2(2, (M, M), n_pml, omega)
+        c_min = c_max = 1.0
+    else:
+        omega = 2 * math.pi * (12.5 * N + 2.5)
+        c = layered_velocity(2, (M, M), n_pml, h, L, np.random.default_rng(BASE_SEED + 50 + N),
+                             smooth_cells=16.0 * M / 2048)
+        k2 = (omega / c) ** 2
+        c_min, c_max = float(c.min()), float(c.max())
+    s0 = sigma0_for_reflection(1e-6, omega / c_max, n_pml * h)
+    f = delta_shot(2, (M, M), n_pml, h, (core // 4, core // 3))[None]
+    return Workload("paper-weak-%s-N%d" % (medium, N), 2, (M, M), L, omega, n_pml, n_ov, (N, N), s0, k2, f,
+                    c_min=c_min, c_max=c_max)
+
+
 def const_3d_96(M: int = 96, N: int = 3, n_pml: int = 6, n_ov: int = 2) -> Workload:
     """3D constant medium, M = 96 (10 ppw, omega = 2 pi 9.6), PML 6, 3x3x3
     subdomains, overlap 2, Gaussian (s = 2h) at the centre."""

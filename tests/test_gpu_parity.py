@@ -346,3 +346,19 @@ def test_step_graph_replays_match_eager(case, mixed):
     uref = o.global_solve(w.f).reshape(w.nrhs, -1)
     assert relerr(_n(u1), uref, axis=1) < (1e-7 if mixed else 1e-8)
     g.close()
+
+
+def test_paper_weak_recipe_small():
+    """The weak-scaling recipe (delta shot a quarter / a third of a core into
+    the first subdomain, omega/2pi = 25 N + 5, 30-cell PML scaled down):
+    FP64 iterates match the oracle's and reach its global solution."""
+    w = di.paper_weak(2, "constant", core=48, n_pml=8, n_ov=4)
+    o, g = make_pair(w)
+    uo, _ = o.ddm_run(w.f, 6)
+    ug, _ = g.iterate(_t(w.f.reshape(1, -1)), 6)
+    assert relerr(_n(ug), uo, axis=1) < 1e-10
+    u, info, st = g.solve(_t(w.f.reshape(1, -1)), method="stationary", tol=1e-10, maxiter=200)
+    assert st == 0 and info[0]["relres"] <= 1e-10
+    uref = o.global_solve(w.f).reshape(1, -1)
+    assert relerr(_n(u), uref, axis=1) < 1e-8
+    g.close()

@@ -36,3 +36,25 @@ def test_serving_stream_is_seeded_and_follows_the_recipe():
     for r in a:
         by_key.setdefault(r.key, r.workload.k2)
         assert by_key[r.key] is r.workload.k2
+
+
+def test_paper_weak_recipe():
+    for N in (2, 3):
+        w = di.paper_weak(N, "constant", core=60, n_pml=10)
+        assert w.M == (60 * N, 60 * N) and w.N == (N, N)
+        assert abs(w.omega / (2 * np.pi) - (25 * N + 5)) < 1e-12
+        # one delta shot of mass 1 at node (15, 20): a quarter / a third of a core
+        nz = np.argwhere(w.f[0] != 0)
+        assert len(nz) == 1
+        iy, ix = nz[0]
+        assert (ix - (w.n_pml - 1), iy - (w.n_pml - 1)) == (15, 20)
+        assert abs(w.f[0][iy, ix] * w.h ** 2 - 1.0) < 1e-12
+    wl = di.paper_weak(2, "layered", core=60, n_pml=10)
+    assert abs(wl.omega / (2 * np.pi) - 27.5) < 1e-12 and 1.5 <= wl.c_min < wl.c_max <= 4.5
+
+
+def test_const_2048_layout_matches_layered():
+    a = di.const_2d_2048(nrhs=2, M=256, N=4)
+    b = di.layered_2d_2048(nrhs=2, M=256, N=4)
+    assert (a.M, a.N, a.n_pml, a.n_ov) == (b.M, b.N, b.n_pml, b.n_ov)
+    assert np.allclose(a.k2, a.omega ** 2)
