@@ -186,6 +186,63 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def gaussian_free_space_2d(x, y, k, centre, nq=256):
+    """Exact solution of Laplace(u) + k^2 u = f in the whole plane, radiating,
+    for the Gaussian f = A exp(-a r^2), A = 16 k^2 / pi^3, a = (4k/pi)^2
+    (Sec. 4.1.1), at the nodes x (columns) by y (rows).  The free-space Green
+    function is -(i/4) H0(k|x - y|); averaging it over the angle of y (Graf's
+    addition theorem) gives, with r = |x - centre|,
+        u(r) = -(i pi / 2) [H0(kr) I_J(r) + J0(kr) I_H(r)],
+        I_J(r) = int_0^r J0(k p) f(p) p dp,  I_H(r) = int_r^inf H0(k p) f(p) p dp,
+    and u'(r) = (i pi k / 2) [H1(kr) I_J(r) + J1(kr) I_H(r)].  Beyond the
+    source (a r^2 > 40) I_J is its full value exp(-pi^2/64) / (2 pi) and I_H
+    vanishes; inside, both are Gauss-Legendre sums of nq points.  Returns
+    (u, du/dx, du/dy) shaped [len(y), len(x)]."""
+    import numpy as np
+    from scipy.special import hankel1, jv
+
+    A = 16 * k * k / math.pi ** 3
+    a = (4 * k / math.pi) ** 2
+    X, Y = np.meshgrid(np.asarray(x, float) - centre[0], np.asarray(y, float) - centre[1], indexing="xy")
+    r = np.hypot(X, Y)
+    R = math.sqrt(40.0 / a)
+    IJ = np.full(r.shape, math.exp(-math.pi ** 2 / 64) / (2 * math.pi), dtype=np.complex128)
+    IH = np.zeros(r.shape, dtype=np.complex128)
+    near = r < R
+    if near.any():
+        t, wq = np.polynomial.legendre.leggauss(nq)
+        rn = r[near][:, None]
+        p = 0.5 * rn * (t + 1)                                  # [0, r]
+        IJ[near] = 0.5 * rn[:, 0] * (wq * jv(0, k * p) * A * np.exp(-a * p * p) * p).sum(1)
+        p = rn + 0.5 * (R - rn) * (t + 1)                       # [r, R]
+        IH[near] = 0.5 * (R - rn[:, 0]) * (wq * hankel1(0, k * p) * A * np.exp(-a * p * p) * p).sum(1)
+    kr = k * r
+    u = -0.5j * math.pi * (hankel1(0, kr) * IJ + jv(0, kr) * IH)
+    du = 0.5j * math.pi * k * (hankel1(1, kr) * IJ + jv(1, kr) * IH)
+    return u, du * X / r, du * Y / r
+
+
+def l2_h1_errors(uh, x, h, L, k, centre):
+    """Discrete L2 and H1 errors on the physical box [0, L]^2 of the nodal
+    solution uh ([len(x), len(x)], PML nodes included, node coordinates x on
+    both axes) against the free-space solution of the Gaussian source: the L2
+    part is the h^2-weighted sum over the physical nodes, the gradient part
+    compares the difference quotient on each physical mesh edge with the
+    exact derivative at the edge midpoint."""
+    import numpy as np
+    phys = (x >= -1e-9 * L) & (x <= L * (1 + 1e-9))
+    xp = x[phys]
+    up = uh[np.ix_(phys, phys)]
+    xm = 0.5 * (xp[1:] + xp[:-1])
+    u = gaussian_free_space_2d(xp, xp, k, centre)[0]
+    ux = gaussian_free_space_2d(xm, xp, k, centre)[1]
+    uy = gaussian_free_space_2d(xp, xm, k, centre)[2]
+    l2 = h * np.linalg.norm(up - u)
+    dx = (up[:, 1:] - up[:, :-1]) / h - ux
+    dy = (up[1:, :] - up[:-1, :]) / h - uy
+    h1 = math.sqrt(l2 * l2 + h * h * (np.linalg.norm(dx) ** 2 + np.linalg.norm(dy) ** 2))
+    return float(l2), float(h1)
+
 def run_study(args):
     """Studies beyond the benchmark line (one JSON line with a table):
     k-sweep: FGMRES(30) with K DDM steps per preconditioner application,
@@ -196,7 +253,14 @@ def run_study(args):
         30 PML cells, omega growing with N, a delta shot in the first
         subdomain, to relres 1e-8 (the iterative-solver experiments of
         Sec. 4.2.1), N in {2, 4, 8, 16}; FP64 where its factors fit (N <= 8),
-        mixed for every N."""
+        mixed for every N;
+    accuracy: the convergence experiment of Sec. 4.1.1 (Table 1): k/2pi = 25,
+        5x5 subdomains, the paper's Gaussian source, PML of fixed thickness
+        3/56, meshes 560^2, 1120^2 and 2240^2 (the larger ones of the table
+        need more than one GPU's HBM for FP64 factors); L2 and H1 errors on
+        the physical box of the FP64 DDM solution after N1 + N2 = 10 steps
+        (the paper's DDM solution) and after convergence to relres 1e-11,
+        against the exact free-space solution."""
     import numpy as np
     import torch
 
@@ -243,7 +307,7 @@ def run_study(args):
                         log("study: %s %s K=%2d: %3d FGMRES iterations, %4d local solves, %.2f s, relres %.1e"
                             % (medium, r["precision"], K, r["gmres_iters"], r["local_solves"], dt, r["relres_max"]))
                 run(w, mixed, sweep)
-    else:
+    elif args.study == "weak":
         for medium in ("constant", "layered"):
             for N in (2, 4, 8, 16):
                 w = di.paper_weak(N, medium)
@@ -265,6 +329,38 @@ def run_study(args):
                             "relres %.1e" % (medium, r["precision"], N, w.M[0], steps, r["n_ddm_solve"], dt, t_fac,
                                               r["relres"]))
                     run(w, mixed, it)
+    elif args.study == "accuracy":
+        k = 2 * math.pi * 25
+        c0 = di.PAPER_ACCURACY_CENTRE_2D
+        for scale in (1, 2, 4):
+            w = di.paper_accuracy_2d(scale)
+            x = di.node_coords(w.M[0], w.n_pml, w.h)
+
+            def acc(s, f, t_fac):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                u10, rel10 = s.iterate(f, sum(w.N))
+                torch.cuda.synchronize()
+                t10 = time.perf_counter() - t0
+                u = torch.empty_like(f)
+                _, info, st = s.solve(f, method="stationary", tol=1e-11, maxiter=200, u=u)
+                torch.cuda.synchronize()
+                r = {"mesh": 560 * scale, "local_core": 100 * scale, "n_pml": w.n_pml, "n_ov": w.n_ov,
+                     "factor_s": t_fac, "ddm_steps": sum(w.N), "ddm_s": t10, "relres_ddm": rel10[-1][0],
+                     "steps_to_1e-11": info[0]["iters"], "status": st}
+                for tag, uu in (("ddm", u10), ("converged", u)):
+                    e0, e1 = l2_h1_errors(uu.cpu().numpy().reshape(len(x), len(x)), x, w.h, w.L, k, c0)
+                    r[tag + "_l2"], r[tag + "_h1"] = e0, e1
+                if rows:
+                    for key in ("ddm_l2", "ddm_h1"):
+                        r[key + "_rate"] = math.log(rows[-1][key] / r[key], 2)
+                rows.append(r)
+                log("study: mesh %d^2: factor %.1f s; %d DDM steps %.3f s (relres %.1e): L2 %.3e H1 %.3e%s; "
+                    "converged (%d steps to 1e-11): L2 %.3e H1 %.3e"
+                    % (r["mesh"], t_fac, r["ddm_steps"], t10, r["relres_ddm"], r["ddm_l2"], r["ddm_h1"],
+                       "" if "ddm_l2_rate" not in r else " (rates %.2f, %.2f)" % (r["ddm_l2_rate"], r["ddm_h1_rate"]),
+                       r["steps_to_1e-11"], r["converged_l2"], r["converged_h1"]))
+            run(w, False, acc)
     print(json.dumps({"study": args.study, "rows": rows}), flush=True)
 
 
@@ -284,9 +380,10 @@ def main():
     ap.add_argument("--tol", type=float, default=None, help="stationary/FGMRES tolerance (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FGMRES and mixed-precision legs")
-    ap.add_argument("--study", choices=["none", "k-sweep", "weak"], default="none",
+    ap.add_argument("--study", choices=["none", "k-sweep", "weak", "accuracy"], default="none",
                     help="k-sweep: FGMRES preconditioner K sweep on 16x16 layouts; weak: iterative solver on "
-                         "N x N subdomains of 300^2 cells (prints one JSON line with the table)")
+                         "N x N subdomains of 300^2 cells; accuracy: L2/H1 errors against the free-space solution "
+                         "on 560^2-2240^2 meshes (prints one JSON line with the table)")
     ap.add_argument("--probe", choices=["none", "traffic"], default="none",
                     help="traffic: run 3 FP64 local solves of the workload and a 1 GiB device copy "
                          "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print nothing else")

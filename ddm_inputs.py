@@ -323,6 +323,31 @@ def paper_weak(N: int, medium: str = "constant", core: int = 300, n_pml: int = 3
                     c_min=c_min, c_max=c_max)
 
 
+def paper_accuracy_2d(scale: int) -> Workload:
+    """The 2D convergence experiment (Sec. 4.1.1, Table 1): the box
+    [-1/2, 1/2]^2 meshed with 560*scale cells per side, of which the outer
+    3/56 on each side is PML (30*scale cells), leaving the physical box
+    [-25/56, 25/56]^2 of 500*scale cells split into 5 x 5 subdomains of
+    (100*scale)^2 cells.  k/2pi = 25 (constant medium) and the paper's
+    Gaussian source centred at (0.09, 0.268).  Stored on [0, 25/28]^2, i.e.
+    shifted by 25/56 (the centre becomes (0.09 + 25/56, 0.268 + 25/56)).
+    Overlap 8*scale cells (a fixed physical width); sigma0 for a PML
+    reflection of 1e-8."""
+    M = 500 * scale
+    L = 25.0 / 28.0
+    h = L / M
+    k = 2 * math.pi * 25
+    n_pml = 30 * scale
+    s0 = sigma0_for_reflection(1e-8, k, n_pml * h)
+    k2 = constant_k2(2, (M, M), n_pml, k)
+    f = paper_gaussian_source(2, (M, M), n_pml, h, L, PAPER_ACCURACY_CENTRE_2D, k)[None]
+    return Workload("paper-accuracy-2d-%d" % (560 * scale), 2, (M, M), L, k, n_pml, 8 * scale, (5, 5), s0, k2, f)
+
+
+# source centre of the 2D convergence experiment on the stored box [0, 25/28]^2
+PAPER_ACCURACY_CENTRE_2D = (0.09 + 25.0 / 56.0, 0.268 + 25.0 / 56.0)
+
+
 def const_3d_96(M: int = 96, N: int = 3, n_pml: int = 6, n_ov: int = 2) -> Workload:
     """3D constant medium, M = 96 (10 ppw, omega = 2 pi 9.6), PML 6, 3x3x3
     subdomains, overlap 2, Gaussian (s = 2h) at the centre."""

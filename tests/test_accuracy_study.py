@@ -1,0 +1,126 @@
+"""Pins of the accuracy study's yardstick (Sec. 4.1.1, Table 1): the exact
+free-space solution of the paper's 2D Gaussian source, its gradient, and the
+discrete L2/H1 error norms the study reports.
+
+* The exact solution is a sum of two Gauss-Legendre quadratures inside the
+  source and a closed form outside it: the two branches agree where they
+  meet, and the quadrature branch satisfies Laplace(u) + k^2 u = f (checked
+  with a fine five-point stencil, which shares nothing with the quadrature).
+* The returned gradient matches central differences of u.
+* The oracle's discrete solution of a smaller-k copy of the experiment
+  (k/2pi = 5, same points per wavelength, same source shape and PML width in
+  cells per wavelength) converges to it at the second order printed in
+  Table 1, in both norms.
+* On the GPU (tests/test_gpu_parity.py) the DDM solution of the 560^2 mesh
+  itself lands on Table 1's L2 error.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import bench
+import ddm_inputs as di
+from oracle import Oracle
+
+K25 = 2 * math.pi * 25
+
+
+def _source(x, y, k, c0):
+    a = (4 * k / math.pi) ** 2
+    X, Y = np.meshgrid(np.asarray(x) - c0[0], np.asarray(y) - c0[1], indexing="xy")
+    return 16 * k * k / math.pi ** 3 * np.exp(-a * (X * X + Y * Y))
+
+
+def test_exact_solution_branches_meet_at_the_source_edge():
+    k = K25
+    c0 = (0.3, 0.4)
+    R = math.sqrt(40.0) / (4 * k / math.pi)
+    xs = np.array([c0[0] + R * (1 - 1e-13), c0[0] + R * (1 + 1e-13)])
+    u, ux, uy = bench.gaussian_free_space_2d(xs, [c0[1]], k, c0)
+    assert abs(u[0, 0] - u[0, 1]) < 1e-10 * abs(u[0, 0])
+    assert abs(ux[0, 0] - ux[0, 1]) < 1e-10 * abs(ux[0, 0])
+    assert abs(uy[0, 0]) < 1e-12 * abs(ux[0, 0]) + 1e-300
+
+
+@pytest.mark.parametrize("frac", [0.05, 0.2, 0.5, 0.9, 1.5])
+def test_exact_solution_satisfies_helmholtz(frac):
+    k = K25
+    c0 = (0.0, 0.0)
+    a = (4 * k / math.pi) ** 2
+    R = math.sqrt(40.0 / a)
+    p = (frac * R * math.cos(0.7), frac * R * math.sin(0.7))
+    d = 1e-3 / math.sqrt(a)
+    x = p[0] + d * np.arange(-1, 2)
+    y = p[1] + d * np.arange(-1, 2)
+    u = bench.gaussian_free_space_2d(x, y, k, c0)[0]
+    lap = (u[1, 0] + u[1, 2] + u[0, 1] + u[2, 1] - 4 * u[1, 1]) / (d * d)
+    f = _source([p[0]], [p[1]], k, c0)[0, 0]
+    res = lap + k * k * u[1, 1] - f
+    # O(d^2) stencil error and rounding of the 1/d^2 difference
+    assert abs(res) < 1e-5 * (k * k * abs(u[1, 1]) + abs(f)), (frac, res, f)
+
+
+def test_exact_gradient_matches_differences():
+    k = K25
+    c0 = (0.0, 0.0)
+    d = 1e-7
+    for p in ((0.004, 0.003), (0.02, -0.011), (0.2, 0.1)):
+        u, ux, uy = bench.gaussian_free_space_2d([p[0]], [p[1]], k, c0)
+        up = bench.gaussian_free_space_2d([p[0] - d, p[0] + d], [p[1]], k, c0)[0]
+        vp = bench.gaussian_free_space_2d([p[0]], [p[1] - d, p[1] + d], k, c0)[0]
+        gx = (up[0, 1] - up[0, 0]) / (2 * d)
+        gy = (vp[1, 0] - vp[0, 0]) / (2 * d)
+        assert abs(gx - ux[0, 0]) < 1e-6 * abs(ux[0, 0])
+        assert abs(gy - uy[0, 0]) < 1e-6 * abs(uy[0, 0])
+
+
+def _small_copy_errors(scale):
+    # the Table 1 setting at k/2pi = 5: 112 cells per unit length at scale 1
+    # (22.4 per wavelength, as 560 at k/2pi = 25), 100 physical cells, PML 6
+    k = 2 * math.pi * 5
+    M = 100 * scale
+    L = 100 / 112
+    h = L / M
+    n_pml = 6 * scale
+    c0 = (L / 2 + 0.09, L / 2 + 0.05)
+    s0 = di.sigma0_for_reflection(1e-8, k, n_pml * h)
+    k2 = di.constant_k2(2, (M, M), n_pml, k)
+    f = di.paper_gaussian_source(2, (M, M), n_pml, h, L, c0, k)
+    u = Oracle(2, (M, M), h, n_pml, s0, (1, 1), 2, k2).global_solve(f).reshape(f.shape)
+    return bench.l2_h1_errors(u, di.node_coords(M, n_pml, h), h, L, k, c0)
+
+
+def test_discrete_solution_converges_at_second_order():
+    (l2a, h1a), (l2b, h1b) = _small_copy_errors(1), _small_copy_errors(2)
+    assert 3.7 < l2a / l2b < 4.3, (l2a, l2b)
+    assert 3.7 < h1a / h1b < 4.3, (h1a, h1b)
+    assert l2b < 1e-3
+
+
+def test_error_norms_on_exact_data_vanish():
+    k = K25
+    c0 = (0.45, 0.5)
+    M, n_pml = 40, 3
+    L = 0.9
+    h = L / M
+    x = di.node_coords(M, n_pml, h)
+    u = bench.gaussian_free_space_2d(x, x, k, c0)[0]
+    l2, h1 = bench.l2_h1_errors(u, x, h, L, k, c0)
+    assert l2 == 0.0
+    assert h1 > 0.0   # difference quotients differ from exact derivatives
+    # a constant shift e on the (M + 1)^2 physical nodes: L2 error h |e| (M + 1)
+    l2s, _ = bench.l2_h1_errors(u + 1e-3, x, h, L, k, c0)
+    assert abs(l2s - 1e-3 * h * (M + 1)) < 1e-12
+
+
+def test_paper_accuracy_recipe(golden):
+    t = golden["table1_2d_convergence"]
+    for scale in (1, 2):
+        w = di.paper_accuracy_2d(scale)
+        assert w.M[0] + 2 * w.n_pml == t["mesh"][scale - 1]
+        assert w.M[0] // w.N[0] == t["local_size_without_pml"][scale - 1]
+        assert abs(w.n_pml * w.h - 3.0 / 56.0) < 1e-12
+        assert abs(w.omega / (2 * math.pi) - 25) < 1e-12
+        # unit-mass source, all of it inside the physical box
+        assert abs(w.f.real.sum() * w.h ** 2 - 1) < 1e-9

@@ -362,3 +362,20 @@ def test_paper_weak_recipe_small():
     uref = o.global_solve(w.f).reshape(1, -1)
     assert relerr(_n(u), uref, axis=1) < 1e-8
     g.close()
+
+
+def test_paper_accuracy_560_lands_on_table1(golden):
+    """Sec. 4.1.1: the DDM solution (N1 + N2 = 10 steps) of the 560^2 mesh,
+    k/2pi = 25, 5x5 subdomains, against the exact free-space solution: its L2
+    error on the physical box is Table 1's 3.13e-3 (within 2 %)."""
+    import math
+    import bench
+    w = di.paper_accuracy_2d(1)
+    g = ddm.HelmholtzDDM(ddm.Problem.from_workload(w), _t(w.k2.reshape(-1)), 1)
+    u, _ = g.iterate(_t(w.f.reshape(1, -1)), sum(w.N))
+    g.close()
+    x = di.node_coords(w.M[0], w.n_pml, w.h)
+    l2, _ = bench.l2_h1_errors(_n(u).reshape(len(x), len(x)), x, w.h, w.L, w.omega, di.PAPER_ACCURACY_CENTRE_2D)
+    ref = golden["table1_2d_convergence"]["l2_error"][0]
+    assert abs(l2 - ref) < 0.02 * ref, (l2, ref)
+    assert math.isfinite(l2)
