@@ -222,25 +222,72 @@ def gaussian_free_space_2d(x, y, k, centre, nq=256):
     return u, du * X / r, du * Y / r
 
 
-def l2_h1_errors(uh, x, h, L, k, centre):
-    """Discrete L2 and H1 errors on the physical box [0, L]^2 of the nodal
-    solution uh ([len(x), len(x)], PML nodes included, node coordinates x on
-    both axes) against the free-space solution of the Gaussian source: the L2
-    part is the h^2-weighted sum over the physical nodes, the gradient part
-    compares the difference quotient on each physical mesh edge with the
-    exact derivative at the edge midpoint."""
+def gaussian_free_space_3d(x, y, z, k, centre, nq=256):
+    """Exact radiating solution of Laplace(u) + k^2 u = f in space for the
+    Gaussian f = A exp(-a r^2), A = 64 k^3 / pi^(9/2), a = (4k/pi)^2
+    (Sec. 4.1.2), at the nodes x by y by z.  The Green function
+    -exp(ik|x - y|) / (4 pi |x - y|) averaged over spheres keeps only the
+    l = 0 term of its addition theorem, sin(k r_<) exp(ik r_>) / (4 pi k r_< r_>),
+    so with r = |x - centre|
+        u(r) = -(1/(k r)) [exp(ikr) I_S(r) + sin(kr) I_E(r)],
+        I_S(r) = int_0^r f(p) p sin(k p) dp,  I_E(r) = int_r^inf f(p) p exp(ik p) dp,
+    and u'(r) = -(1/k) [(ikr - 1) exp(ikr) I_S + (kr cos(kr) - sin(kr)) I_E] / r^2.
+    Beyond the source (a r^2 > 40) I_S = k exp(-pi^2/64) / (4 pi) and I_E = 0;
+    inside, both are Gauss-Legendre sums of nq points.  Returns (u, du/dx,
+    du/dy, du/dz) shaped [len(z), len(y), len(x)]."""
     import numpy as np
+
+    A = 64 * k ** 3 / math.pi ** 4.5
+    a = (4 * k / math.pi) ** 2
+    Z, Y, X = np.meshgrid(np.asarray(z, float) - centre[2], np.asarray(y, float) - centre[1],
+                          np.asarray(x, float) - centre[0], indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    R = math.sqrt(40.0 / a)
+    IS = np.full(r.shape, k * math.exp(-math.pi ** 2 / 64) / (4 * math.pi), dtype=np.complex128)
+    IE = np.zeros(r.shape, dtype=np.complex128)
+    near = r < R
+    if near.any():
+        t, wq = np.polynomial.legendre.leggauss(nq)
+        rn = r[near][:, None]
+        p = 0.5 * rn * (t + 1)
+        IS[near] = 0.5 * rn[:, 0] * (wq * A * np.exp(-a * p * p) * p * np.sin(k * p)).sum(1)
+        p = rn + 0.5 * (R - rn) * (t + 1)
+        IE[near] = 0.5 * (R - rn[:, 0]) * (wq * A * np.exp(-a * p * p) * p * np.exp(1j * k * p)).sum(1)
+    kr = k * r
+    e = np.exp(1j * kr)
+    u = -(e * IS + np.sin(kr) * IE) / kr
+    du = -((1j * kr - 1) * e * IS + (kr * np.cos(kr) - np.sin(kr)) * IE) / (k * r * r)
+    return u, du * X / r, du * Y / r, du * Z / r
+
+
+def l2_h1_errors(uh, x, h, L, k, centre):
+    """Discrete L2 and H1 errors on the physical box [0, L]^dim of the nodal
+    solution uh (C order [z][y][x], PML nodes included, node coordinates x on
+    every axis) against the free-space solution of the paper's Gaussian
+    source (dim = len(centre)): the L2 part is the h^dim-weighted sum over the
+    physical nodes, the gradient part compares the difference quotient on
+    each physical mesh edge with the exact derivative at the edge midpoint."""
+    import numpy as np
+    dim = len(centre)
     phys = (x >= -1e-9 * L) & (x <= L * (1 + 1e-9))
     xp = x[phys]
-    up = uh[np.ix_(phys, phys)]
     xm = 0.5 * (xp[1:] + xp[:-1])
-    u = gaussian_free_space_2d(xp, xp, k, centre)[0]
-    ux = gaussian_free_space_2d(xm, xp, k, centre)[1]
-    uy = gaussian_free_space_2d(xp, xm, k, centre)[2]
-    l2 = h * np.linalg.norm(up - u)
-    dx = (up[:, 1:] - up[:, :-1]) / h - ux
-    dy = (up[1:, :] - up[:-1, :]) / h - uy
-    h1 = math.sqrt(l2 * l2 + h * h * (np.linalg.norm(dx) ** 2 + np.linalg.norm(dy) ** 2))
+    up = uh[np.ix_(*([phys] * dim))]
+    if dim == 2:
+        exact = lambda xs: gaussian_free_space_2d(xs[0], xs[1], k, centre)
+    else:
+        exact = lambda xs: gaussian_free_space_3d(xs[0], xs[1], xs[2], k, centre)
+    w = h ** (dim / 2.0)
+    l2 = w * np.linalg.norm(up - exact([xp] * dim)[0])
+    g2 = 0.0
+    for d in range(dim):   # axis d of x is array axis dim - 1 - d
+        xs = [xp] * dim
+        xs[d] = xm
+        ax = dim - 1 - d
+        n = up.shape[ax]
+        dq = (np.take(up, range(1, n), axis=ax) - np.take(up, range(n - 1), axis=ax)) / h
+        g2 += np.linalg.norm(dq - exact(xs)[1 + d]) ** 2
+    h1 = math.sqrt(l2 * l2 + w * w * g2)
     return float(l2), float(h1)
 
 def run_study(args):
@@ -260,7 +307,11 @@ def run_study(args):
         need more than one GPU's HBM for FP64 factors); L2 and H1 errors on
         the physical box of the FP64 DDM solution after N1 + N2 = 10 steps
         (the paper's DDM solution) and after convergence to relres 1e-11,
-        against the exact free-space solution."""
+        against the exact free-space solution;
+    accuracy-3d: the same for Sec. 4.1.2 (Table 2): k/2pi = 10, 3x3x3
+        subdomains, meshes 80^3 and 96^3 (the larger ones need more HBM than
+        one GPU has for dense plane-block inverses), N1 + N2 + N3 = 9 steps,
+        FP64 and mixed precision."""
     import numpy as np
     import torch
 
@@ -361,6 +412,44 @@ def run_study(args):
                        "" if "ddm_l2_rate" not in r else " (rates %.2f, %.2f)" % (r["ddm_l2_rate"], r["ddm_h1_rate"]),
                        r["steps_to_1e-11"], r["converged_l2"], r["converged_h1"]))
             run(w, False, acc)
+    elif args.study == "accuracy-3d":
+        k = 2 * math.pi * 10
+        c0 = di.PAPER_ACCURACY_CENTRE_3D
+        for mesh in (80, 96):
+            w = di.paper_accuracy_3d(mesh)
+            x = di.node_coords(w.M[0], w.n_pml, w.h)
+            for mixed in (False, True):
+                def acc3(s, f, t_fac):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    u9, rel9 = s.iterate(f, sum(w.N))
+                    torch.cuda.synchronize()
+                    t9 = time.perf_counter() - t0
+                    u = torch.empty_like(f)
+                    tol = 1e-7 if mixed else 1e-10
+                    _, info, st = s.solve(f, method="stationary", tol=tol, maxiter=200, u=u)
+                    torch.cuda.synchronize()
+                    r = {"mesh": mesh, "local_core": w.M[0] // 3, "n_pml": w.n_pml, "n_ov": w.n_ov,
+                         "precision": "mixed" if mixed else "fp64", "factor_s": t_fac, "ddm_steps": sum(w.N),
+                         "ddm_s": t9, "relres_ddm": rel9[-1][0], "tol": tol, "steps_to_tol": info[0]["iters"],
+                         "status": st}
+                    n = len(x)
+                    for tag, uu in (("ddm", u9), ("converged", u)):
+                        e0, e1 = l2_h1_errors(uu.cpu().numpy().reshape(n, n, n), x, w.h, w.L, k, c0)
+                        r[tag + "_l2"], r[tag + "_h1"] = e0, e1
+                    prev = [q for q in rows if q["precision"] == r["precision"]]
+                    if prev:
+                        for key in ("ddm_l2", "ddm_h1"):
+                            r[key + "_rate"] = math.log(prev[-1][key] / r[key]) / math.log(mesh / prev[-1]["mesh"])
+                    rows.append(r)
+                    log("study: mesh %d^3 %s: factor %.1f s; %d DDM steps %.3f s (relres %.1e): L2 %.3e H1 %.3e%s; "
+                        "to %.0e in %d steps: L2 %.3e H1 %.3e"
+                        % (mesh, r["precision"], t_fac, r["ddm_steps"], t9, r["relres_ddm"], r["ddm_l2"], r["ddm_h1"],
+                           "" if "ddm_l2_rate" not in r else " (rates %.2f, %.2f)" % (r["ddm_l2_rate"], r["ddm_h1_rate"]),
+                           tol, r["steps_to_tol"], r["converged_l2"], r["converged_h1"]))
+                log("study: mesh %d^3 %s: factorising (%.0f GB)" % (mesh, "mixed" if mixed else "fp64",
+                    ddm.Problem.from_workload(w, mixed=mixed).memory_required(1) / 1e9))
+                run(w, mixed, acc3)
     print(json.dumps({"study": args.study, "rows": rows}), flush=True)
 
 
@@ -380,10 +469,11 @@ def main():
     ap.add_argument("--tol", type=float, default=None, help="stationary/FGMRES tolerance (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FGMRES and mixed-precision legs")
-    ap.add_argument("--study", choices=["none", "k-sweep", "weak", "accuracy"], default="none",
+    ap.add_argument("--study", choices=["none", "k-sweep", "weak", "accuracy", "accuracy-3d"], default="none",
                     help="k-sweep: FGMRES preconditioner K sweep on 16x16 layouts; weak: iterative solver on "
                          "N x N subdomains of 300^2 cells; accuracy: L2/H1 errors against the free-space solution "
-                         "on 560^2-2240^2 meshes (prints one JSON line with the table)")
+                         "on 560^2-2240^2 meshes; accuracy-3d: the same on 80^3 and 96^3 (prints one JSON line "
+                         "with the table)")
     ap.add_argument("--probe", choices=["none", "traffic"], default="none",
                     help="traffic: run 3 FP64 local solves of the workload and a 1 GiB device copy "
                          "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print nothing else")

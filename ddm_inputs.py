@@ -344,8 +344,32 @@ def paper_accuracy_2d(scale: int) -> Workload:
     return Workload("paper-accuracy-2d-%d" % (560 * scale), 2, (M, M), L, k, n_pml, 8 * scale, (5, 5), s0, k2, f)
 
 
+def paper_accuracy_3d(mesh: int) -> Workload:
+    """The 3D convergence experiment (Sec. 4.1.2, Table 2): the box
+    [-1/2, 1/2]^3 meshed with `mesh` cells per side (a multiple of 8), of
+    which the outer 1/8 on each side is PML, leaving the physical box
+    [-3/8, 3/8]^3 of 3 mesh / 4 cells split into 3 x 3 x 3 subdomains.
+    k/2pi = 10 (constant medium), the paper's Gaussian source centred at
+    (0.12, 0.133, 0.125).  Stored on [0, 3/4]^3 (shifted by 3/8); overlap
+    mesh / 20 cells rounded (4 at 80, 5 at 96); sigma0 for R = 1e-8."""
+    if mesh % 8:
+        raise ValueError("mesh must be a multiple of 8")
+    M = 3 * mesh // 4
+    L = 0.75
+    h = L / M
+    k = 2 * math.pi * 10
+    n_pml = mesh // 8
+    s0 = sigma0_for_reflection(1e-8, k, n_pml * h)
+    k2 = constant_k2(3, (M, M, M), n_pml, k)
+    f = paper_gaussian_source(3, (M, M, M), n_pml, h, L, PAPER_ACCURACY_CENTRE_3D, k)[None]
+    return Workload("paper-accuracy-3d-%d" % mesh, 3, (M, M, M), L, k, n_pml, int(round(mesh / 20)), (3, 3, 3),
+                    s0, k2, f)
+
+
 # source centre of the 2D convergence experiment on the stored box [0, 25/28]^2
 PAPER_ACCURACY_CENTRE_2D = (0.09 + 25.0 / 56.0, 0.268 + 25.0 / 56.0)
+# and of the 3D one on [0, 3/4]^3
+PAPER_ACCURACY_CENTRE_3D = (0.12 + 0.375, 0.133 + 0.375, 0.125 + 0.375)
 
 
 def const_3d_96(M: int = 96, N: int = 3, n_pml: int = 6, n_ov: int = 2) -> Workload:

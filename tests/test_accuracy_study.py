@@ -1,12 +1,13 @@
-"""Pins of the accuracy study's yardstick (Sec. 4.1.1, Table 1): the exact
-free-space solution of the paper's 2D Gaussian source, its gradient, and the
-discrete L2/H1 error norms the study reports.
+"""Pins of the accuracy study's yardstick (Sec. 4.1, Tables 1-2): the exact
+free-space solutions of the paper's 2D and 3D Gaussian sources, their
+gradients, and the discrete L2/H1 error norms the study reports.
 
 * The exact solution is a sum of two Gauss-Legendre quadratures inside the
   source and a closed form outside it: the two branches agree where they
   meet, and the quadrature branch satisfies Laplace(u) + k^2 u = f (checked
   with a fine five-point stencil, which shares nothing with the quadrature).
-* The returned gradient matches central differences of u.
+* The same for the 3D solution (seven-point stencil).
+* The returned gradients match central differences of u.
 * The oracle's discrete solution of a smaller-k copy of the experiment
   (k/2pi = 5, same points per wavelength, same source shape and PML width in
   cells per wavelength) converges to it at the second order printed in
@@ -124,3 +125,61 @@ def test_paper_accuracy_recipe(golden):
         assert abs(w.omega / (2 * math.pi) - 25) < 1e-12
         # unit-mass source, all of it inside the physical box
         assert abs(w.f.real.sum() * w.h ** 2 - 1) < 1e-9
+
+
+def test_paper_accuracy_3d_recipe(golden):
+    t = golden["table2_3d_convergence"]
+    for mesh, core in zip(t["mesh"][:2], t["local_size_without_pml"][:2]):
+        w = di.paper_accuracy_3d(mesh)
+        assert w.M[0] + 2 * w.n_pml == mesh and w.M[0] // w.N[0] == core
+        assert abs(w.n_pml * w.h - 1.0 / 8.0) < 1e-12
+        assert abs(w.f.real.sum() * w.h ** 3 - 1) < 1e-4   # unit mass, sampled at ~1 node per e-fold
+
+
+K10 = 2 * math.pi * 10
+
+
+def _source3(p, k):
+    a = (4 * k / math.pi) ** 2
+    return 64 * k ** 3 / math.pi ** 4.5 * math.exp(-a * sum(c * c for c in p))
+
+
+def test_exact_3d_branches_meet_at_the_source_edge():
+    k = K10
+    c0 = (0.3, 0.4, 0.2)
+    R = math.sqrt(40.0) / (4 * k / math.pi)
+    xs = np.array([c0[0] + R * (1 - 1e-13), c0[0] + R * (1 + 1e-13)])
+    u, ux, uy, uz = bench.gaussian_free_space_3d(xs, [c0[1]], [c0[2]], k, c0)
+    assert abs(u[0, 0, 0] - u[0, 0, 1]) < 1e-10 * abs(u[0, 0, 0])
+    assert abs(ux[0, 0, 0] - ux[0, 0, 1]) < 1e-10 * abs(ux[0, 0, 0])
+
+
+@pytest.mark.parametrize("frac", [0.05, 0.3, 0.8, 1.4])
+def test_exact_3d_solution_satisfies_helmholtz(frac):
+    k = K10
+    c0 = (0.0, 0.0, 0.0)
+    a = (4 * k / math.pi) ** 2
+    R = math.sqrt(40.0 / a)
+    p = frac * R * np.array([0.48, 0.6, 0.64])
+    d = 1e-3 / math.sqrt(a)
+    x, y, z = (p[i] + d * np.arange(-1, 2) for i in range(3))
+    u = bench.gaussian_free_space_3d(x, y, z, k, c0)[0]
+    lap = (u[1, 1, 0] + u[1, 1, 2] + u[1, 0, 1] + u[1, 2, 1] + u[0, 1, 1] + u[2, 1, 1] - 6 * u[1, 1, 1]) / (d * d)
+    f = _source3(p, k)
+    res = lap + k * k * u[1, 1, 1] - f
+    assert abs(res) < 1e-5 * (k * k * abs(u[1, 1, 1]) + abs(f)), (frac, res, f)
+
+
+def test_exact_3d_gradient_matches_differences():
+    k = K10
+    c0 = (0.0, 0.0, 0.0)
+    d = 1e-7
+    for p in ((0.01, 0.007, -0.004), (0.05, -0.02, 0.03), (0.3, 0.1, 0.2)):
+        g = bench.gaussian_free_space_3d([p[0]], [p[1]], [p[2]], k, c0)
+        for ax in range(3):
+            lo, hi = list(p), list(p)
+            lo[ax] -= d
+            hi[ax] += d
+            ul = bench.gaussian_free_space_3d([lo[0]], [lo[1]], [lo[2]], k, c0)[0][0, 0, 0]
+            uh = bench.gaussian_free_space_3d([hi[0]], [hi[1]], [hi[2]], k, c0)[0][0, 0, 0]
+            assert abs((uh - ul) / (2 * d) - g[1 + ax][0, 0, 0]) < 1e-6 * abs(g[1 + ax][0, 0, 0])
