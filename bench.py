@@ -311,7 +311,12 @@ def run_study(args):
     accuracy-3d: the same for Sec. 4.1.2 (Table 2): k/2pi = 10, 3x3x3
         subdomains, meshes 80^3 and 96^3 (the larger ones need more HBM than
         one GPU has for dense plane-block inverses), N1 + N2 + N3 = 9 steps,
-        FP64 and mixed precision."""
+        FP64 and mixed precision;
+    phi: the Phi form of the transferred source (eq. Phi) against the
+        direct form on the 1024^2 problem split 8 x 1 (all transfers
+        horizontal): plain DDM iterates (2 (N1 + N2) steps) in FP64 and
+        complex64, their error against the FP64 direct-form iterate, the
+        transfer kernel's time, and FGMRES(30) with K = N1 + N2 to 1e-10."""
     import numpy as np
     import torch
 
@@ -450,6 +455,37 @@ def run_study(args):
                 log("study: mesh %d^3 %s: factorising (%.0f GB)" % (mesh, "mixed" if mixed else "fp64",
                     ddm.Problem.from_workload(w, mixed=mixed).memory_required(1) / 1e9))
                 run(w, mixed, acc3)
+    elif args.study == "phi":
+        w = di.strip_2d_1024()
+        nst = 2 * sum(w.N)
+        ref = {}
+        for mixed in (False, True):
+            def phi(s, f, t_fac):
+                for form in ("direct", "phi"):
+                    s.set_transfer_form(form)
+                    s.iterate(f, 2)  # warm-up
+                    s.profile_enable(True)
+                    u, rel = s.iterate(f, nst)
+                    torch.cuda.synchronize()
+                    pr = s.profile_read()["transfer"]
+                    s.profile_enable(False)
+                    if not mixed and form == "direct":
+                        ref["u"] = u.clone()
+                    err = float(torch.max(torch.linalg.vector_norm(u - ref["u"], dim=1)
+                                          / torch.linalg.vector_norm(ref["u"], dim=1)))
+                    _, info, st = s.solve(f, method="fgmres", tol=1e-10, maxiter=300, restart=30, K=sum(w.N))
+                    r = {"precision": "mixed" if mixed else "fp64", "form": form, "steps": nst,
+                         "relres_after_steps": max(rel[-1]), "err_vs_fp64_direct": err,
+                         "transfer_ms_per_launch": pr["ms"] / max(pr["launches"], 1),
+                         "fgmres_iters": max(x["iters"] for x in info),
+                         "fgmres_relres": max(x["relres"] for x in info), "fgmres_status": st}
+                    rows.append(r)
+                    log("study: %s %s: %d steps relres %.2e, error vs FP64 direct %.2e, transfer %.4f ms/launch; "
+                        "FGMRES(30, K=%d) to 1e-10: %d iterations (relres %.1e, status %d)"
+                        % (r["precision"], form, nst, r["relres_after_steps"], err, r["transfer_ms_per_launch"],
+                           sum(w.N), r["fgmres_iters"], r["fgmres_relres"], st))
+                s.set_transfer_form("direct")
+            run(w, mixed, phi)
     print(json.dumps({"study": args.study, "rows": rows}), flush=True)
 
 
@@ -469,11 +505,12 @@ def main():
     ap.add_argument("--tol", type=float, default=None, help="stationary/FGMRES tolerance (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FGMRES and mixed-precision legs")
-    ap.add_argument("--study", choices=["none", "k-sweep", "weak", "accuracy", "accuracy-3d"], default="none",
+    ap.add_argument("--study", choices=["none", "k-sweep", "weak", "accuracy", "accuracy-3d", "phi"], default="none",
                     help="k-sweep: FGMRES preconditioner K sweep on 16x16 layouts; weak: iterative solver on "
                          "N x N subdomains of 300^2 cells; accuracy: L2/H1 errors against the free-space solution "
-                         "on 560^2-2240^2 meshes; accuracy-3d: the same on 80^3 and 96^3 (prints one JSON line "
-                         "with the table)")
+                         "on 560^2-2240^2 meshes; accuracy-3d: the same on 80^3 and 96^3; phi: the Phi form of the "
+                         "transferred source against the direct one on an 8x1 layout (prints one JSON line with "
+                         "the table)")
     ap.add_argument("--probe", choices=["none", "traffic"], default="none",
                     help="traffic: run 3 FP64 local solves of the workload and a 1 GiB device copy "
                          "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print nothing else")

@@ -180,6 +180,16 @@ def const_2d_1024(nrhs: int = 4) -> Workload:
                     notes="centres=%s" % np.round(centres, 4).tolist())
 
 
+def strip_2d_1024(nrhs: int = 4) -> Workload:
+    """The 2D 1024^2 constant-medium problem (10 ppw, PML 16, overlap 8, the
+    same seeded Gaussians) split along x only: 8 x 1 subdomains of
+    128 x 1024 cells, so every transfer is horizontal (the setting in which
+    the source can be written in the Phi form of eq. Phi)."""
+    w = const_2d_1024(nrhs)
+    return Workload("2d-const-1024-8x1", 2, w.M, w.L, w.omega, w.n_pml, w.n_ov, (8, 1), w.sigma0, w.k2, w.f,
+                    notes=w.notes)
+
+
 def const_2d_1024_cut(Ncut: int = 2, nrhs: int = 4) -> Workload:
     """A Ncut x Ncut block of the 2D 1024^2 workload: same mesh size h = 1/1024,
     frequency, PML, overlap and 128^2 cores (M = 128 Ncut cells), nrhs seeded

@@ -269,6 +269,28 @@ long ddm_graph_launches(const ddm_handle *h);
  * failure path can be exercised from the host. */
 int ddm_set_spin_limit(ddm_handle *h, int limit);
 
+/* Form of the transferred sources Psi_{b->a}(v) (every transfer: ddm_transfer,
+ * the stationary step, the FGMRES preconditioner, the slots).
+ *   DDM_TRANSFER_DIRECT (default): -L_a(beta_{b->a} v) on chi_{b->a}
+ *       (the transfer operators of Sec. 2.2);
+ *   DDM_TRANSFER_PHI: -(L_a(beta v) - beta L_a v) on chi_{b->a}, the
+ *       discrete counterpart of the Phi form of eq. Phi (the remark after the
+ *       horizontal transfer in Sec. 2.2): first differences of beta times v,
+ *       without the wave number.  It equals the direct form wherever L_a v
+ *       vanishes on the support of beta.  The DDM's local solutions satisfy
+ *       that only when the subdomains lie along one axis (N > 1 on one axis
+ *       at most: every transfer in one direction, the remark's setting); then
+ *       the iterates agree with the direct form's to rounding.  With corner
+ *       transfers they do not (a box's sources reach into its other overlap
+ *       bands) and the iteration would lose its fixed point, so DDM_EINVAL is
+ *       returned for such layouts.  On arbitrary inputs to ddm_transfer the
+ *       two forms differ by beta L_a v on chi.
+ * Changing the form discards captured step graphs.  DDM_EINVAL for any other
+ * value. */
+#define DDM_TRANSFER_DIRECT 0
+#define DDM_TRANSFER_PHI 1
+int ddm_set_transfer_form(ddm_handle *h, int form);
+
 /* Library version string. */
 const char *ddm_version(void);
 

@@ -479,8 +479,14 @@ void or_restrict_core(const or_ctx *c, int nrhs, const cplx *f, cplx *g) {
  *   g_a = sum_{b neighbour of a} Psi_{b->a}(uhat_b^{lag(b,a)}),
  *   Psi_{b->a}(v)(p) = -(L_a (beta_{b->a} v))(p) for p in chi_{b->a}, else 0,
  * with lag = number of axes on which b and a differ.  lagged[k] points to the
- * packed local solutions k+1 steps back (NULL = zero). */
-void or_transfer(const or_ctx *c, int nrhs, const cplx *const *lagged, cplx *g) {
+ * packed local solutions k+1 steps back (NULL = zero).
+ * form 1 takes the Phi form of the source instead (eq. Phi, the remark after
+ * the horizontal transfer in Sec. 2.2): the terms of L_a(beta v) in which
+ * the derivatives fall on beta, i.e. the product-rule remainder
+ *   Phi(v; beta) = L_a(beta v) - beta L_a(v),
+ * written here as exactly that difference of two operator applications
+ * (v is zero outside b's box). */
+void or_transfer_form(const or_ctx *c, int nrhs, const cplx *const *lagged, cplx *g, int form) {
     long nmax = 0;
     for (int a = 0; a < c->nsub; ++a) if (c->nloc[a] > nmax) nmax = c->nloc[a];
     memset(g, 0, sizeof(cplx) * c->etot * nrhs);
@@ -488,6 +494,9 @@ void or_transfer(const or_ctx *c, int nrhs, const cplx *const *lagged, cplx *g) 
     {
         cplx *w = (cplx *)malloc(sizeof(cplx) * nmax);
         cplx *lw = (cplx *)malloc(sizeof(cplx) * nmax);
+        cplx *v = form ? (cplx *)malloc(sizeof(cplx) * nmax) : NULL;
+        cplx *lv = form ? (cplx *)malloc(sizeof(cplx) * nmax) : NULL;
+        double *bw = form ? (double *)malloc(sizeof(double) * nmax) : NULL;
         #pragma omp for collapse(2) schedule(dynamic)
         for (int r = 0; r < nrhs; ++r)
         for (int a = 0; a < c->nsub; ++a) {
@@ -510,22 +519,29 @@ void or_transfer(const or_ctx *c, int nrhs, const cplx *const *lagged, cplx *g) 
                 for (p[1] = c->elo[a][1]; p[1] <= c->ehi[a][1]; ++p[1])
                 for (p[0] = c->elo[a][0]; p[0] <= c->ehi[a][0]; ++p[0]) {
                     long ip = box_index(c->elo[a], c->ehi[a], p);
-                    w[ip] = in_box(c->elo[b], c->ehi[b], p)
-                          ? beta_transfer(c, b, a, p) * ub[box_index(c->elo[b], c->ehi[b], p)]
-                          : 0.0;
+                    int inb = in_box(c->elo[b], c->ehi[b], p);
+                    cplx vb = inb ? ub[box_index(c->elo[b], c->ehi[b], p)] : 0.0;
+                    double be = inb ? beta_transfer(c, b, a, p) : 0.0;
+                    w[ip] = be * vb;
+                    if (form) { v[ip] = vb; bw[ip] = be; }
                 }
                 apply_box(c, a, sigma_local, c->elo[a], c->ehi[a], w, lw);
+                if (form) apply_box(c, a, sigma_local, c->elo[a], c->ehi[a], v, lv);
                 for (p[2] = c->elo[a][2]; p[2] <= c->ehi[a][2]; ++p[2])
                 for (p[1] = c->elo[a][1]; p[1] <= c->ehi[a][1]; ++p[1])
                 for (p[0] = c->elo[a][0]; p[0] <= c->ehi[a][0]; ++p[0]) {
                     if (!chi_transfer(c, b, a, p)) continue;
                     long ip = box_index(c->elo[a], c->ehi[a], p);
-                    ga[ip] -= lw[ip];
+                    ga[ip] -= form ? lw[ip] - bw[ip] * lv[ip] : lw[ip];
                 }
             }
         }
-        free(w); free(lw);
+        free(w); free(lw); free(v); free(lv); free(bw);
     }
+}
+
+void or_transfer(const or_ctx *c, int nrhs, const cplx *const *lagged, cplx *g) {
+    or_transfer_form(c, nrhs, lagged, g, 0);
 }
 
 /* u = sum_a beta_{0;a} U_a on the global grid (eq. tsum). */

@@ -53,6 +53,7 @@ def _lib():
         lib.or_local_solve.argtypes = [P, i32, P, P]
         lib.or_restrict_core.argtypes = [P, i32, P, P]
         lib.or_transfer.argtypes = [P, i32, P, P]
+        lib.or_transfer_form.argtypes = [P, i32, P, P, i32]
         lib.or_assemble.argtypes = [P, i32, P, P]
         lib.or_relres.argtypes = [P, i32, P, P, P]
         lib.or_ddm_run.restype = i32
@@ -168,12 +169,14 @@ class Oracle:
         _lib().or_restrict_core(self._c, nrhs, _ptr(f), _ptr(g))
         return g
 
-    def transfer(self, lagged, nrhs):
-        """lagged[k] = packed local solutions k+1 steps back (None = zero)."""
+    def transfer(self, lagged, nrhs, form="direct"):
+        """lagged[k] = packed local solutions k+1 steps back (None = zero).
+        form "direct": -L_a(beta v) on chi (Sec. 2.2); "phi": the Phi form
+        -(L_a(beta v) - beta L_a v) on chi (eq. Phi)."""
         keep = [None if x is None else _c128(x) for x in list(lagged) + [None] * (3 - len(lagged))]
         arr = (ctypes.c_void_p * 3)(*[_ptr(x) for x in keep])
         g = np.empty((nrhs, self.etot), dtype=np.complex128)
-        _lib().or_transfer(self._c, nrhs, arr, _ptr(g))
+        _lib().or_transfer_form(self._c, nrhs, arr, _ptr(g), {"direct": 0, "phi": 1}[form])
         return g
 
     def assemble(self, U):

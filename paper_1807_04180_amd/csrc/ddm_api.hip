@@ -577,14 +577,35 @@ int ddm_profile_read(ddm_handle *h, ddm_profile *out) {
     return DDM_OK;
 }
 
+// captured step graphs hold kernel choices and arguments: drop them when a
+// setting they bake in changes
+static void drop_step_graphs(ddm_handle *h) {
+    for (int k = 0; k < 4; ++k)
+        if (h->step_graph[k]) { (void)hipGraphExecDestroy(h->step_graph[k]); h->step_graph[k] = nullptr; }
+}
+
 int ddm_set_solve_variant(ddm_handle *h, int variant) {
     if (!h) return DDM_EINVAL;
     if (variant < 0 || variant >= kSolveNVariants || !solve_variant_ok(h->plan, variant))
         return fail(h, DDM_EINVAL, "substitution variant does not apply to this problem");
-    if (variant != h->solve_variant)
-        for (int k = 0; k < 4; ++k)
-            if (h->step_graph[k]) { (void)hipGraphExecDestroy(h->step_graph[k]); h->step_graph[k] = nullptr; }
+    if (variant != h->solve_variant) drop_step_graphs(h);
     h->solve_variant = variant;
+    return DDM_OK;
+}
+
+int ddm_set_transfer_form(ddm_handle *h, int form) {
+    if (!h) return DDM_EINVAL;
+    if (form != DDM_TRANSFER_DIRECT && form != DDM_TRANSFER_PHI) return fail(h, DDM_EINVAL, "unknown transfer form");
+    if (form == DDM_TRANSFER_PHI) {
+        int split = 0;
+        for (int d = 0; d < h->plan.dim; ++d) split += h->plan.N[d] > 1;
+        if (split > 1)
+            return fail(h, DDM_EINVAL,
+                        "the Phi form of the transferred source needs subdomains along one axis only: with corner "
+                        "transfers the local sources do not vanish where the cut-offs vary");
+    }
+    if (form != h->transfer_form) drop_step_graphs(h);
+    h->transfer_form = form;
     return DDM_OK;
 }
 
@@ -617,6 +638,7 @@ int ddm_get_solve_variant(const ddm_handle *h) { return h ? h->solve_variant : -
 
 int ddm_set_spin_limit(ddm_handle *h, int limit) {
     if (!h || limit < 1) return DDM_EINVAL;
+    if (limit != h->spin_limit) drop_step_graphs(h);
     h->spin_limit = limit;
     return DDM_OK;
 }

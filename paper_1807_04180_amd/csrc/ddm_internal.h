@@ -131,6 +131,7 @@ struct ddm_handle {
     int solve_variant = 0;
     int *d_sync = nullptr;          // 2 nsub meeting flags + 1 abort flag
     int spin_limit = 1 << 22;
+    int transfer_form = 0;          // DDM_TRANSFER_DIRECT / DDM_TRANSFER_PHI
     // continuous batching: per-slot step counts (-1 = free), the handle's
     // global step counter drives the ring phase
     std::vector<int> slot_steps;

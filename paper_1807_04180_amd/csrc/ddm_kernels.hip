@@ -211,12 +211,27 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const SubDesc *__restrict__
 // b over the 8 / 26 neighbours, lag = number of differing axes.
 // Only the first n_ov core layers of a facing b can be non-zero (beta
 // vanishes n_ov nodes past b's core); every other node gets 0.
+//
+// The Phi form (the remark on horizontal / vertical transfers in Sec. 2.2,
+// eq. Phi) replaces L_a(beta v) by the commutator
+//   L_a(beta v) - beta L_a v = sum_d cp_d (beta(p+e_d) - beta(p)) v(p+e_d)
+//                                  + cm_d (beta(p-e_d) - beta(p)) v(p-e_d),
+// the discrete product rule: first differences of beta times v, no k^2 and
+// no v(p).  The two agree wherever L_a v = 0 on the support of beta.  The
+// DDM's local solutions satisfy that when the subdomains are split along one
+// axis (every transfer runs in one direction, the setting of the remark);
+// with corner transfers a box's sources reach into its other overlap bands,
+// the forms differ there and the iteration loses its fixed point, so the
+// host accepts the Phi form only for one-axis layouts.  Its terms are
+// O(v |grad beta| / h) with no cancellation of O(v / h^2) terms.
 // ---------------------------------------------------------------------------
-template <typename TIN>
-__device__ inline double2 weighted(const SubDesc &b, const int *dd, const TIN *__restrict__ src,
-                                   const double *__restrict__ btab, int n_ov, int q0, int q1, int q2) {
-    if (q0 < b.lo[0] || q0 > b.hi[0] || q1 < b.lo[1] || q1 > b.hi[1] || q2 < b.lo[2] || q2 > b.hi[2])
-        return make_double2(0, 0);
+__device__ inline bool in_box(const SubDesc &b, int q0, int q1, int q2) {
+    return q0 >= b.lo[0] && q0 <= b.hi[0] && q1 >= b.lo[1] && q1 <= b.hi[1] && q2 >= b.lo[2] && q2 <= b.hi[2];
+}
+
+// beta_{b->a}(q): b's side factors facing a on every axis where they differ
+__device__ inline double beta_ba(const SubDesc &b, const int *dd, const double *__restrict__ btab, int n_ov, int q0,
+                                 int q1, int q2) {
     int q[3] = {q0, q1, q2};
     double beta = 1.0;
 #pragma unroll
@@ -224,9 +239,32 @@ __device__ inline double2 weighted(const SubDesc &b, const int *dd, const TIN *_
         if (dd[d] < 0) beta *= side_factor(btab, n_ov, q[d] - b.chi[d]);       // b below a: b's high side
         else if (dd[d] > 0) beta *= side_factor(btab, n_ov, b.clo[d] - q[d]);  // b above a: b's low side
     }
-    if (beta == 0.0) return make_double2(0, 0);
+    return beta;
+}
+
+template <typename TIN>
+__device__ inline double2 box_value(const SubDesc &b, const TIN *__restrict__ src, int q0, int q1, int q2) {
     long long li = (long long)(q0 - b.lo[0]) + (long long)b.n[0] * ((long long)(q1 - b.lo[1]) + (long long)b.n[1] * (q2 - b.lo[2]));
-    return cscale(to_d2(src[b.off + li]), beta);
+    return to_d2(src[b.off + li]);
+}
+
+template <typename TIN>
+__device__ inline double2 weighted(const SubDesc &b, const int *dd, const TIN *__restrict__ src,
+                                   const double *__restrict__ btab, int n_ov, int q0, int q1, int q2) {
+    if (!in_box(b, q0, q1, q2)) return make_double2(0, 0);
+    const double beta = beta_ba(b, dd, btab, n_ov, q0, q1, q2);
+    if (beta == 0.0) return make_double2(0, 0);
+    return cscale(box_value(b, src, q0, q1, q2), beta);
+}
+
+// (beta(q) - beta0) v(q), zero outside b's box
+template <typename TIN>
+__device__ inline double2 dweighted(const SubDesc &b, const int *dd, const TIN *__restrict__ src,
+                                    const double *__restrict__ btab, int n_ov, double beta0, int q0, int q1, int q2) {
+    if (!in_box(b, q0, q1, q2)) return make_double2(0, 0);
+    const double db = beta_ba(b, dd, btab, n_ov, q0, q1, q2) - beta0;
+    if (db == 0.0) return make_double2(0, 0);
+    return cscale(box_value(b, src, q0, q1, q2), db);
 }
 
 // With rcorr (residual-corrected sources): on the core of a the source is
@@ -241,7 +279,7 @@ __device__ inline double2 weighted(const SubDesc &b, const int *dd, const TIN *_
 // thread per node of the strip list (the nodes within n_ov core layers of
 // a box side) adds the neighbour terms, so that no lane idles on the many
 // nodes far from every interface.
-template <typename TIN, typename TOUT>
+template <typename TIN, typename TOUT, bool PHI>
 __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__ subs, const Coef *__restrict__ coef,
                                                      const double *__restrict__ k2, const double *__restrict__ btab,
                                                      const TIN *__restrict__ l1, const TIN *__restrict__ l2,
@@ -271,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
     const bool corrected = rcorr && p[0] >= s.clo[0] && p[0] <= s.chi[0] && p[1] >= s.clo[1] &&
                            p[1] <= s.chi[1] && p[2] >= s.clo[2] && p[2] <= s.chi[2];
     if (corrected) acc = rcorr[rhs * A.nglob + glob_index(A, p[0], p[1], p[2])];
-    double kk = k2[glob_index(A, p[0], p[1], p[2])];
+    const double kk = PHI ? 0.0 : k2[glob_index(A, p[0], p[1], p[2])];
     Coef cf[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) cf[d] = coef[s.coff[d] + l[d]];
@@ -306,22 +344,44 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
                 src += rhs * A.etot;
                 if (src2) src2 += rhs * A.etot;
                 const SubDesc &b = subs[bidx];
-                auto wsum = [&](int q0, int q1, int q2) {
-                    double2 v = weighted(b, dd, src, btab, A.n_ov, q0, q1, q2);
-                    if (src2) v = cadd(v, weighted(b, dd, src2, btab, A.n_ov, q0, q1, q2));
-                    return v;
-                };
-                double2 w0 = wsum(p[0], p[1], p[2]);
-                double2 Lw = cscale(w0, kk);
+                double2 Lw;
+                if constexpr (PHI) {
+                    // commutator: sum_d cp (beta_+ - beta_0) v_+ + cm (beta_- - beta_0) v_-
+                    const double b0 = in_box(b, p[0], p[1], p[2]) ? beta_ba(b, dd, btab, A.n_ov, p[0], p[1], p[2]) : 0.0;
+                    auto dsum = [&](int q0, int q1, int q2) {
+                        double2 v = dweighted(b, dd, src, btab, A.n_ov, b0, q0, q1, q2);
+                        if (src2) v = cadd(v, dweighted(b, dd, src2, btab, A.n_ov, b0, q0, q1, q2));
+                        return v;
+                    };
+                    Lw = make_double2(0, 0);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    if (d >= A.dim) continue;
-                    int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
-                    qp[d] += 1;
-                    qm[d] -= 1;
-                    double2 wp = p[d] < s.hi[d] ? wsum(qp[0], qp[1], qp[2]) : make_double2(0, 0);
-                    double2 wm = p[d] > s.lo[d] ? wsum(qm[0], qm[1], qm[2]) : make_double2(0, 0);
-                    Lw = cadd(Lw, csub(cmul(cf[d].cp, csub(wp, w0)), cmul(cf[d].cm, csub(w0, wm))));
+                    for (int d = 0; d < 3; ++d) {
+                        if (d >= A.dim) continue;
+                        int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
+                        qp[d] += 1;
+                        qm[d] -= 1;
+                        double2 dp = p[d] < s.hi[d] ? dsum(qp[0], qp[1], qp[2]) : make_double2(0, 0);
+                        double2 dm = p[d] > s.lo[d] ? dsum(qm[0], qm[1], qm[2]) : make_double2(0, 0);
+                        Lw = cadd(Lw, cadd(cmul(cf[d].cp, dp), cmul(cf[d].cm, dm)));
+                    }
+                } else {
+                    auto wsum = [&](int q0, int q1, int q2) {
+                        double2 v = weighted(b, dd, src, btab, A.n_ov, q0, q1, q2);
+                        if (src2) v = cadd(v, weighted(b, dd, src2, btab, A.n_ov, q0, q1, q2));
+                        return v;
+                    };
+                    double2 w0 = wsum(p[0], p[1], p[2]);
+                    Lw = cscale(w0, kk);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        if (d >= A.dim) continue;
+                        int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
+                        qp[d] += 1;
+                        qm[d] -= 1;
+                        double2 wp = p[d] < s.hi[d] ? wsum(qp[0], qp[1], qp[2]) : make_double2(0, 0);
+                        double2 wm = p[d] > s.lo[d] ? wsum(qm[0], qm[1], qm[2]) : make_double2(0, 0);
+                        Lw = cadd(Lw, csub(cmul(cf[d].cp, csub(wp, w0)), cmul(cf[d].cm, csub(w0, wm))));
+                    }
                 }
                 // plain: acc += Psi = -L(beta v); corrected: acc -= Psi
                 acc = corrected ? cadd(acc, Lw) : csub(acc, Lw);
@@ -407,8 +467,12 @@ hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TI
     const long long ns = (long long)P.strip.size();
     if (ns > 0) {
         dim3 grid((unsigned)((ns + kBlock - 1) / kBlock), nrhs);
-        k_transfer<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g,
-                                                              pack_args(P), rcorr, h->d_strip, ns);
+        if (h->transfer_form == DDM_TRANSFER_PHI)
+            k_transfer<TIN, TOUT, true><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2,
+                                                                        l3, g, pack_args(P), rcorr, h->d_strip, ns);
+        else
+            k_transfer<TIN, TOUT, false><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1,
+                                                                         l2, l3, g, pack_args(P), rcorr, h->d_strip, ns);
     }
     return hipGetLastError();
 }

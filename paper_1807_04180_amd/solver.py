@@ -214,6 +214,11 @@ class HelmholtzDDM:
     def set_spin_limit(self, limit: int):
         self._check(self.lib.ddm_set_spin_limit(self._h, int(limit)))
 
+    def set_transfer_form(self, form: str):
+        """"direct": -L_a(beta v) chi (default); "phi": the k-free commutator
+        form -(L_a(beta v) - beta L_a v) chi (eq. Phi)."""
+        self._check(self.lib.ddm_set_transfer_form(self._h, _ffi.TRANSFER_FORMS.index(form)))
+
     # -- continuous batching (slots) -------------------------------------
     def slot_admit(self, slot: int, f: torch.Tensor):
         if f.dtype != torch.complex128 or f.numel() != self.nglob:
