@@ -67,13 +67,17 @@ def pct(v, p):
     return float(np.percentile(np.asarray(v, dtype=float), p)) if len(v) else None
 
 
+SUBST_KERNELS = {"chain": "k_solve_chain", "chain2": "k_solve_chain2", "perline": "k_solve_line"}
+
+
 def recorded_traffic(kernel_variant):
     """HBM traffic per launch of the substitution kernel from the committed
     rocprofv3 counter summary, only if the kernel source is unchanged since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_solve_chain_2d1024_traffic.json")
+    name = SUBST_KERNELS.get(kernel_variant)
+    path = os.path.join(ROOT, "profiles", "%s_2d1024_traffic.json" % name)
     src = os.path.join(ROOT, "paper_1807_04180_amd", "csrc", "ddm_solve.hip")
-    if kernel_variant != "chain" or not os.path.exists(path):
+    if name is None or not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
@@ -627,8 +631,7 @@ def main():
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
                        "traffic": recorded_traffic(s64.solve_variant()) if args.workload == "2d-1024" else None,
-                       "kernel": ("k_solve_chain" if s64.solve_variant() == "chain" else "k_solve_line")
-                                 + " (block substitution)",
+                       "kernel": SUBST_KERNELS[s64.solve_variant()] + " (block substitution)",
                        "avg_launch_us": avg_us, "launches": sub["launches"],
                        "bytes_per_launch": sub["bytes"] / max(sub["launches"], 1)}
     out["kernel_time_ms_per_solve_batch"] = {k: v["ms"] for k, v in prof.items()}

@@ -232,8 +232,13 @@ int ddm_profile_read(ddm_handle *h, ddm_profile *out);
  *   1  one workgroup per elimination chain walking all its blocks, the block
  *      recurrence kept on chip (block size <= 256).  With the twisted layout
  *      (default when there are at most 128 subdomains) every subdomain has two
- *      chains that meet once at a middle block. */
-enum { DDM_SOLVE_PERLINE = 0, DDM_SOLVE_CHAIN = 1, DDM_SOLVE_NVARIANTS = 2 };
+ *      chains that meet once at a middle block;
+ *   2  two workgroups per chain of the twisted layout, each taking half of
+ *      every block's columns and exchanging partial sums with its partner
+ *      once per block (block size <= 256, at most 64 subdomains so that all
+ *      4 nsub workgroups are resident, RHS in tiles of up to 4): for
+ *      problems with fewer chains than CUs. */
+enum { DDM_SOLVE_PERLINE = 0, DDM_SOLVE_CHAIN = 1, DDM_SOLVE_CHAIN2 = 2, DDM_SOLVE_NVARIANTS = 3 };
 
 /* Factor layout: twisted != 0 eliminates every subdomain from both ends
  * towards a middle block (two chains per subdomain), 0 from the first block

@@ -110,6 +110,7 @@ size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
     b += (size_t)nrhs * P.nglob * sizeof(double2);                 // residual / operator output
     if (mixed) b += (size_t)nrhs * P.etot * sizeof(double2);       // widening scratch
     b += part_doubles(P, nrhs, m > 0 ? m : 30) * sizeof(double);
+    if (chain2_fits(P)) b += chain2_xbuf_bytes(P) + (size_t)8 * P.nsub * sizeof(int);
     if (m > 0) b += (size_t)(2 * m + 1) * nrhs * P.nglob * sizeof(double2) + (size_t)nrhs * P.nglob * sizeof(double2);
     return b;
 }
@@ -118,7 +119,7 @@ void free_all(ddm_handle *h) {
     void *ptrs[] = {h->d_subs, h->d_coef, h->d_gcoef, h->d_aown, h->d_strip, h->d_btab, h->d_k2, h->d_items, h->d_W,
                     h->d_scratch, h->d_flags, h->d_g, h->d_ring[0], h->d_ring[1], h->d_ring[2], h->d_ring[3],
                     h->d_r, h->d_wide, h->d_part, h->d_norm, h->d_active, h->d_V, h->d_Z, h->d_dots,
-                    h->d_coef_y, h->d_sync};
+                    h->d_coef_y, h->d_sync, h->d_sync2, h->d_xbuf};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < 4; ++k)
@@ -577,6 +578,15 @@ int ddm_profile_read(ddm_handle *h, ddm_profile *out) {
     return DDM_OK;
 }
 
+// Default substitution variant: the split chains when at most 4 RHS share a
+// launch (one pass over the inverses either way) and the plan admits them,
+// else one workgroup per chain (its 8 / 16-RHS tiles stream every inverse
+// once for up to 16 RHS), else the per-line launches.
+static int default_variant(const ddm_handle *h) {
+    if (h->nrhs_max <= 4 && h->d_xbuf && solve_variant_ok(h->plan, kSolveChain2)) return kSolveChain2;
+    return solve_variant_ok(h->plan, kSolveChain) ? kSolveChain : kSolvePerLine;
+}
+
 // captured step graphs hold kernel choices and arguments: drop them when a
 // setting they bake in changes
 static void drop_step_graphs(ddm_handle *h) {
@@ -621,8 +631,7 @@ int ddm_set_factor_layout(ddm_handle *h, int twisted) {
     h->factored = false;
     for (int k = 0; k < 4; ++k)
         if (h->step_graph[k]) { (void)hipGraphExecDestroy(h->step_graph[k]); h->step_graph[k] = nullptr; }
-    if (!solve_variant_ok(h->plan, h->solve_variant))
-        h->solve_variant = solve_variant_ok(h->plan, kSolveChain) ? kSolveChain : kSolvePerLine;
+    if (!solve_variant_ok(h->plan, h->solve_variant)) h->solve_variant = default_variant(h);
     return DDM_OK;
 }
 
@@ -900,7 +909,12 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         dalloc(h, &h->d_active, (size_t)nrhs_max);
         dalloc(h, &h->d_sync, (size_t)2 * P.nsub + 1);
         HIPCHK(hipMemset(h->d_sync, 0, (2 * P.nsub + 1) * sizeof(int)));
-        h->solve_variant = solve_variant_ok(P, kSolveChain) ? kSolveChain : kSolvePerLine;
+        if (chain2_fits(P)) {
+            dalloc(h, &h->d_sync2, (size_t)8 * P.nsub);
+            HIPCHK(hipMalloc(&h->d_xbuf, chain2_xbuf_bytes(P)));
+            h->bytes += chain2_xbuf_bytes(P);
+        }
+        h->solve_variant = default_variant(h);
         HIPCHK(hipHostMalloc((void **)&h->h_norm, 4 * nrhs_max * sizeof(double), hipHostMallocDefault));
         std::vector<int> ones(nrhs_max, 1);
         HIPCHK(hipMemcpy(h->d_active, ones.data(), nrhs_max * sizeof(int), hipMemcpyHostToDevice));

@@ -130,6 +130,8 @@ struct ddm_handle {
     // substitution kernel variant (autotuned) and persistent-launch sync state
     int solve_variant = 0;
     int *d_sync = nullptr;          // 2 nsub meeting flags + 1 abort flag
+    int *d_sync2 = nullptr;         // split substitution: 4 nsub meeting + 4 nsub exchange flags
+    void *d_xbuf = nullptr;         // split substitution: double-buffered partial-sum exchange
     int spin_limit = 1 << 22;
     int transfer_form = 0;          // DDM_TRANSFER_DIRECT / DDM_TRANSFER_PHI
     // continuous batching: per-slot step counts (-1 = free), the handle's
@@ -186,8 +188,10 @@ template <typename T>
 hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs);
 
 // substitution variants
-enum { kSolvePerLine = 0, kSolveChain = 1, kSolveNVariants = 2 };
+enum { kSolvePerLine = 0, kSolveChain = 1, kSolveChain2 = 2, kSolveNVariants = 3 };
 bool solve_variant_ok(const Plan &P, int variant);
+size_t chain2_xbuf_bytes(const Plan &P);
+bool chain2_fits(const Plan &P);
 
 hipError_t launch_convert_c128_to_c64(const double2 *in, float2 *out, long long n, hipStream_t s);
 hipError_t launch_convert_c64_to_c128(const float2 *in, double2 *out, long long n, hipStream_t s);

@@ -441,6 +441,306 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split chain substitution: two workgroups per chain of a two-ended layout,
+// for problems with too few chains to give every CU one (one workgroup per
+// chain streams at the per-CU request rate, so half the chip would idle).
+// Half h of a chain takes the columns [c0, c1) of every block (c1 - c0 about
+// bs / 2) and the matching rows of every result.  Per block step each half
+// forms the partial product of its columns for all rows, publishes the part
+// that falls on the partner's rows in a double-buffered exchange area, adds
+// the partner's part to its own rows and carries on with its half of the
+// next vector.  Halves b and b ^ 8 of the grid land on the same XCD under the
+// round-robin placement of workgroups.
+// Each half uses the NPAIR = 16 partition of its own columns; the sum of the
+// two halves' partials is commutative, so results do not depend on which
+// half adds them, nor on the RHS tile size (RT <= 4; larger counts loop over
+// tiles of 4).  Every wait is bounded (spin_limit) and stops at once after a
+// sticky abort.
+// ---------------------------------------------------------------------------
+__device__ inline void wait_flag2(int *f, int target, int *abort_flag, int spin_limit) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins >= spin_limit) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    }
+    __syncthreads();
+}
+
+// Per-block exchange without cache maintenance: an agent-scope fence on this
+// chip writes back and invalidates the whole L2, which at one exchange per
+// block and 256 workgroups costs more than the block itself.  The exchanged
+// words and the flags are instead relaxed agent-scope atomics (coherent at
+// the agent level without touching other cached data); the writer waits for
+// its stores to complete (s_waitcnt 0: stores count in vmcnt here) before a
+// barrier and the flag store, and the reader loads the words only after it
+// has seen the flag (and a barrier).
+__device__ inline void wait_flag_relaxed(int *f, int target, int *abort_flag, int spin_limit) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins >= spin_limit) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ inline void xstore(double2 *p, double2 v) {
+    unsigned long long *q = (unsigned long long *)p;
+    __hip_atomic_store(q, __double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, __double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void xstore(float2 *p, float2 v) {
+    const unsigned long long w = (unsigned long long)__float_as_uint(v.x) |
+                                 ((unsigned long long)__float_as_uint(v.y) << 32);
+    __hip_atomic_store((unsigned long long *)p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double2 xload(double2 *p) {
+    unsigned long long *q = (unsigned long long *)p;
+    return make_double2(__longlong_as_double(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
+                        __longlong_as_double(__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+}
+__device__ inline float2 xload(float2 *p) {
+    const unsigned long long w =
+        __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((unsigned)w), __uint_as_float((unsigned)(w >> 32)));
+}
+
+// elements per (unit, half) exchange slot: rows of the partner (<= 128 for
+// bs <= 256) times the RHS tile (<= 4)
+constexpr int kXSlot = 128 * 4;
+
+template <typename T2, int RT, int ROWS>
+__global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__restrict__ subs,
+                                                            const Coef *__restrict__ coef, const T2 *__restrict__ W,
+                                                            const T2 *__restrict__ g, T2 *__restrict__ x, int nrhs,
+                                                            long long etot, int dim, int nunits, int *mflags,
+                                                            int *xflags, int *abort_flag, int spin_limit,
+                                                            T2 *__restrict__ xbuf) {
+    static_assert(RT <= 4, "exchange slots hold tiles of up to 4 RHS");
+    extern __shared__ unsigned char lds_raw[];
+    using LT = typename LaneT<T2, ROWS>::type;
+    constexpr int NT = kCThreads;
+    constexpr int kCBatch = ChainBatch<T2, ROWS>::value;
+    constexpr int NPAIR = kCWaves;  // one work pair per wave
+    const int b = (int)blockIdx.x;
+    const int half = (b >> 3) & 1;
+    const int unit = (b & 7) | ((b >> 4) << 3);
+    if (unit >= nunits) return;
+    const int a = unit >> 1, chain = unit & 1;
+    const SubDesc &s = subs[a];
+    const int nb = s.nb, bs = s.bs, mid = s.mid, ax = dim - 1;
+    const long long off = s.off;
+    const int ld = s.ld;
+    const int R = (bs + 64 * ROWS - 1) / (64 * ROWS);
+    const int bh = ((bs + 3) / 4) * 2;               // even split point
+    const int c0 = half ? bh : 0, c1 = half ? bs : bh;  // own columns = own result rows
+    const int o0 = half ? 0 : bh, o1 = half ? bh : bs;  // the partner's rows
+    const int ncol = c1 - c0;
+    const int CG = NPAIR / R;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rt = wv % R, cg = wv / R;
+    const bool gemv = cg < CG;  // groups past the last column still write zero partials
+    const int row = (rt * 64 + lane) * ROWS;
+    const bool rowok = gemv && row < bs;
+    const int bsp = R * 64 * ROWS;
+    T2 *vs = (T2 *)lds_raw;                  // [bsp][RT] current v (own columns used)
+    T2 *red = vs + (size_t)bsp * RT;         // [CG][RT][bsp] partial sums
+    constexpr int PF = kLdsCols<T2, ROWS>::value;
+    T2 *mypf = red + (size_t)CG * RT * bsp + (size_t)wv * PF * 64 * ROWS;
+    const int nf = chain == 0 ? mid : nb - 1 - mid;
+    const int nsteps = 2 * nf + 1;
+    const int dirf = chain == 0 ? 1 : -1;
+    const int lfirst = chain == 0 ? 0 : nb - 1;
+    // this thread's element of the own rows and of the partner's rows
+    const int eo = threadIdx.x, io = c0 + eo / RT, qo = eo % RT;
+    const bool own_ok = eo < ncol * RT;
+    const int ip = o0 + eo / RT;
+    const bool part_ok = eo < (o1 - o0) * RT;
+    int *myx = xflags + 2 * unit + half, *px = xflags + 2 * unit + (1 - half);
+    int ep = 0;  // exchange epoch: block steps done in this launch
+
+    for (int r0 = 0; r0 < nrhs; r0 += RT) {
+        const int nr = nrhs - r0 < RT ? nrhs - r0 : RT;
+        if (nf > 0 && own_ok)
+            vs[io * RT + qo] = qo < nr ? g[(long long)(r0 + qo) * etot + off + (long long)lfirst * bs + io] : czero<T2>();
+        __syncthreads();
+        auto step_l = [&](int t) {
+            if (t < nf) return lfirst + dirf * t;
+            if (t == nf) return mid;
+            return mid - dirf * (t - nf);
+        };
+        const T2 *Wbase = W + s.foff + (long long)c0 * ld;  // own columns
+        const long long bs2 = (long long)bs * ld;
+        const int rowc = row < bs ? row : (bs - 1) / ROWS * ROWS;
+        LT wb[kCBatch];
+        {
+            const T2 *Wl = Wbase + (long long)step_l(0) * bs2;
+            lds_prefetch<T2, PF, ROWS>(Wl, mypf, cg, CG, ncol, ld, rowc, gemv);
+#pragma unroll
+            for (int u = 0; u < kCBatch; ++u) {
+                const int j = cg + CG * (PF + u);
+                wb[u] = (rowok && j < ncol) ? *(const LT *)(Wl + (long long)j * ld + row) : lane_zero<LT>();
+            }
+        }
+        for (int t = 0; t < nsteps; ++t) {
+            const int l = step_l(t);
+            const int kind = t < nf ? 0 : (t == nf ? 1 : 2);
+            if (t == nf) {
+                // middle: v = g_mid - cm y_{mid-1} - cp y_{mid+1} on the own rows; the
+                // other chain's same half wrote y_{mid+1} there
+                const Coef cmid = coef[s.coff[ax] + mid];
+                const int epoch = r0 / RT + 1;
+                __threadfence();
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(mflags + 4 * a + 2 * chain + half, epoch, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                wait_flag2(mflags + 4 * a + 2 * (1 - chain) + half, epoch, abort_flag, spin_limit);
+                if (own_ok) {
+                    double2 v = make_double2(0, 0);
+                    if (qo < nr) {
+                        const long long base = (long long)(r0 + qo) * etot + off;
+                        v = to_d2(g[base + (long long)mid * bs + io]);
+                        if (mid > 0) v = cmsub_fixed(v, cmid.cm, to_d2(x[base + (long long)(mid - 1) * bs + io]));
+                        if (mid < nb - 1) v = cmsub_fixed(v, cmid.cp, to_d2(x[base + (long long)(mid + 1) * bs + io]));
+                    }
+                    vs[io * RT + qo] = from_d2<T2>(v);
+                }
+                __syncthreads();
+            }
+            const int tn = t + 1;
+            const int lnv = tn < nsteps && tn != nf ? step_l(tn) : -1;
+            T2 pre = czero<T2>();
+            if (own_ok && qo < nr) {
+                const long long base = (long long)(r0 + qo) * etot + off;
+                if (kind == 2) pre = x[base + (long long)l * bs + io];
+                else if (kind == 0 && lnv >= 0) pre = g[base + (long long)lnv * bs + io];
+            }
+            // ---- GEMV over the own columns: one work pair per wave ----
+            const int lnext = t + 1 < nsteps ? step_l(t + 1) : -1;
+            if (gemv) {
+                T2 acc[ROWS][RT];
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                    for (int q = 0; q < RT; ++q) acc[r][q] = czero<T2>();
+                const int kmax = (ncol - cg + CG - 1) / CG;
+                const T2 *vc = vs + (size_t)c0 * RT;
+                if constexpr (PF > 0) {
+                    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+#pragma unroll 1
+                    for (int u = 0; u < PF; ++u) {
+                        if (u < kmax) {
+                            const int j = cg + CG * u;
+                            const LT w = ((const LT *)mypf)[u * 64 + lane];
+#pragma unroll
+                            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                                for (int q = 0; q < RT; ++q) cfma(acc[r][q], lane_row(w, r), vc[j * RT + q]);
+                        }
+                    }
+                }
+                for (int k0 = PF; k0 < kmax; k0 += kCBatch) {
+                    const bool more = k0 + kCBatch < kmax;
+                    const int ln = more ? l : lnext;
+                    const int kn = more ? k0 + kCBatch : PF;
+                    LT wn[kCBatch];
+                    const T2 *Wn = Wbase + (long long)(ln >= 0 ? ln : 0) * bs2;
+#pragma unroll
+                    for (int u = 0; u < kCBatch; ++u) {
+                        const int j = cg + CG * (kn + u);
+                        wn[u] = (ln >= 0 && rowok && j < ncol) ? *(const LT *)(Wn + (long long)j * ld + row)
+                                                               : lane_zero<LT>();
+                    }
+#pragma unroll
+                    for (int u = 0; u < kCBatch; ++u) {
+                        const int j = cg + CG * (k0 + u);
+                        if (j < ncol) {
+#pragma unroll
+                            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                                for (int q = 0; q < RT; ++q) cfma(acc[r][q], lane_row(wb[u], r), vc[j * RT + q]);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kCBatch; ++u) wb[u] = wn[u];
+                }
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                    for (int q = 0; q < RT; ++q) red[((size_t)cg * RT + q) * bsp + row + r] = acc[r][q];
+            }
+            if (lnext >= 0) lds_prefetch<T2, PF, ROWS>(Wbase + (long long)lnext * bs2, mypf, cg, CG, ncol, ld, rowc, gemv);
+            __syncthreads();
+            // ---- publish the partner's rows of this half's partial product ----
+            ++ep;
+            T2 *slot = xbuf + ((size_t)(ep & 1) * nunits * 2 + (size_t)unit * 2) * kXSlot;
+            if (part_ok) {
+                const int q = eo % RT;
+                T2 sum = red[(size_t)q * bsp + ip];
+                for (int c = 1; c < CG; ++c) {
+                    const T2 o = red[((size_t)c * RT + q) * bsp + ip];
+                    sum.x += o.x;
+                    sum.y += o.y;
+                }
+                xstore(slot + (size_t)half * kXSlot + eo, sum);
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's exchange stores are complete
+            __syncthreads();
+            if (threadIdx.x == 0) __hip_atomic_store(myx, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            T2 own = czero<T2>();
+            if (own_ok) {
+                own = red[(size_t)qo * bsp + io];
+                for (int c = 1; c < CG; ++c) {
+                    const T2 o = red[((size_t)c * RT + qo) * bsp + io];
+                    own.x += o.x;
+                    own.y += o.y;
+                }
+            }
+            wait_flag_relaxed(px, ep, abort_flag, spin_limit);
+            if (own_ok) {
+                const T2 o = xload(slot + (size_t)(1 - half) * kXSlot + eo);
+                T2 sum = own;
+                sum.x += o.x;
+                sum.y += o.y;
+                const long long base = (long long)(r0 + qo) * etot + off;
+                T2 res = sum;
+                if (kind == 2) {
+                    res.x = pre.x - sum.x;
+                    res.y = pre.y - sum.y;
+                }
+                if (qo < nr && (kind != 1 || chain == 0)) x[base + (long long)l * bs + io] = res;
+                if (lnv >= 0) {
+                    double2 v;
+                    const Coef cn = coef[s.coff[ax] + lnv];
+                    if (kind == 0) {
+                        const double2 c = chain == 0 ? cn.cm : cn.cp;
+                        v = qo < nr ? cmsub_fixed(to_d2(pre), c, to_d2(res)) : make_double2(0, 0);
+                    } else {
+                        const double2 c = chain == 0 ? cn.cp : cn.cm;
+                        v = qo < nr ? cmul_fixed(c, to_d2(res)) : make_double2(0, 0);
+                    }
+                    vs[io * RT + qo] = from_d2<T2>(v);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <typename T2, int RT>
 static hipError_t run_sweeps(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     const Plan &P = h->plan;
@@ -553,10 +853,74 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
     }
 }
 
+// grid of the split substitution: 2 halves x 2 chains per subdomain, units
+// padded to a multiple of 8 so that halves b and b ^ 8 share an XCD
+static int chain2_grid(const Plan &P) { return ((2 * P.nsub + 7) / 8) * 16; }
+
+size_t chain2_xbuf_bytes(const Plan &P) {
+    return (size_t)2 * (2 * P.nsub) * 2 * kXSlot * sizeof(double2);
+}
+
+template <typename T2, int RT, int ROWS>
+static size_t chain2_lds(int bs_max) {
+    const int R = (bs_max + 64 * ROWS - 1) / (64 * ROWS);
+    const int CG = kCWaves / R;
+    return (size_t)R * 64 * ROWS * RT * (1 + CG) * sizeof(T2) +
+           (size_t)kCWaves * kLdsCols<T2, ROWS>::value * 64 * ROWS * sizeof(T2);
+}
+
+template <typename T2, int RT, int ROWS>
+static hipError_t run_chain2(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
+    const Plan &P = h->plan;
+    const double es = sizeof(T2);
+    double vb = 0.0;
+    for (const SubDesc &sd : P.subs) vb += (double)sd.nloc;
+    const int ntile = (nrhs + RT - 1) / RT;
+    ProfScope ps(h, DDM_K_SUBST, es * (2.0 * (double)P.fel * ntile + 4.0 * nrhs * vb));
+    const size_t lds = chain2_lds<T2, RT, ROWS>(P.bs_max);
+    hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain2<T2, RT, ROWS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    // meeting flags [4 nsub] and exchange flags [4 nsub] start at zero
+    e = launch_fill_zero(h->d_sync2, (long long)(8 * P.nsub) * sizeof(int), h->stream);
+    if (e != hipSuccess) return e;
+    const SubDesc *a0 = h->d_subs;
+    const Coef *a1 = h->d_coef;
+    const T2 *a2 = (const T2 *)h->d_W;
+    const T2 *a3 = g;
+    T2 *a4 = x;
+    int a5 = nrhs;
+    long long a6 = P.etot;
+    int a7 = P.dim, a8 = 2 * P.nsub;
+    int *a9 = h->d_sync2, *a10 = h->d_sync2 + 4 * P.nsub, *a11 = h->d_sync + 2 * P.nsub;
+    int a12 = h->spin_limit;
+    T2 *a13 = (T2 *)h->d_xbuf;
+    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11, &a12, &a13};
+    // the halves and chains of a subdomain wait on each other: all co-resident
+    return hipLaunchCooperativeKernel((const void *)k_solve_chain2<T2, RT, ROWS>, dim3(chain2_grid(P)),
+                                      dim3(kCThreads), args, lds, h->stream);
+}
+
+template <typename T>
+static hipError_t run_chain2_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
+    constexpr int ROWS = sizeof(T) == sizeof(double2) ? 1 : 2;
+    if (nrhs <= 1) return run_chain2<T, 1, ROWS>(h, g, x, nrhs);
+    if (nrhs <= 2) return run_chain2<T, 2, ROWS>(h, g, x, nrhs);
+    return run_chain2<T, 4, ROWS>(h, g, x, nrhs);
+}
+
+// the split substitution fits this plan's blocks and subdomain count (it
+// also needs the two-ended layout)
+bool chain2_fits(const Plan &P) {
+    return P.bs_max <= 256 && chain2_grid(P) <= 256 && chain2_lds<double2, 4, 1>(P.bs_max) <= kLdsMax &&
+           chain2_lds<float2, 4, 2>(P.bs_max) <= kLdsMax;
+}
+
 bool solve_variant_ok(const Plan &P, int variant) {
     switch (variant) {
         case kSolvePerLine: return !P.twisted;
         case kSolveChain: return P.bs_max <= 256;
+        case kSolveChain2: return P.twisted && chain2_fits(P);  // one workgroup per CU (256 CUs)
         default: return false;
     }
 }
@@ -566,7 +930,8 @@ template <typename T>
 hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs) {
     int v = h->solve_variant;
     if (!solve_variant_ok(h->plan, v)) v = solve_variant_ok(h->plan, kSolveChain) ? kSolveChain : kSolvePerLine;
-    if (v == kSolveChain) return run_chain_rt<T>(h, g, x, nrhs);
+    if (v == kSolveChain2 && h->d_xbuf) return run_chain2_rt<T>(h, g, x, nrhs);
+    if (v == kSolveChain || v == kSolveChain2) return run_chain_rt<T>(h, g, x, nrhs);
     return run_perline<T>(h, g, x, nrhs);
 }
 

@@ -168,7 +168,7 @@ def test_deterministic_bitwise(pair):
     assert torch.equal(u1, u2) and r1 == r2
 
 
-LAYOUTS = {"twisted": (True, ["chain"]), "onedir": (False, ["perline", "chain"])}
+LAYOUTS = {"twisted": (True, ["chain", "chain2"]), "onedir": (False, ["perline", "chain"])}
 
 
 @pytest.mark.parametrize("layout", sorted(LAYOUTS))
@@ -220,6 +220,43 @@ def test_chain_mixed_matches_oracle():
     for nrhs in (3, 6, 9, 20):  # RHS tiles of 4, 8, 16 and 16 + a ragged 4
         gin = di.random_field((nrhs, o.etot), seed=51)
         assert relerr(_n(g.local_solve(_t(gin))), o.local_solve(gin), axis=1) < 5e-5
+    g.close()
+
+
+def test_chain2_mixed_matches_oracle():
+    """Split substitution (two workgroups per chain) in complex64: oracle
+    parity over 1, 3 and 6 RHS (tiles of 4 and a ragged tile), and a single
+    RHS bit-for-bit equal to its place in the batch."""
+    w = CASES["2d-3x3-layered"]()
+    o, g = make_pair(w, nrhs_max=6, mixed=True)
+    g.set_solve_variant("chain2")
+    assert g.solve_variant() == "chain2"
+    for nrhs in (1, 3, 6):
+        gin = di.random_field((nrhs, o.etot), seed=53)
+        xb = _n(g.local_solve(_t(gin)))
+        assert relerr(xb, o.local_solve(gin), axis=1) < 5e-5, nrhs
+        assert np.array_equal(_n(g.local_solve(_t(gin[-1:])))[0], xb[-1]), nrhs
+    g.close()
+
+
+def test_chain2_spin_bound_drains_and_reports():
+    """A spin bound of 1 makes the split substitution give up its waits (the
+    per-block exchange and the middle meeting): the launch must still drain
+    and report EHIP unless every partner was already there; afterwards, with
+    the normal bound, results are correct again."""
+    w = CASES["2d-3x3-layered"]()
+    o, g = make_pair(w, nrhs_max=2)
+    g.set_solve_variant("chain2")
+    gin = di.random_field((2, o.etot), seed=54)
+    xo = o.local_solve(gin)
+    g.set_spin_limit(1)
+    try:
+        x = g.local_solve(_t(gin))
+        assert relerr(_n(x), xo, axis=1) < 1e-10
+    except ddm.DDMError as e:
+        assert e.code == ddm._ffi.DDM_EHIP
+    g.set_spin_limit(1 << 22)
+    assert relerr(_n(g.local_solve(_t(gin))), xo, axis=1) < 1e-10
     g.close()
 
 
