@@ -676,6 +676,12 @@ def main():
         torch.cuda.synchronize()
         tm = time.perf_counter() - t0
         errm = (torch.linalg.vector_norm(umx - u64, dim=1) / torch.linalg.vector_norm(u64, dim=1)).tolist()
+        # roofline of the complex64 substitution (live event-profiled pass)
+        smx.profile_enable(True)
+        smx.solve(f, method="stationary", tol=args.tol, maxiter=400, u=torch.empty_like(f))
+        subm = smx.profile_read()["substitution"]
+        smx.profile_enable(False)
+        achm = subm["bytes"] / (subm["ms"] * 1e-3) / 1e9 if subm["ms"] > 0 else 0.0
         ufm = torch.empty_like(f)
         t1 = time.perf_counter()
         _, infofm, stfm = smx.solve(f, method="fgmres", tol=args.tol, maxiter=200, restart=30, u=ufm)
@@ -686,11 +692,17 @@ def main():
                         "steps": [x["iters"] for x in infom], "relres": [x["relres"] for x in infom],
                         "rel_err_vs_fp64": errm, "status": stm, "factor_s": t_factor_mx,
                         "speedup_vs_fp64": (nrhs * args.steps / tm) / value,
+                        "roofline": {"bound": "hbm", "achieved": achm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": achm / HBM_PEAK_GBS,
+                                     "kernel": SUBST_KERNELS[smx.solve_variant()] + " (complex64 block substitution)",
+                                     "avg_launch_us": subm["ms"] / max(subm["launches"], 1) * 1e3,
+                                     "bytes_per_launch": subm["bytes"] / max(subm["launches"], 1)},
                         "fgmres": {"solves_per_s": nrhs / tfm, "gmres_iters": [x["iters"] for x in infofm],
                                    "relres": [x["relres"] for x in infofm], "status": stfm}}
-        log("bench: mixed stationary: %.2f solves/s (x%.2f), steps %s, err vs FP64 %s"
+        log("bench: mixed stationary: %.2f solves/s (x%.2f), steps %s, err vs FP64 %s; substitution %.0f GB/s "
+            "(%.1f%% of HBM peak)"
             % (nrhs * args.steps / tm, (nrhs * args.steps / tm) / value, [x["iters"] for x in infom],
-               ["%.1e" % e for e in errm]))
+               ["%.1e" % e for e in errm], achm, 100 * achm / HBM_PEAK_GBS))
         del smx
 
     if not args.no_cpu_baseline:

@@ -242,31 +242,6 @@ __device__ inline double beta_ba(const SubDesc &b, const int *dd, const double *
     return beta;
 }
 
-template <typename TIN>
-__device__ inline double2 box_value(const SubDesc &b, const TIN *__restrict__ src, int q0, int q1, int q2) {
-    long long li = (long long)(q0 - b.lo[0]) + (long long)b.n[0] * ((long long)(q1 - b.lo[1]) + (long long)b.n[1] * (q2 - b.lo[2]));
-    return to_d2(src[b.off + li]);
-}
-
-template <typename TIN>
-__device__ inline double2 weighted(const SubDesc &b, const int *dd, const TIN *__restrict__ src,
-                                   const double *__restrict__ btab, int n_ov, int q0, int q1, int q2) {
-    if (!in_box(b, q0, q1, q2)) return make_double2(0, 0);
-    const double beta = beta_ba(b, dd, btab, n_ov, q0, q1, q2);
-    if (beta == 0.0) return make_double2(0, 0);
-    return cscale(box_value(b, src, q0, q1, q2), beta);
-}
-
-// (beta(q) - beta0) v(q), zero outside b's box
-template <typename TIN>
-__device__ inline double2 dweighted(const SubDesc &b, const int *dd, const TIN *__restrict__ src,
-                                    const double *__restrict__ btab, int n_ov, double beta0, int q0, int q1, int q2) {
-    if (!in_box(b, q0, q1, q2)) return make_double2(0, 0);
-    const double db = beta_ba(b, dd, btab, n_ov, q0, q1, q2) - beta0;
-    if (db == 0.0) return make_double2(0, 0);
-    return cscale(box_value(b, src, q0, q1, q2), db);
-}
-
 // With rcorr (residual-corrected sources): on the core of a the source is
 // built from the FP64 residual r = f - L_h u of the current iterate instead:
 //     g_a(p) = r(p) - sum_{b: lag >= 2} Psi_{b->a}(uhat_b^s + ... + uhat_b^{s-lag+2})(p),
@@ -279,14 +254,19 @@ __device__ inline double2 dweighted(const SubDesc &b, const int *dd, const TIN *
 // thread per node of the strip list (the nodes within n_ov core layers of
 // a box side) adds the neighbour terms, so that no lane idles on the many
 // nodes far from every interface.
-template <typename TIN, typename TOUT, bool PHI>
+// One thread per strip node and tile of up to RQ right-hand sides: the
+// geometry of every neighbour term (which stencil points lie in b's box, their
+// cut-off weights and packed indices) is worked out once and applied to every
+// RHS of the tile.
+template <typename TIN, typename TOUT, bool PHI, int RQ>
 __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__ subs, const Coef *__restrict__ coef,
                                                      const double *__restrict__ k2, const double *__restrict__ btab,
                                                      const TIN *__restrict__ l1, const TIN *__restrict__ l2,
                                                      const TIN *__restrict__ l3, TOUT *__restrict__ g, PackArgs A,
                                                      const double2 *__restrict__ rcorr, const int2 *__restrict__ strip,
-                                                     long long nstrip) {
-    const int rhs = blockIdx.y;
+                                                     long long nstrip, int nrhs) {
+    const int r0 = blockIdx.y * RQ;
+    const int nr = nrhs - r0 < RQ ? nrhs - r0 : RQ;
     const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= nstrip) return;
     const int2 se = strip[t];
@@ -296,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
     const int lx = (int)(e % s.n[0]), ly = (int)((e / s.n[0]) % s.n[1]), lz = (int)(e / ((long long)s.n[0] * s.n[1]));
     int p[3] = {s.lo[0] + lx, s.lo[1] + ly, s.lo[2] + lz};
     int l[3] = {lx, ly, lz};
-    double2 acc = make_double2(0, 0);
+    double2 acc[RQ];
     // strip membership per axis: inlo = one of the first n_ov core layers
     // (faces the lower neighbour), inhi = one of the last n_ov core layers;
     // both can hold when the core is narrower than 2 n_ov
@@ -308,8 +288,11 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
     }
     const bool corrected = rcorr && p[0] >= s.clo[0] && p[0] <= s.chi[0] && p[1] >= s.clo[1] &&
                            p[1] <= s.chi[1] && p[2] >= s.clo[2] && p[2] <= s.chi[2];
-    if (corrected) acc = rcorr[rhs * A.nglob + glob_index(A, p[0], p[1], p[2])];
-    const double kk = PHI ? 0.0 : k2[glob_index(A, p[0], p[1], p[2])];
+    const long long gi = glob_index(A, p[0], p[1], p[2]);
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+        acc[q] = (corrected && q < nr) ? rcorr[(long long)(r0 + q) * A.nglob + gi] : make_double2(0, 0);
+    const double kk = PHI ? 0.0 : k2[gi];
     Coef cf[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) cf[d] = coef[s.coff[d] + l[d]];
@@ -341,52 +324,72 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
                     src2 = lag == 3 ? l2 : nullptr;
                 }
                 if (!src) continue;
-                src += rhs * A.etot;
-                if (src2) src2 += rhs * A.etot;
                 const SubDesc &b = subs[bidx];
-                double2 Lw;
-                if constexpr (PHI) {
-                    // commutator: sum_d cp (beta_+ - beta_0) v_+ + cm (beta_- - beta_0) v_-
-                    const double b0 = in_box(b, p[0], p[1], p[2]) ? beta_ba(b, dd, btab, A.n_ov, p[0], p[1], p[2]) : 0.0;
-                    auto dsum = [&](int q0, int q1, int q2) {
-                        double2 v = dweighted(b, dd, src, btab, A.n_ov, b0, q0, q1, q2);
-                        if (src2) v = cadd(v, dweighted(b, dd, src2, btab, A.n_ov, b0, q0, q1, q2));
-                        return v;
-                    };
-                    Lw = make_double2(0, 0);
+                // stencil points: 0 = p, 2d + 1 = p + e_d, 2d + 2 = p - e_d;
+                // weight of the packed value at each (direct: beta, Phi form:
+                // beta - beta(p)), its packed index, -1 outside b's box or
+                // a's box
+                double wt[7];
+                long long li[7];
+                auto point = [&](int j, int q0, int q1, int q2) {
+                    if (!in_box(b, q0, q1, q2)) { li[j] = -1; wt[j] = 0.0; return; }
+                    wt[j] = beta_ba(b, dd, btab, A.n_ov, q0, q1, q2);
+                    li[j] = b.off + (long long)(q0 - b.lo[0]) +
+                            (long long)b.n[0] * ((long long)(q1 - b.lo[1]) + (long long)b.n[1] * (q2 - b.lo[2]));
+                };
+                point(0, p[0], p[1], p[2]);
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        if (d >= A.dim) continue;
-                        int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
-                        qp[d] += 1;
-                        qm[d] -= 1;
-                        double2 dp = p[d] < s.hi[d] ? dsum(qp[0], qp[1], qp[2]) : make_double2(0, 0);
-                        double2 dm = p[d] > s.lo[d] ? dsum(qm[0], qm[1], qm[2]) : make_double2(0, 0);
-                        Lw = cadd(Lw, cadd(cmul(cf[d].cp, dp), cmul(cf[d].cm, dm)));
-                    }
-                } else {
-                    auto wsum = [&](int q0, int q1, int q2) {
-                        double2 v = weighted(b, dd, src, btab, A.n_ov, q0, q1, q2);
-                        if (src2) v = cadd(v, weighted(b, dd, src2, btab, A.n_ov, q0, q1, q2));
-                        return v;
-                    };
-                    double2 w0 = wsum(p[0], p[1], p[2]);
-                    Lw = cscale(w0, kk);
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        if (d >= A.dim) continue;
-                        int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
-                        qp[d] += 1;
-                        qm[d] -= 1;
-                        double2 wp = p[d] < s.hi[d] ? wsum(qp[0], qp[1], qp[2]) : make_double2(0, 0);
-                        double2 wm = p[d] > s.lo[d] ? wsum(qm[0], qm[1], qm[2]) : make_double2(0, 0);
-                        Lw = cadd(Lw, csub(cmul(cf[d].cp, csub(wp, w0)), cmul(cf[d].cm, csub(w0, wm))));
-                    }
+                for (int d = 0; d < 3; ++d) {
+                    li[2 * d + 1] = li[2 * d + 2] = -1;
+                    wt[2 * d + 1] = wt[2 * d + 2] = 0.0;
+                    if (d >= A.dim) continue;
+                    int qp[3] = {p[0], p[1], p[2]}, qm[3] = {p[0], p[1], p[2]};
+                    qp[d] += 1;
+                    qm[d] -= 1;
+                    if (p[d] < s.hi[d]) point(2 * d + 1, qp[0], qp[1], qp[2]);
+                    if (p[d] > s.lo[d]) point(2 * d + 2, qm[0], qm[1], qm[2]);
                 }
-                // plain: acc += Psi = -L(beta v); corrected: acc -= Psi
-                acc = corrected ? cadd(acc, Lw) : csub(acc, Lw);
+                if constexpr (PHI) {
+                    const double b0 = wt[0];
+#pragma unroll
+                    for (int j = 1; j < 7; ++j) wt[j] -= b0;
+                }
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) {
+                    if (q >= nr) continue;
+                    const long long ro = (long long)(r0 + q) * A.etot;
+                    auto val = [&](int j) {
+                        if (li[j] < 0 || wt[j] == 0.0) return make_double2(0, 0);
+                        double2 v = to_d2(src[ro + li[j]]);
+                        if (src2) v = cadd(v, to_d2(src2[ro + li[j]]));
+                        return cscale(v, wt[j]);
+                    };
+                    double2 Lw;
+                    if constexpr (PHI) {
+                        // commutator: sum_d cp (beta_+ - beta_0) v_+ + cm (beta_- - beta_0) v_-
+                        Lw = make_double2(0, 0);
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            if (d >= A.dim) continue;
+                            Lw = cadd(Lw, cadd(cmul(cf[d].cp, val(2 * d + 1)), cmul(cf[d].cm, val(2 * d + 2))));
+                        }
+                    } else {
+                        const double2 w0 = val(0);
+                        Lw = cscale(w0, kk);
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            if (d >= A.dim) continue;
+                            const double2 wp = val(2 * d + 1), wm = val(2 * d + 2);
+                            Lw = cadd(Lw, csub(cmul(cf[d].cp, csub(wp, w0)), cmul(cf[d].cm, csub(w0, wm))));
+                        }
+                    }
+                    // plain: acc += Psi = -L(beta v); corrected: acc -= Psi
+                    acc[q] = corrected ? cadd(acc[q], Lw) : csub(acc[q], Lw);
+                }
             }
-    g[rhs * A.etot + s.off + e] = from_d2<TOUT>(acc);
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+        if (q < nr) g[(long long)(r0 + q) * A.etot + s.off + e] = from_d2<TOUT>(acc[q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -466,13 +469,14 @@ hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TI
     }
     const long long ns = (long long)P.strip.size();
     if (ns > 0) {
-        dim3 grid((unsigned)((ns + kBlock - 1) / kBlock), nrhs);
+        constexpr int RQ = 4;
+        dim3 grid((unsigned)((ns + kBlock - 1) / kBlock), (nrhs + RQ - 1) / RQ);
         if (h->transfer_form == DDM_TRANSFER_PHI)
-            k_transfer<TIN, TOUT, true><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2,
-                                                                        l3, g, pack_args(P), rcorr, h->d_strip, ns);
+            k_transfer<TIN, TOUT, true, RQ><<<grid, kBlock, 0, h->stream>>>(
+                h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g, pack_args(P), rcorr, h->d_strip, ns, nrhs);
         else
-            k_transfer<TIN, TOUT, false><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1,
-                                                                         l2, l3, g, pack_args(P), rcorr, h->d_strip, ns);
+            k_transfer<TIN, TOUT, false, RQ><<<grid, kBlock, 0, h->stream>>>(
+                h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g, pack_args(P), rcorr, h->d_strip, ns, nrhs);
     }
     return hipGetLastError();
 }
