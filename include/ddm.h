@@ -231,18 +231,20 @@ int ddm_profile_read(ddm_handle *h, ddm_profile *out);
  *      with the one-directional factor layout);
  *   1  one workgroup per elimination chain walking all its blocks, the block
  *      recurrence kept on chip (block size <= 256).  With the twisted layout
- *      (default when there are at most 128 subdomains) every subdomain has two
+ *      (default when 2 nsub workgroups fit on the device's compute units, at
+ *      most 128 subdomains on a 256-CU MI355X) every subdomain has two
  *      chains that meet once at a middle block;
  *   2  two workgroups per chain of the twisted layout, each taking half of
  *      every block's columns and exchanging partial sums with its partner
- *      once per block (block size <= 256, at most 64 subdomains so that all
- *      4 nsub workgroups are resident, RHS in tiles of up to 4): for
- *      problems with fewer chains than CUs. */
+ *      once per block (block size <= 256, all 4 nsub workgroups resident:
+ *      at most 64 subdomains on a 256-CU MI355X, RHS in tiles of up to 4):
+ *      for problems with fewer chains than CUs. */
 enum { DDM_SOLVE_PERLINE = 0, DDM_SOLVE_CHAIN = 1, DDM_SOLVE_CHAIN2 = 2, DDM_SOLVE_NVARIANTS = 3 };
 
 /* Factor layout: twisted != 0 eliminates every subdomain from both ends
  * towards a middle block (two chains per subdomain), 0 from the first block
- * on.  Default: twisted when there are at most 128 subdomains.  Changing it
+ * on.  Default: twisted when every chain can have its own compute unit
+ * (2 nsub <= CUs: at most 128 subdomains on MI355X).  Changing it
  * discards the factors (call ddm_factor again). */
 int ddm_set_factor_layout(ddm_handle *h, int twisted);
 

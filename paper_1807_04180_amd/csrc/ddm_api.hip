@@ -623,6 +623,8 @@ int ddm_set_factor_layout(ddm_handle *h, int twisted) {
     if (!h) return DDM_EINVAL;
     if (twisted && !solve_variant_ok(h->plan, kSolveChain))
         return fail(h, DDM_EINVAL, "the twisted layout needs the chain substitution (block size <= 256)");
+    if (twisted && 2 * h->plan.nsub > h->plan.ncu)
+        return fail(h, DDM_EINVAL, "the twisted layout needs one resident workgroup per chain (2 nsub <= compute units)");
     (void)hipStreamSynchronize(h->stream);
     plan_set_twist(&h->plan, twisted != 0);
     if (hipMemcpy(h->d_subs, h->plan.subs.data(), h->plan.subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice) !=
@@ -859,6 +861,16 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
     std::string err;
     int st = build_plan(p, &h->plan, &err);
     if (st) { delete h; return fail(nullptr, st, err); }
+    {
+        // the chain launches need every workgroup resident: bound them by this
+        // device's compute units (the plan assumes 256 until it knows)
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) {
+            h->plan.ncu = ncu;
+            if (h->plan.twisted && !plan_twist_fits(h->plan)) plan_set_twist(&h->plan, false);
+        }
+    }
     h->prob = *p;
     h->mixed = p->precision == DDM_MIXED;
     h->nrhs_max = nrhs_max;

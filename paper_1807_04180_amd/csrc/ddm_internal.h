@@ -78,6 +78,7 @@ struct Plan {
     std::vector<double> btab;   // side cut-off factor b(m), m = 0 .. n_ov
     std::vector<SolveItem> items;
     bool twisted = false;           // factor layout: both-ends elimination
+    int ncu = 256;                  // compute units of the device: co-residency bound of the chain launches
     std::vector<double> w_el_by_l;  // sum over subdomains with > l blocks of bs^2
     std::vector<double> v_el_by_l;  // same, of bs
 };
@@ -85,6 +86,7 @@ struct Plan {
 int build_plan(const ddm_problem *p, Plan *plan, std::string *err);
 // choose the elimination layout (sets mid of every subdomain)
 void plan_set_twist(Plan *plan, bool twisted);
+bool plan_twist_fits(const Plan &P);
 
 }  // namespace ddm
 

@@ -191,9 +191,9 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
             P.v_el_by_l[l] += (double)s.bs;
         }
     // two chains per subdomain (both-ends elimination) while they all fit on
-    // the chip's 256 compute units and the chain kernel applies (block size
-    // <= 256), one otherwise
-    plan_set_twist(&P, P.nsub <= 128 && P.nb_max >= 4 && P.bs_max <= 256);
+    // the device's compute units (one 1024-thread chain workgroup per CU) and
+    // the chain kernel applies (block size <= 256), one otherwise
+    plan_set_twist(&P, plan_twist_fits(P));
     P.btab.resize(p->n_ov + 1);
     for (int m = 0; m <= p->n_ov; ++m)
         P.btab[m] = m <= 1 ? 1.0 : (m >= p->n_ov ? 0.0 : beta0((double)(m - 1) / (double)(p->n_ov - 1)));
@@ -248,6 +248,8 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
     }
     return DDM_OK;
 }
+
+bool plan_twist_fits(const Plan &P) { return 2 * P.nsub <= P.ncu && P.nb_max >= 4 && P.bs_max <= 256; }
 
 void plan_set_twist(Plan *plan, bool twisted) {
     plan->twisted = twisted;

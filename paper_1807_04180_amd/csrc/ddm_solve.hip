@@ -834,7 +834,7 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
         // more RHS: 512-thread workgroups (256 VGPRs per lane) hold 8 or 16
         // RHS per tile, so each inverse is streamed once per tile of 16;
         // a twisted launch needs every workgroup resident (one per CU here)
-        const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= 256;
+        const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= h->plan.ncu;
         if (coop_ok && nrhs > 8 && chain_lds<T, 16, 1, 512>(h->plan.bs_max) <= kLdsMax)
             return run_chain<T, 16, 1, 512>(h, g, x, nrhs);
         if (coop_ok && chain_lds<T, 8, 1, 512>(h->plan.bs_max) <= kLdsMax) return run_chain<T, 8, 1, 512>(h, g, x, nrhs);
@@ -846,7 +846,7 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
         if (nrhs <= 8) return run_chain<T, 8, 1>(h, g, x, nrhs);
         // 16 RHS with 16-byte loads needs the 256-VGPR budget of 512-thread
         // workgroups (and 8 work pairs to fit the partial sums in LDS)
-        const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= 256;
+        const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= h->plan.ncu;
         if (coop_ok && chain_lds<T, 16, 2, 512, 8>(h->plan.bs_max) <= kLdsMax)
             return run_chain<T, 16, 2, 512, 8>(h, g, x, nrhs);
         return run_chain<T, 16, 1>(h, g, x, nrhs);
@@ -912,7 +912,7 @@ static hipError_t run_chain2_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
 // the split substitution fits this plan's blocks and subdomain count (it
 // also needs the two-ended layout)
 bool chain2_fits(const Plan &P) {
-    return P.bs_max <= 256 && chain2_grid(P) <= 256 && chain2_lds<double2, 4, 1>(P.bs_max) <= kLdsMax &&
+    return P.bs_max <= 256 && chain2_grid(P) <= P.ncu && chain2_lds<double2, 4, 1>(P.bs_max) <= kLdsMax &&
            chain2_lds<float2, 4, 2>(P.bs_max) <= kLdsMax;
 }
 
@@ -920,7 +920,7 @@ bool solve_variant_ok(const Plan &P, int variant) {
     switch (variant) {
         case kSolvePerLine: return !P.twisted;
         case kSolveChain: return P.bs_max <= 256;
-        case kSolveChain2: return P.twisted && chain2_fits(P);  // one workgroup per CU (256 CUs)
+        case kSolveChain2: return P.twisted && chain2_fits(P);  // one workgroup per CU
         default: return false;
     }
 }
