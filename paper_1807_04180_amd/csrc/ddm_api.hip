@@ -84,7 +84,7 @@ void dalloc(ddm_handle *h, T **p, size_t count) {
 
 size_t elem_size(bool mixed) { return mixed ? sizeof(float2) : sizeof(double2); }
 
-int norm_blocks(const Plan &P) { return P.G[1] * P.G[2]; }
+int norm_blocks(const Plan &P) { return stencil_blocks(P); }
 
 constexpr int kDotBlocks = 256;
 

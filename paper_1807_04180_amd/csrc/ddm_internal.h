@@ -192,6 +192,12 @@ hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs);
 // substitution variants
 enum { kSolvePerLine = 0, kSolveChain = 1, kSolveChain2 = 2, kSolveNVariants = 3 };
 bool solve_variant_ok(const Plan &P, int variant);
+
+// XCDs of the chip: workgroups are placed on them round-robin by index
+constexpr int kXcds = 8;
+// blocks of the row-per-block stencil launches: grid rows padded to a
+// multiple of the XCD count
+inline int stencil_blocks(const Plan &P) { return (P.G[1] * P.G[2] + kXcds - 1) / kXcds * kXcds; }
 size_t chain2_xbuf_bytes(const Plan &P);
 bool chain2_fits(const Plan &P);
 

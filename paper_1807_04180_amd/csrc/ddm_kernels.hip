@@ -69,7 +69,11 @@ __device__ inline double2 apply_global_at(const double2 *__restrict__ u, const d
 }
 
 // mode 0: out = f - L u and partial norms of out and f; mode 1: out = L u.
-// One block per grid row (fixed y, z) and RHS; threads along x.
+// One block per grid row (fixed y, z) and RHS; threads along x.  Workgroups
+// go to the 8 XCDs round-robin, so block b takes row (b % 8) chunk + b / 8:
+// each XCD sweeps one contiguous band of rows and the rows above and below
+// a row are read from its own L2 (a plain row-per-block order spreads the
+// three readers of every row over three XCDs and fetched 2.2x the bytes).
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil(const double2 *__restrict__ f, const double2 *__restrict__ u,
                                                     double2 *__restrict__ out, const double *__restrict__ k2,
@@ -77,7 +81,15 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const double2 *__restrict__ 
                                                     double *__restrict__ part_r, double *__restrict__ part_f) {
     __shared__ double sh[kBlock / 64];
     const int rhs = blockIdx.y;
-    const int rowi = blockIdx.x;  // y + G1 * z
+    const int chunk = (int)gridDim.x / kXcds;
+    const int rowi = ((int)blockIdx.x % kXcds) * chunk + (int)blockIdx.x / kXcds;  // y + G1 * z
+    if (rowi >= g.G1 * g.G2) {  // padding block: zero partials
+        if (MODE == 0 && threadIdx.x == 0) {
+            part_r[(long long)rhs * gridDim.x + blockIdx.x] = 0.0;
+            part_f[(long long)rhs * gridDim.x + blockIdx.x] = 0.0;
+        }
+        return;
+    }
     const int y = rowi % g.G1, z = rowi / g.G1;
     const long long row0 = (long long)rowi * g.G0;
     const double2 *ur = u + rhs * g.nglob;
@@ -136,7 +148,7 @@ static GridArgs grid_args(const Plan &P) {
 
 hipError_t launch_apply(ddm_handle *h, const double2 *u, double2 *out, int nrhs) {
     const Plan &P = h->plan;
-    dim3 grid((unsigned)(P.G[1] * P.G[2]), nrhs);
+    dim3 grid((unsigned)stencil_blocks(P), nrhs);
     k_stencil<1><<<grid, kBlock, 0, h->stream>>>(nullptr, u, out, h->d_k2, h->d_gcoef, grid_args(P), nullptr, nullptr);
     return hipGetLastError();
 }
@@ -144,7 +156,7 @@ hipError_t launch_apply(ddm_handle *h, const double2 *u, double2 *out, int nrhs)
 hipError_t launch_residual(ddm_handle *h, const double2 *f, const double2 *u, double2 *r, int nrhs, double *d_rn2,
                            double *d_fn2) {
     const Plan &P = h->plan;
-    int nblk = P.G[1] * P.G[2];
+    int nblk = stencil_blocks(P);
     dim3 grid(nblk, nrhs);
     double *part_r = h->d_part, *part_f = h->d_part + (long long)nrhs * nblk;
     // f and u read, r written (if requested), k^2 read
