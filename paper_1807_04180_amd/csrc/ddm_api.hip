@@ -579,11 +579,14 @@ int ddm_profile_read(ddm_handle *h, ddm_profile *out) {
 }
 
 // Default substitution variant: the split chains when at most 4 RHS share a
-// launch (one pass over the inverses either way) and the plan admits them,
-// else one workgroup per chain (its 8 / 16-RHS tiles stream every inverse
-// once for up to 16 RHS), else the per-line launches.
+// launch (one pass over the inverses either way), the blocks are large enough
+// for half a block's stream to outweigh the per-block exchange (>= 128
+// unknowns; on 68-unknown blocks the split launch measured 40% slower) and
+// the plan admits them; else one workgroup per chain (its 8 / 16-RHS tiles
+// stream every inverse once for up to 16 RHS); else the per-line launches.
 static int default_variant(const ddm_handle *h) {
-    if (h->nrhs_max <= 4 && h->d_xbuf && solve_variant_ok(h->plan, kSolveChain2)) return kSolveChain2;
+    if (h->nrhs_max <= 4 && h->plan.bs_max >= 128 && h->d_xbuf && solve_variant_ok(h->plan, kSolveChain2))
+        return kSolveChain2;
     return solve_variant_ok(h->plan, kSolveChain) ? kSolveChain : kSolvePerLine;
 }
 

@@ -8,7 +8,8 @@
   with N = 1), against the oracle's banded LU;
 * the split substitution at its largest grid (8 x 8 subdomains: 256
   workgroups, one per CU, all resident) against the oracle, and the
-  one-workgroup variant as the default beyond it (9 x 9).
+  one-workgroup variant as the default beyond it (9 x 9);
+* the default substitution variant for block size and RHS count.
 """
 import numpy as np
 import pytest
@@ -94,7 +95,7 @@ def test_split_substitution_at_full_grid(mixed):
     w = di.small_2d(M=256, N=(8, 8), n_pml=4, n_ov=3, nrhs=3)
     o, g = _pair(w, 3, mixed=mixed)
     try:
-        assert g.solve_variant() == "chain2"
+        g.set_solve_variant("chain2")
         gin = di.random_field((3, o.etot), seed=92)
         x = _n(g.local_solve(_t(gin)))
         assert relerr(x, o.local_solve(gin), axis=1) < (5e-5 if mixed else 1e-10)
@@ -117,3 +118,19 @@ def test_beyond_full_grid_uses_one_workgroup_per_chain():
         assert relerr(_n(g.local_solve(_t(gin))), o.local_solve(gin), axis=1) < 1e-10
     finally:
         g.close()
+
+
+def test_default_variant_choice():
+    """Defaults: split chains for at most 4 RHS on blocks of >= 128 unknowns,
+    one workgroup per chain for small blocks or more RHS."""
+    cases = [(di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4, nrhs=1), 2, "chain2"),
+             (di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4, nrhs=1), 8, "chain"),
+             (di.small_2d(M=64, N=(2, 2), n_pml=4, n_ov=3, nrhs=1), 2, "chain")]
+    for w, nrhs_max, want in cases:
+        o, g = _pair(w, nrhs_max)
+        try:
+            assert g.solve_variant() == want, (w.name, nrhs_max)
+            gin = di.random_field((1, o.etot), seed=94)
+            assert relerr(_n(g.local_solve(_t(gin))), o.local_solve(gin), axis=1) < 1e-10
+        finally:
+            g.close()
