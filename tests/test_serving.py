@@ -109,10 +109,17 @@ def _workload_request(rid, w, mixed, t, seed, nrhs):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("blocks", ["small", "large"])
 @pytest.mark.parametrize("mixed", [False, True])
-def test_alone_vs_mix(mixed):
-    wa = di.small_2d(M=128, N=(2, 2), n_pml=6, n_ov=4)
-    wb = di.small_2d(M=144, N=(3, 3), n_pml=6, n_ov=4, layered=True, seed=2)
+def test_alone_vs_mix(mixed, blocks):
+    # small: blocks of 84-92 unknowns (one workgroup per chain); large: blocks
+    # of 148-160 unknowns, where handles of at most 4 slots use split chains
+    if blocks == "small":
+        wa = di.small_2d(M=128, N=(2, 2), n_pml=6, n_ov=4)
+        wb = di.small_2d(M=144, N=(3, 3), n_pml=6, n_ov=4, layered=True, seed=2)
+    else:
+        wa = di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4)
+        wb = di.small_2d(M=288, N=(2, 2), n_pml=8, n_ov=4, layered=True, seed=2)
     rng = np.random.default_rng(7)
     t = np.cumsum(rng.exponential(0.02, size=8))
     reqs = [_workload_request(i, wa if i % 2 == 0 else wb, mixed, float(t[i]), i, 1 + i % 3) for i in range(8)]
