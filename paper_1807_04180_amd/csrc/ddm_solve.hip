@@ -180,6 +180,13 @@ template <> struct ChainBatch<float2, 2> { static constexpr int value = 4; };
 template <typename T2, int ROWS> struct kLdsCols { static constexpr int value = 0; };
 template <> struct kLdsCols<double2, 1> { static constexpr int value = 4; };
 template <> struct kLdsCols<float2, 2> { static constexpr int value = 4; };
+// The split variant stages one column per wave: the wait for its exchange
+// stores (vmcnt 0) also waits for every prefetch load the wave has in flight,
+// so deeper staging lengthens the exchange (measured: 1 column is faster
+// than 0, 2, 3 or 4).
+template <typename T2, int ROWS> struct kLdsCols2 { static constexpr int value = 0; };
+template <> struct kLdsCols2<double2, 1> { static constexpr int value = 1; };
+template <> struct kLdsCols2<float2, 2> { static constexpr int value = 1; };
 
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
 constexpr int kWaitVm0 = 0x0F70;
@@ -558,7 +565,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__res
     const int bsp = R * 64 * ROWS;
     T2 *vs = (T2 *)lds_raw;                  // [bsp][RT] current v (own columns used)
     T2 *red = vs + (size_t)bsp * RT;         // [CG][RT][bsp] partial sums
-    constexpr int PF = kLdsCols<T2, ROWS>::value;
+    constexpr int PF = kLdsCols2<T2, ROWS>::value;
     T2 *mypf = red + (size_t)CG * RT * bsp + (size_t)wv * PF * 64 * ROWS;
     const int nf = chain == 0 ? mid : nb - 1 - mid;
     const int nsteps = 2 * nf + 1;
@@ -832,11 +839,16 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
         if (nrhs <= 2) return run_chain<T, 2, 1>(h, g, x, nrhs);
         if (nrhs <= 4) return run_chain<T, 4, 1>(h, g, x, nrhs);
         // more RHS: 512-thread workgroups (256 VGPRs per lane) hold 8 or 16
-        // RHS per tile, so each inverse is streamed once per tile of 16;
-        // a twisted launch needs every workgroup resident (one per CU here)
+        // RHS per tile; a twisted launch needs every workgroup resident (one
+        // per CU here).  Batches of 16 or more take 16-RHS tiles, which stream
+        // each inverse once per 16 RHS (2048^2 layered, 16 RHS: 18.5 against
+        // 22.5 ms per local solve in 8-RHS tiles); their partial sums fit in
+        // LDS only on the 8-pair partition, so such batches round differently
+        // from batches of up to 15, which keep the 16-pair partition of every
+        // smaller tile (a RHS alone or in any such batch: the same bits)
         const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= h->plan.ncu;
-        if (coop_ok && nrhs > 8 && chain_lds<T, 16, 1, 512>(h->plan.bs_max) <= kLdsMax)
-            return run_chain<T, 16, 1, 512>(h, g, x, nrhs);
+        if (coop_ok && nrhs >= 16 && chain_lds<T, 16, 1, 512, 8>(h->plan.bs_max) <= kLdsMax)
+            return run_chain<T, 16, 1, 512, 8>(h, g, x, nrhs);
         if (coop_ok && chain_lds<T, 8, 1, 512>(h->plan.bs_max) <= kLdsMax) return run_chain<T, 8, 1, 512>(h, g, x, nrhs);
         return run_chain<T, 4, 1>(h, g, x, nrhs);
     } else {
@@ -866,7 +878,7 @@ static size_t chain2_lds(int bs_max) {
     const int R = (bs_max + 64 * ROWS - 1) / (64 * ROWS);
     const int CG = kCWaves / R;
     return (size_t)R * 64 * ROWS * RT * (1 + CG) * sizeof(T2) +
-           (size_t)kCWaves * kLdsCols<T2, ROWS>::value * 64 * ROWS * sizeof(T2);
+           (size_t)kCWaves * kLdsCols2<T2, ROWS>::value * 64 * ROWS * sizeof(T2);
 }
 
 template <typename T2, int RT, int ROWS>

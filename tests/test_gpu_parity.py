@@ -2,7 +2,7 @@
 oracle on the same seeded inputs, element by element.
 
 Sizes: subdomain blocks of 75-98 nodes span two 64-row tiles of the
-substitution kernel with a ragged tail; RHS counts 1, 3, 5 and 9 exercise
+substitution kernel with a ragged tail; RHS counts 1, 3, 5, 9, 16 and 20 exercise
 ragged RHS tiles; layouts 2x2, 3x2 and 3x3 mix interior, edge and corner
 boxes of different sizes in one launch.
 
@@ -221,6 +221,26 @@ def test_chain_mixed_matches_oracle():
         gin = di.random_field((nrhs, o.etot), seed=51)
         assert relerr(_n(g.local_solve(_t(gin))), o.local_solve(gin), axis=1) < 5e-5
     g.close()
+
+
+@pytest.mark.parametrize("case", ["2d-3x3-layered", "2d-2x2-146"])
+def test_chain_16_rhs_tiles_fp64(case):
+    """Complex128 batches of 16 or more RHS take 16-RHS tiles (8-pair
+    partition), on blocks of two (75-98 nodes) and three (146 nodes) 64-row
+    tiles: oracle parity for 16 RHS, and every RHS gives the same bits in a
+    batch of 20 (reordered, the last 4 in a ragged second tile)."""
+    w = CASES[case]() if case in CASES else di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4, nrhs=1)
+    o, g = make_pair(w, nrhs_max=20)
+    try:
+        assert g.solve_variant() == "chain"
+        gin = di.random_field((16, o.etot), seed=54)
+        x16 = _n(g.local_solve(_t(gin)))
+        assert relerr(x16, o.local_solve(gin), axis=1) < 1e-10
+        x20 = _n(g.local_solve(_t(np.concatenate([gin[::-1], gin[:4]]))))
+        assert np.array_equal(x20[:16], x16[::-1])
+        assert np.array_equal(x20[16:], x16[:4])
+    finally:
+        g.close()
 
 
 def test_chain2_mixed_matches_oracle():
