@@ -128,8 +128,9 @@ __global__ __launch_bounds__(kSThreads) void k_solve_line(const SubDesc *__restr
 //   back:    x_l = y_l - W_l (cp(l) x_{l+1})  (chain 0, l = mid-1 .. 0)
 //            x_l = y_l - W_l (cm(l) x_{l-1})  (chain 1, l = mid+1 .. nb-1)
 // (W_l here is the stored inverse of the chain's Schur block.)  The two
-// chains of a subdomain meet once, at the middle block: each publishes its
-// last y through global memory with an agent-scope release/acquire pair.
+// chains of a subdomain meet once, at the middle block: each stores its last
+// y block with relaxed agent-scope atomics and raises a flag, the other
+// reads it with atomic loads once it has seen the flag (no fences).
 // GEMV mapping: R = ceil(bs/64) row tiles, CG = 16 / R column groups; wave w
 // takes row tile w % R and columns w / R, w / R + CG, ...  The first batch of
 // the next block's W is loaded before the current block's reduction.
@@ -138,19 +139,51 @@ constexpr int kCThreads = 1024;
 constexpr int kCWaves = 16;
 constexpr size_t kLdsMax = 160 * 1024;  // LDS per workgroup on gfx950
 
-__device__ inline void wait_flag(int *f, int target, int *abort_flag, int spin_limit) {
+// Meetings of workgroups without cache maintenance: an agent-scope fence on
+// this chip writes back and invalidates the whole L2 (at one exchange per
+// block and 256 workgroups that costs more than the block itself; at the one
+// meeting per launch of the two chains of a subdomain it cost 0.19 ms of a
+// 2.46 ms split local solve).  The exchanged words and the flags are instead
+// relaxed agent-scope atomics (coherent at the agent level without touching
+// other cached data); the writer waits for its stores to complete (s_waitcnt
+// 0: stores count in vmcnt here) before a barrier and the flag store, and
+// the reader loads the words only after it has seen the flag (and a
+// barrier).  Every wait is bounded (spin_limit) and stops at once after a
+// sticky abort.
+__device__ inline void wait_flag_relaxed(int *f, int target, int *abort_flag, int spin_limit) {
     if (threadIdx.x == 0) {
         int spins = 0;
         while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(2);
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            __builtin_amdgcn_s_sleep(1);
             if (++spins >= spin_limit) {
                 __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
         }
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
     }
     __syncthreads();
+}
+
+__device__ inline void xstore(double2 *p, double2 v) {
+    unsigned long long *q = (unsigned long long *)p;
+    __hip_atomic_store(q, __double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, __double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void xstore(float2 *p, float2 v) {
+    const unsigned long long w = (unsigned long long)__float_as_uint(v.x) |
+                                 ((unsigned long long)__float_as_uint(v.y) << 32);
+    __hip_atomic_store((unsigned long long *)p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double2 xload(double2 *p) {
+    unsigned long long *q = (unsigned long long *)p;
+    return make_double2(__longlong_as_double(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
+                        __longlong_as_double(__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+}
+__device__ inline float2 xload(float2 *p) {
+    const unsigned long long w =
+        __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((unsigned)w), __uint_as_float((unsigned)(w >> 32)));
 }
 
 // Rows per lane: complex64 lanes take two consecutive rows so that every
@@ -296,16 +329,17 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
             if (t == nf) {
                 // entering the middle block: v = g_mid - cm(mid) y_{mid-1} - cp(mid) y_{mid+1}
                 const Coef cmid = coef[s.coff[ax] + mid];
-                __syncthreads();  // this chain's y stores are issued
+                // the last y block of each chain was stored with relaxed
+                // agent-scope atomics (the other chain reads it here)
+                __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are complete
+                __syncthreads();
                 if (twisted) {
                     // flags count RHS tiles: tile k publishes k + 1 (no reset
                     // inside the launch, so a fast chain cannot erase a signal)
                     const int epoch = r0 / RT + 1;
-                    __threadfence();
-                    __syncthreads();
                     if (threadIdx.x == 0)
-                        __hip_atomic_store(flags + 2 * a + chain, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    wait_flag(flags + 2 * a + (1 - chain), epoch, abort_flag, spin_limit);
+                        __hip_atomic_store(flags + 2 * a + chain, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    wait_flag_relaxed(flags + 2 * a + (1 - chain), epoch, abort_flag, spin_limit);
                 }
                 for (int e = threadIdx.x; e < bsp * RT; e += NT) {
                     const int i = e / RT, q = e % RT;
@@ -313,8 +347,9 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
                     if (i < bs && q < nr) {
                         const long long base = (long long)(r0 + q) * etot + off;
                         v = to_d2(g[base + (long long)mid * bs + i]);
-                        if (mid > 0) v = cmsub_fixed(v, cmid.cm, to_d2(x[base + (long long)(mid - 1) * bs + i]));
-                        if (mid < nb - 1) v = cmsub_fixed(v, cmid.cp, to_d2(x[base + (long long)(mid + 1) * bs + i]));
+                        if (mid > 0) v = cmsub_fixed(v, cmid.cm, to_d2(xload(x + base + (long long)(mid - 1) * bs + i)));
+                        if (mid < nb - 1)
+                            v = cmsub_fixed(v, cmid.cp, to_d2(xload(x + base + (long long)(mid + 1) * bs + i)));
                     }
                     vs[e] = from_d2<T2>(v);
                 }
@@ -332,7 +367,9 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
                 const int i = e / RT, q = e % RT;
                 const bool ok = e < bsp * RT && i < bs && q < nr;
                 const long long base = (long long)(ok ? r0 + q : 0) * etot + off;
-                if (kind == 2) pre[u] = ok ? x[base + (long long)l * bs + i] : czero<T2>();
+                if (kind == 2)  // the first backward block is the atomically stored one
+                    pre[u] = ok ? (t == nf + 1 ? xload(x + base + (long long)l * bs + i) : x[base + (long long)l * bs + i])
+                                : czero<T2>();
                 else if (kind == 0 && lnv >= 0) pre[u] = ok ? g[base + (long long)lnv * bs + i] : czero<T2>();
                 else pre[u] = czero<T2>();
             }
@@ -428,7 +465,10 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
                     res.x = pre[u].x - sum.x;
                     res.y = pre[u].y - sum.y;
                 }
-                if (q < nr && (kind != 1 || chain == 0)) x[base + (long long)l * bs + i] = res;
+                if (q < nr && (kind != 1 || chain == 0)) {
+                    if (t == nf - 1) xstore(x + base + (long long)l * bs + i, res);  // read at the middle
+                    else x[base + (long long)l * bs + i] = res;
+                }
                 if (lnv >= 0) {
                     // next v from this block's result
                     double2 v;
@@ -465,66 +505,6 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
 // tiles of 4).  Every wait is bounded (spin_limit) and stops at once after a
 // sticky abort.
 // ---------------------------------------------------------------------------
-__device__ inline void wait_flag2(int *f, int target, int *abort_flag, int spin_limit) {
-    if (threadIdx.x == 0) {
-        int spins = 0;
-        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins >= spin_limit) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-        }
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    }
-    __syncthreads();
-}
-
-// Per-block exchange without cache maintenance: an agent-scope fence on this
-// chip writes back and invalidates the whole L2, which at one exchange per
-// block and 256 workgroups costs more than the block itself.  The exchanged
-// words and the flags are instead relaxed agent-scope atomics (coherent at
-// the agent level without touching other cached data); the writer waits for
-// its stores to complete (s_waitcnt 0: stores count in vmcnt here) before a
-// barrier and the flag store, and the reader loads the words only after it
-// has seen the flag (and a barrier).
-__device__ inline void wait_flag_relaxed(int *f, int target, int *abort_flag, int spin_limit) {
-    if (threadIdx.x == 0) {
-        int spins = 0;
-        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins >= spin_limit) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-        }
-    }
-    __syncthreads();
-}
-
-__device__ inline void xstore(double2 *p, double2 v) {
-    unsigned long long *q = (unsigned long long *)p;
-    __hip_atomic_store(q, __double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(q + 1, __double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void xstore(float2 *p, float2 v) {
-    const unsigned long long w = (unsigned long long)__float_as_uint(v.x) |
-                                 ((unsigned long long)__float_as_uint(v.y) << 32);
-    __hip_atomic_store((unsigned long long *)p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double2 xload(double2 *p) {
-    unsigned long long *q = (unsigned long long *)p;
-    return make_double2(__longlong_as_double(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
-                        __longlong_as_double(__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-}
-__device__ inline float2 xload(float2 *p) {
-    const unsigned long long w =
-        __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return make_float2(__uint_as_float((unsigned)w), __uint_as_float((unsigned)(w >> 32)));
-}
-
 // elements per (unit, half) exchange slot: rows of the partner (<= 128 for
 // bs <= 256) times the RHS tile (<= 4)
 constexpr int kXSlot = 128 * 4;
@@ -610,19 +590,20 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__res
                 // other chain's same half wrote y_{mid+1} there
                 const Coef cmid = coef[s.coff[ax] + mid];
                 const int epoch = r0 / RT + 1;
-                __threadfence();
+                __builtin_amdgcn_s_waitcnt(0);  // this wave's stores of the last y block are complete
                 __syncthreads();
                 if (threadIdx.x == 0)
-                    __hip_atomic_store(mflags + 4 * a + 2 * chain + half, epoch, __ATOMIC_RELEASE,
+                    __hip_atomic_store(mflags + 4 * a + 2 * chain + half, epoch, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                wait_flag2(mflags + 4 * a + 2 * (1 - chain) + half, epoch, abort_flag, spin_limit);
+                wait_flag_relaxed(mflags + 4 * a + 2 * (1 - chain) + half, epoch, abort_flag, spin_limit);
                 if (own_ok) {
                     double2 v = make_double2(0, 0);
                     if (qo < nr) {
                         const long long base = (long long)(r0 + qo) * etot + off;
                         v = to_d2(g[base + (long long)mid * bs + io]);
-                        if (mid > 0) v = cmsub_fixed(v, cmid.cm, to_d2(x[base + (long long)(mid - 1) * bs + io]));
-                        if (mid < nb - 1) v = cmsub_fixed(v, cmid.cp, to_d2(x[base + (long long)(mid + 1) * bs + io]));
+                        if (mid > 0) v = cmsub_fixed(v, cmid.cm, to_d2(xload(x + base + (long long)(mid - 1) * bs + io)));
+                        if (mid < nb - 1)
+                            v = cmsub_fixed(v, cmid.cp, to_d2(xload(x + base + (long long)(mid + 1) * bs + io)));
                     }
                     vs[io * RT + qo] = from_d2<T2>(v);
                 }
@@ -633,7 +614,8 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__res
             T2 pre = czero<T2>();
             if (own_ok && qo < nr) {
                 const long long base = (long long)(r0 + qo) * etot + off;
-                if (kind == 2) pre = x[base + (long long)l * bs + io];
+                if (kind == 2)  // the first backward block is the atomically stored one
+                    pre = t == nf + 1 ? xload(x + base + (long long)l * bs + io) : x[base + (long long)l * bs + io];
                 else if (kind == 0 && lnv >= 0) pre = g[base + (long long)lnv * bs + io];
             }
             // ---- GEMV over the own columns: one work pair per wave ----
@@ -729,7 +711,10 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__res
                     res.x = pre.x - sum.x;
                     res.y = pre.y - sum.y;
                 }
-                if (qo < nr && (kind != 1 || chain == 0)) x[base + (long long)l * bs + io] = res;
+                if (qo < nr && (kind != 1 || chain == 0)) {
+                    if (t == nf - 1) xstore(x + base + (long long)l * bs + io, res);  // read at the middle
+                    else x[base + (long long)l * bs + io] = res;
+                }
                 if (lnv >= 0) {
                     double2 v;
                     const Coef cn = coef[s.coff[ax] + lnv];
