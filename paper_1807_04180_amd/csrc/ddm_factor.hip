@@ -14,7 +14,8 @@
 // pivoting:
 //   * panels of kPanel columns; a panel kernel (one workgroup per chain)
 //     picks the panel's pivot rows by unblocked elimination of a copy of the
-//     panel, inverts the kPanel x kPanel pivot block A11 and forms
+//     panel (left-looking for blocks above 512 rows), inverts the kPanel x
+//     kPanel pivot block A11 and forms
 //     Y = A11^{-1} [pivot rows of S] and X = -[panel columns of S], pivot rows
 //     zeroed;
 //   * an update kernel applies S <- S + X Y (panel columns start from zero,
@@ -383,6 +384,170 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel(const SubDesc *__res
     }
 }
 
+// Left-looking panel kernel for blocks of more than 512 rows (kLLRows rows
+// per thread at most).  The right-looking elimination above rewrites the
+// whole bs x kPanel working panel at every pivot step; here column t of the
+// eliminated panel is formed only when it becomes the pivot column, from the
+// stored multipliers F (the panel's L, in the workspace) and the pivot rows'
+// eliminated values U (in LDS):
+//   col_t(i) = S(i, k0 + t) - sum_{u < t} F_u(i) U(u, t),   F_t(i) = col_t(i) / U(t, t),
+//   U(t, t') = col_t'(r_t) (the same sum for the pivot row, t' >= t).
+// The pivots are those of partial pivoting on the panel.  A11^{-1} is the
+// in-place Gauss-Jordan inverse (pivots on the diagonal, in pivot order) of
+// the panel's original pivot rows; Y and X are formed as above.
+constexpr int kLLRows = 8;
+
+__global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__restrict__ subs, FactWs w, int s,
+                                                                int p, int mid, int *__restrict__ flags, int nsub) {
+    extern __shared__ double2 lds[];
+    __shared__ double sv[kPWaves];
+    __shared__ int si[kPWaves];
+    const int c = blockIdx.x;
+    const ChainPos q = chain_pos(subs, c, s, mid != 0);
+    if (!q.active) return;
+    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
+    if (k0 >= bs) return;
+    const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
+    const double2 *M = chain_M(w, c, q.cur);
+    double *Xr = w.X + (long long)c * 2 * kPanel * bsp, *Xi = Xr + (long long)kPanel * bsp;
+    double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
+    int *ppos = w.ppos + (long long)c * bsp, *piv = w.piv + (long long)c * bsp;
+    double2 *Ainv = lds;                      // [kPanel][kPanel]
+    double2 *U = Ainv + kPanel * kPanel;      // [kPanel][kPanel] pivot rows of the eliminated panel
+    int *R1 = (int *)(U + kPanel * kPanel);   // [kPanel]
+    int *ppos_s = R1 + kPanel;                // [bsp]
+    double2 *F = w.Pw + (long long)c * kPanel * bsp;  // [kPanel][bsp] multipliers
+    const int tid = threadIdx.x;
+    const double mx = slot_read(w.mxb + 2 * c + q.cur);
+    if (p == 0) {
+        for (int i = tid; i < bsp; i += kPThreads) ppos_s[i] = -1;
+        if (tid == 0) w.mxb[2 * c + (q.cur ^ 1)] = 0ull;  // the store of this step fills it
+    } else {
+        for (int i = tid; i < bsp; i += kPThreads) ppos_s[i] = ppos[i];
+    }
+    // X = -panel
+    for (int e = tid; e < kPanel * bsp; e += kPThreads) {
+        const int t = e / bsp, i = e % bsp;
+        const double2 v = (t < bw && i < bs) ? M[(long long)(k0 + t) * bs + i] : make_double2(0, 0);
+        Xr[e] = -v.x;
+        Xi[e] = -v.y;
+    }
+    __syncthreads();
+    double tiny2 = (double)bs * DBL_EPSILON;
+    tiny2 = tiny2 * tiny2 * mx;
+    int status = 0;
+    for (int t = 0; t < bw; ++t) {
+        // column t at this thread's candidate rows, and the best of them
+        double2 cv[kLLRows];
+        double best = -1.0;
+        int bi = bs;
+#pragma unroll
+        for (int k = 0; k < kLLRows; ++k) {
+            const int i = tid + k * kPThreads;
+            cv[k] = make_double2(0, 0);
+            if (i < bs && ppos_s[i] < 0) {
+                double2 v = M[(long long)(k0 + t) * bs + i];
+                for (int u = 0; u < t; ++u) v = csub(v, cmul(F[(long long)u * bsp + i], U[u * kPanel + t]));
+                cv[k] = v;
+                const double a2 = cabs2(v);
+                if (a2 > best) { best = a2; bi = i; }
+            }
+        }
+        block_argmax_n<kPWaves>(best, bi, sv, si);
+        const int r = bi < bs ? bi : bs - 1;  // no finite candidate: flagged below, indices stay in range
+        if (!(best > tiny2) && status == 0) status = 1 + q.l * bs + k0 + t;
+        // the pivot row's eliminated values in columns t .. bw-1
+        if (tid >= t && tid < bw) {
+            double2 v = M[(long long)(k0 + tid) * bs + r];
+            for (int u = 0; u < t; ++u) v = csub(v, cmul(F[(long long)u * bsp + r], U[u * kPanel + tid]));
+            U[t * kPanel + tid] = v;
+        }
+        if (tid == 0) {
+            ppos_s[r] = k0 + t;
+            R1[t] = r;
+        }
+        __syncthreads();
+        // multipliers of the remaining candidates
+        const double2 pinv = cinv(U[t * kPanel + t]);
+#pragma unroll
+        for (int k = 0; k < kLLRows; ++k) {
+            const int i = tid + k * kPThreads;
+            if (i < bs && ppos_s[i] < 0) F[(long long)t * bsp + i] = cmul(cv[k], pinv);
+        }
+        __syncthreads();
+    }
+    // A11 (original pivot rows, pivot order) and its in-place inverse by one wave
+    for (int e = tid; e < bw * bw; e += kPThreads) {
+        const int t = e / bw, u = e % bw;
+        Ainv[t * kPanel + u] = M[(long long)(k0 + u) * bs + R1[t]];
+    }
+    __syncthreads();
+    if (tid < 64) {
+        constexpr int kE = kPanel * kPanel / 64;  // elements per lane
+        for (int t = 0; t < bw; ++t) {
+            const double2 pi = cinv(Ainv[t * kPanel + t]);
+            double2 nv[kE];
+#pragma unroll
+            for (int k = 0; k < kE; ++k) {
+                const int e = tid + 64 * k, i = e / kPanel, u = e % kPanel;
+                nv[k] = make_double2(0, 0);
+                if (i < bw && u < bw) {
+                    const double2 rt = u == t ? pi : cmul(Ainv[t * kPanel + u], pi);  // new row t
+                    if (i == t) {
+                        nv[k] = rt;
+                    } else {
+                        const double2 f = Ainv[i * kPanel + t];
+                        nv[k] = u == t ? make_double2(-(f.x * pi.x - f.y * pi.y), -(f.x * pi.y + f.y * pi.x))
+                                       : csub(Ainv[i * kPanel + u], cmul(f, rt));
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < kE; ++k) {
+                const int e = tid + 64 * k, i = e / kPanel, u = e % kPanel;
+                if (i < bw && u < bw) Ainv[i * kPanel + u] = nv[k];
+            }
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS writes are done
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+    // pivot rows of S (all columns) into the panel work area (the multipliers are done)
+    double2 *Pw = F;
+    for (int e = tid; e < kPanel * bsp; e += kPThreads) {
+        const int u = e / bsp, j = e % bsp;
+        Pw[e] = (u < bw && j < bs) ? M[(long long)j * bs + R1[u]] : make_double2(0, 0);
+    }
+    __syncthreads();
+    // Y = A11^{-1} [pivot rows], with A11^{-1} itself in the panel columns
+    for (int e = tid; e < kPanel * bsp; e += kPThreads) {
+        const int t = e / bsp, j = e % bsp;
+        double2 y = make_double2(0, 0);
+        if (t < bw && j < bs) {
+            if (j >= k0 && j < k0 + bw) {
+                y = Ainv[t * kPanel + (j - k0)];
+            } else {
+                for (int u = 0; u < bw; ++u) cfma(y, Ainv[t * kPanel + u], Pw[u * bsp + j]);
+            }
+        }
+        Yr[e] = y.x;
+        Yi[e] = y.y;
+    }
+    // pivot rows take no part in X
+    for (int e = tid; e < bw * kPanel; e += kPThreads) {
+        const int t = e / kPanel, u = e % kPanel;
+        Xr[(long long)u * bsp + R1[t]] = 0.0;
+        Xi[(long long)u * bsp + R1[t]] = 0.0;
+    }
+    for (int i = tid; i < bsp; i += kPThreads) ppos[i] = ppos_s[i];
+    if (tid < bw) piv[k0 + tid] = R1[tid];
+    if (tid == 0 && status) {
+        int *fl = flags + (mid ? 2 * nsub + q.a : c);
+        if (*fl == 0) *fl = status;
+    }
+}
+
 // Pivot key of a candidate row: |value|^2 rounded to float, the low 10 bits
 // replaced by 1023 - row (ties and near-ties, to 1e-4 relative, go to the
 // smaller row); non-candidates have key 0.
@@ -725,6 +890,13 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
     hipError_t e = hipFuncSetAttribute(pw_in_lds ? (const void *)k_factor_panel<true> : (const void *)k_factor_panel<false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    // blocks above 512 rows: the left-looking panel (up to kLLRows rows per thread)
+    const bool use_ll = panel_kind == 2 && P.bs_max <= kLLRows * kPThreads;
+    const size_t lds_ll = (size_t)2 * kPanel * kPanel * sizeof(double2) + kPanel * sizeof(int) + (size_t)w.bsp * sizeof(int);
+    if (use_ll) {
+        e = hipFuncSetAttribute((const void *)k_factor_panel_ll, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_ll);
+        if (e != hipSuccess) return e;
+    }
     e = launch_fill_zero(w.mxb, (long long)2 * nc * sizeof(unsigned long long), h->stream);
     if (e != hipSuccess) return e;
     e = launch_fill_zero(h->d_flags, (long long)3 * P.nsub * sizeof(int), h->stream);
@@ -741,6 +913,8 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
                 k_factor_panel_r<256><<<nc, 256, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
             else if (panel_kind == 1)
                 k_factor_panel_r<512><<<nc, 512, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
+            else if (use_ll)
+                k_factor_panel_ll<<<nc, kPThreads, lds_ll, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
             else if (pw_in_lds)
                 k_factor_panel<true><<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
             else
