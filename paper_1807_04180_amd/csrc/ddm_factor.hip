@@ -410,7 +410,6 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__
     const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
     const double2 *M = chain_M(w, c, q.cur);
     double *Xr = w.X + (long long)c * 2 * kPanel * bsp, *Xi = Xr + (long long)kPanel * bsp;
-    double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
     int *ppos = w.ppos + (long long)c * bsp, *piv = w.piv + (long long)c * bsp;
     double2 *Ainv = lds;                      // [kPanel][kPanel]
     double2 *U = Ainv + kPanel * kPanel;      // [kPanel][kPanel] pivot rows of the eliminated panel
@@ -513,27 +512,9 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__
         }
     }
     __syncthreads();
-    // pivot rows of S (all columns) into the panel work area (the multipliers are done)
-    double2 *Pw = F;
-    for (int e = tid; e < kPanel * bsp; e += kPThreads) {
-        const int u = e / bsp, j = e % bsp;
-        Pw[e] = (u < bw && j < bs) ? M[(long long)j * bs + R1[u]] : make_double2(0, 0);
-    }
-    __syncthreads();
-    // Y = A11^{-1} [pivot rows], with A11^{-1} itself in the panel columns
-    for (int e = tid; e < kPanel * bsp; e += kPThreads) {
-        const int t = e / bsp, j = e % bsp;
-        double2 y = make_double2(0, 0);
-        if (t < bw && j < bs) {
-            if (j >= k0 && j < k0 + bw) {
-                y = Ainv[t * kPanel + (j - k0)];
-            } else {
-                for (int u = 0; u < bw; ++u) cfma(y, Ainv[t * kPanel + u], Pw[u * bsp + j]);
-            }
-        }
-        Yr[e] = y.x;
-        Yi[e] = y.y;
-    }
+    // A11^{-1} to the workspace (the multipliers are done): Y is formed by
+    // k_factor_formy over several workgroups per chain
+    for (int e = tid; e < kPanel * kPanel; e += kPThreads) F[e] = Ainv[e];
     // pivot rows take no part in X
     for (int e = tid; e < bw * kPanel; e += kPThreads) {
         const int t = e / kPanel, u = e % kPanel;
@@ -545,6 +526,56 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__
     if (tid == 0 && status) {
         int *fl = flags + (mid ? 2 * nsub + q.a : c);
         if (*fl == 0) *fl = status;
+    }
+}
+
+// Y = A11^{-1} [pivot rows of S] (kPanel x bsp, zero outside bw x bs, A11^{-1}
+// itself in the panel columns) for the left-looking panel, over kYGroups
+// workgroups per chain: the pivot rows are gathered (one element per row and
+// column of the column-major block) in chunks of 32 columns through LDS.
+constexpr int kYGroups = 8;
+constexpr int kYThreads = 256;
+
+__global__ __launch_bounds__(kYThreads) void k_factor_formy(const SubDesc *__restrict__ subs, FactWs w, int s, int p,
+                                                             int mid) {
+    __shared__ double2 Ai[kPanel * kPanel];
+    __shared__ double2 rows[kPanel * kPanel];  // [u][jj]
+    __shared__ int R1[kPanel];
+    const int c = blockIdx.x / kYGroups, grp = blockIdx.x % kYGroups;
+    const ChainPos q = chain_pos(subs, c, s, mid != 0);
+    if (!q.active) return;
+    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
+    if (k0 >= bs) return;
+    const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
+    const double2 *M = chain_M(w, c, q.cur);
+    const double2 *Ainv = w.Pw + (long long)c * kPanel * bsp;
+    const int *piv = w.piv + (long long)c * bsp;
+    double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kPanel * kPanel; e += kYThreads) Ai[e] = Ainv[e];
+    if (tid < kPanel) R1[tid] = tid < bw ? piv[k0 + tid] : 0;
+    const int nch = bsp / kPanel;  // 32-column chunks (bsp is a multiple of 64)
+    for (int ch = grp; ch < nch; ch += kYGroups) {
+        const int j0 = ch * kPanel;
+        __syncthreads();  // Ai / R1 loaded; the previous chunk's rows consumed
+        for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
+            const int u = e / kPanel, jj = e % kPanel, j = j0 + jj;
+            rows[e] = (u < bw && j < bs) ? M[(long long)j * bs + R1[u]] : make_double2(0, 0);
+        }
+        __syncthreads();
+        for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
+            const int t = e / kPanel, jj = e % kPanel, j = j0 + jj;
+            double2 y = make_double2(0, 0);
+            if (t < bw && j < bs) {
+                if (j >= k0 && j < k0 + bw) {
+                    y = Ai[t * kPanel + (j - k0)];
+                } else {
+                    for (int u = 0; u < bw; ++u) cfma(y, Ai[t * kPanel + u], rows[u * kPanel + jj]);
+                }
+            }
+            Yr[(long long)t * bsp + j] = y.x;
+            Yi[(long long)t * bsp + j] = y.y;
+        }
     }
 }
 
@@ -920,6 +951,7 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
             else
                 k_factor_panel<false><<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags,
                                                                          P.nsub);
+            if (use_ll) k_factor_formy<<<nc * kYGroups, kYThreads, 0, h->stream>>>(h->d_subs, w, ss, p, mid);
             k_factor_update<<<nc * tpd * tpd, kUThreads, 0, h->stream>>>(h->d_subs, w, ss, p, mid, tpd);
         }
         k_factor_store<T><<<nc * groups, kEThreads, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, w, ss, mid,
