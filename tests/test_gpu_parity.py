@@ -369,11 +369,13 @@ def test_3d_large_planes_perline():
     g.close()
 
 
-def test_3d_planes_above_512():
-    """Plane blocks of 576 unknowns: the factorisation's panel elimination
-    runs from the workspace instead of registers or LDS; FP64 and mixed
-    local solves vs oracle."""
-    w = di.small_3d(M=34, N=(2, 2, 2), n_pml=3, n_ov=2, nrhs=2, seed=5)
+@pytest.mark.parametrize("M", [34, 36])
+def test_3d_planes_above_512(M):
+    """Plane blocks of 529 (M = 34: the last 32-column panel has 17 columns)
+    and 576 unknowns (M = 36: whole panels): the factorisation's left-looking
+    panel elimination from the workspace and the multi-workgroup Y; FP64 and
+    mixed local solves vs oracle."""
+    w = di.small_3d(M=M, N=(2, 2, 2), n_pml=3, n_ov=2, nrhs=2, seed=5)
     o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
     gin = di.random_field((2, o.etot), seed=81)
     xo = o.local_solve(gin)
