@@ -779,17 +779,22 @@ __global__ __launch_bounds__(kUThreads) void k_factor_update(const SubDesc *__re
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int g = lane >> 4, qq = lane & 15;
     const int rw = i0 + 32 * (wv & 1), cw = j0 + 32 * (wv >> 1);
-    const int arow = 4 * (qq & 3) + (qq >> 2);  // matrix row of this lane's A operand
+    // The product is formed transposed, S^T += Y^T X^T (A operand Y^T(j, t) at
+    // lane j + 16 t, B operand X^T(t, i) at lane i + 16 t; the accumulator
+    // holds D(m, n) at lane n + 16 (m % 4), register m / 4): in block (bi, bj)
+    // lane qq + 16 g, register r holds S(i, j) with i = rw + 16 bi + qq and
+    // j = cw + 16 bj + g + 4 r, so every load and store instruction covers 16
+    // consecutive rows (256 bytes) of 4 columns.
     dbl4 re[2][2], im[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-            const int j = cw + 16 * bj + qq;
-            const bool keep = j < bs && !(j >= k0 && j < k0 + bw);
+            const int i = rw + 16 * bi + qq;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = rw + 16 * bi + 4 * g + r;
+                const int j = cw + 16 * bj + g + 4 * r;
+                const bool keep = j < bs && !(j >= k0 && j < k0 + bw);  // panel columns start from zero
                 const double2 v = (keep && i < bs) ? M[(long long)j * bs + i] : make_double2(0, 0);
                 re[bi][bj][r] = v.x;
                 im[bi][bj][r] = v.y;
@@ -801,45 +806,46 @@ __global__ __launch_bounds__(kUThreads) void k_factor_update(const SubDesc *__re
         double xr[2], xi[2], yr[2], yi[2];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            xr[b] = Xr[ko + rw + 16 * b + arow];
-            xi[b] = Xi[ko + rw + 16 * b + arow];
-            yr[b] = Yr[ko + cw + 16 * b + qq];
+            xr[b] = Xr[ko + rw + 16 * b + qq];  // B operand: X^T(t, i) at lane i + 16 t
+            xi[b] = Xi[ko + rw + 16 * b + qq];
+            yr[b] = Yr[ko + cw + 16 * b + qq];  // A operand: Y^T(j, t) at lane j + 16 t
             yi[b] = Yi[ko + cw + 16 * b + qq];
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) {
-                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[bi], yr[bj], re[bi][bj], 0, 0, 0);
-                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[bi], yi[bj], im[bi][bj], 0, 0, 0);
+                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xr[bi], re[bi][bj], 0, 0, 0);
+                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], xr[bi], im[bi][bj], 0, 0, 0);
             }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) {
-                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi[bi], yi[bj], re[bi][bj], 0, 0, 0);
-                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[bi], yr[bj], im[bi][bj], 0, 0, 0);
+                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], -xi[bi], re[bi][bj], 0, 0, 0);
+                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xi[bi], im[bi][bj], 0, 0, 0);
             }
     }
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < 2; ++bi) {
+        const int i = rw + 16 * bi + qq;
+        if (i >= bs) continue;
+        const int pr = ppos[i];
+        const bool pivot_row = pr >= k0 && pr < k0 + bw;  // pivot rows become Y
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            const int j = cw + 16 * bj + qq;
-            if (j >= bs) continue;
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = rw + 16 * bi + 4 * g + r;
-                if (i >= bs) continue;
-                const int pr = ppos[i];
+                const int j = cw + 16 * bj + g + 4 * r;
+                if (j >= bs) continue;
                 double2 v = make_double2(re[bi][bj][r], im[bi][bj][r]);
-                if (pr >= k0 && pr < k0 + bw) {
+                if (pivot_row) {
                     const long long yo = (long long)(pr - k0) * bsp + j;
                     v = make_double2(Yr[yo], Yi[yo]);
                 }
                 M[(long long)j * bs + i] = v;
             }
-        }
+    }
 }
 
 // Store the inverse of the chain's block, W_l(i, j) = N(piv[i], ppos[j]), and
