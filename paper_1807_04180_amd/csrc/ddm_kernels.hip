@@ -270,7 +270,7 @@ __device__ inline double beta_ba(const SubDesc &b, const int *dd, const double *
 // geometry of every neighbour term (which stencil points lie in b's box, their
 // cut-off weights and packed indices) is worked out once and applied to every
 // RHS of the tile.
-template <typename TIN, typename TOUT, bool PHI, int RQ>
+template <typename TIN, typename TOUT, bool PHI, int RQ, bool DIM3>
 __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__ subs, const Coef *__restrict__ coef,
                                                      const double *__restrict__ k2, const double *__restrict__ btab,
                                                      const TIN *__restrict__ l1, const TIN *__restrict__ l2,
@@ -308,8 +308,10 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
     Coef cf[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) cf[d] = coef[s.coff[d] + l[d]];
-    int k = 0;
-    for (int dz = -1; dz <= 1; ++dz)
+    // neighbour slots in (dz, dy, dx) order without (0, 0, 0); in 2D only the
+    // dz = 0 slots 9 .. 16 exist
+    int k = DIM3 ? 0 : 9;
+    for (int dz = DIM3 ? -1 : 0; dz <= (DIM3 ? 1 : 0); ++dz)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
                 if (dx == 0 && dy == 0 && dz == 0) continue;
@@ -513,12 +515,11 @@ hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TI
     if (ns > 0) {
         constexpr int RQ = 4;
         dim3 grid((unsigned)((ns + kBlock - 1) / kBlock), (nrhs + RQ - 1) / RQ);
-        if (h->transfer_form == DDM_TRANSFER_PHI)
-            k_transfer<TIN, TOUT, true, RQ><<<grid, kBlock, 0, h->stream>>>(
-                h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g, pack_args(P), rcorr, h->d_strip, ns, nrhs);
-        else
-            k_transfer<TIN, TOUT, false, RQ><<<grid, kBlock, 0, h->stream>>>(
-                h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g, pack_args(P), rcorr, h->d_strip, ns, nrhs);
+        const bool phi = h->transfer_form == DDM_TRANSFER_PHI, d3 = P.dim == 3;
+        auto kern = phi ? (d3 ? k_transfer<TIN, TOUT, true, RQ, true> : k_transfer<TIN, TOUT, true, RQ, false>)
+                        : (d3 ? k_transfer<TIN, TOUT, false, RQ, true> : k_transfer<TIN, TOUT, false, RQ, false>);
+        kern<<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g, pack_args(P), rcorr,
+                                             h->d_strip, ns, nrhs);
     }
     return hipGetLastError();
 }
