@@ -7,8 +7,9 @@
 * one subdomain: the first DDM step is the global direct solve (eq. talg_1
   with N = 1), against the oracle's banded LU;
 * the split substitution at its largest grid (8 x 8 subdomains: 256
-  workgroups, one per CU, all resident) against the oracle, and the
-  one-workgroup variant as the default beyond it (9 x 9);
+  workgroups, one per CU, all resident) and on its largest blocks (255 and
+  256 unknowns) against the oracle, and the one-workgroup variant as the
+  default beyond the grid (9 x 9);
 * the default substitution variant for block size and RHS count.
 """
 import numpy as np
@@ -103,6 +104,28 @@ def test_split_substitution_at_full_grid(mixed):
             uo, _ = o.ddm_run(w.f, 6)
             ug, _ = g.iterate(_t(w.f.reshape(w.nrhs, -1)), 6)
             assert relerr(_n(ug), uo, axis=1) < 1e-10
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_split_substitution_largest_blocks(mixed):
+    """Blocks of 255 and 256 unknowns: four 64-row tiles, the largest blocks
+    the split variant takes (128 partner rows per exchange); the odd complex64
+    block is stored with a padded column stride.  Split and one-workgroup
+    substitution against the oracle for 1 and 4 RHS; the split one is the
+    default."""
+    w = di.small_2d(M=474, N=(2, 2), n_pml=8, n_ov=4, nrhs=1)
+    o, g = _pair(w, 4, mixed=mixed)
+    try:
+        assert g.solve_variant() == "chain2"
+        tol = 5e-5 if mixed else 1e-10
+        for nrhs in (1, 4):
+            gin = di.random_field((nrhs, o.etot), seed=96 + nrhs)
+            xo = o.local_solve(gin)
+            for v in ("chain2", "chain"):
+                g.set_solve_variant(v)
+                assert relerr(_n(g.local_solve(_t(gin))), xo, axis=1) < tol, (v, nrhs)
     finally:
         g.close()
 
