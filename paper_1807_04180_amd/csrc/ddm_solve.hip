@@ -260,7 +260,7 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
     // 512-thread workgroups (256 VGPRs) keep 8 columns per batch, also for
     // 16-RHS tiles (2048^2 layered, 16 RHS: 17.5 against 19.1 ms per local
     // solve with 4 in complex128, 9.8 against 10.8 in complex64)
-    constexpr int kCBatch = NT < kCThreads ? 8 : (RT >= 16 ? 4 : ChainBatch<T2, ROWS>::value);
+    constexpr int kCBatch = NT < kCThreads ? 8 : (RT >= 16 ? 2 : ChainBatch<T2, ROWS>::value);
     const int a = twisted ? (int)(blockIdx.x >> 1) : (int)blockIdx.x;
     const int chain = twisted ? (int)(blockIdx.x & 1) : 0;
     const SubDesc &s = subs[a];
@@ -274,6 +274,11 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
     // sums in the same order; wave w takes pairs w, w + NW, ...
     constexpr int NW = NT / 64;          // waves
     constexpr int NP = NPAIR / NW;      // pairs per wave
+    // 16-RHS tiles on 1024-thread workgroups: the partial sums of the
+    // column groups are added into one [RT][bsp] buffer in column-group
+    // order (one barrier per group) instead of being kept side by side
+    constexpr bool SEQ = RT >= 16 && NT == kCThreads;
+    static_assert(!SEQ || NP == 1, "sequential reduction: one pair per wave");
     const int CG = NPAIR / R;
     const int npair = R * CG;
     // the wave index is uniform: keep it (and what derives from it) scalar
@@ -284,13 +289,13 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
     const bool rowok = gemv && row < bs;
     const int bsp = R * 64 * ROWS;
     T2 *vs = (T2 *)lds_raw;                 // [bsp][RT]  current v
-    T2 *red = vs + (size_t)bsp * RT;        // [CG][RT][bsp] partial sums
+    T2 *red = vs + (size_t)bsp * RT;        // [CG][RT][bsp] partial sums ([RT][bsp] when SEQ)
     // complex128: each wave's first kLdsCols columns of the next block are
     // copied to LDS by direct global->LDS loads while the block step
     // reduces, synchronises and forms the next v (the column stream would
     // otherwise idle there); the register stream starts after them
-    constexpr int PF = NT == kCThreads ? kLdsCols<T2, ROWS>::value : 0;
-    T2 *mypf = red + (size_t)CG * RT * bsp + (size_t)wv * PF * 64 * ROWS;  // [PF][64 lanes][ROWS]
+    constexpr int PF = NT == kCThreads && !SEQ ? kLdsCols<T2, ROWS>::value : 0;
+    T2 *mypf = red + (size_t)(SEQ ? 1 : CG) * RT * bsp + (size_t)wv * PF * 64 * ROWS;  // [PF][64 lanes][ROWS]
     // this chain's block sequence: forward blocks, the middle, backward blocks
     const int nf = chain == 0 ? mid : nb - 1 - mid;
     if (twisted == 0 && chain == 1) return;
@@ -368,20 +373,25 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
             const int tn = t + 1;
             const int lnv = tn < nsteps && tn != nf ? step_l(tn) : -1;
             T2 pre[kPre];
+            auto load_pre = [&]() {
 #pragma unroll
-            for (int u = 0; u < kPre; ++u) {
-                const int e = threadIdx.x + u * NT;
-                const int i = e / RT, q = e % RT;
-                const bool ok = e < bsp * RT && i < bs && q < nr;
-                const long long base = (long long)(ok ? r0 + q : 0) * etot + off;
-                if (kind == 2)  // the first backward block is the atomically stored one
-                    pre[u] = ok ? (t == nf + 1 ? xload(x + base + (long long)l * bs + i) : x[base + (long long)l * bs + i])
-                                : czero<T2>();
-                else if (kind == 0 && lnv >= 0) pre[u] = ok ? g[base + (long long)lnv * bs + i] : czero<T2>();
-                else pre[u] = czero<T2>();
-            }
+                for (int u = 0; u < kPre; ++u) {
+                    const int e = threadIdx.x + u * NT;
+                    const int i = e / RT, q = e % RT;
+                    const bool ok = e < bsp * RT && i < bs && q < nr;
+                    const long long base = (long long)(ok ? r0 + q : 0) * etot + off;
+                    if (kind == 2)  // the first backward block is the atomically stored one
+                        pre[u] = ok ? (t == nf + 1 ? xload(x + base + (long long)l * bs + i)
+                                                   : x[base + (long long)l * bs + i])
+                                    : czero<T2>();
+                    else if (kind == 0 && lnv >= 0) pre[u] = ok ? g[base + (long long)lnv * bs + i] : czero<T2>();
+                    else pre[u] = czero<T2>();
+                }
+            };
+            load_pre();
             // ---- GEMV: acc = W_l v, per work pair of this wave ----
             const int lnext = t + 1 < nsteps ? step_l(t + 1) : -1;
+            T2 acc[ROWS][RT];
 #pragma unroll
             for (int pi = 0; pi < NP; ++pi) {
                 const int pp = wv + pi * NW;
@@ -397,7 +407,6 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
                 const int qrow = nextpair ? ((pq % R) * 64 + lane) * ROWS : row;
                 const int qcg = nextpair ? pq / R : cg;
                 const bool qrowok = nextpair ? qrow < bs : rowok;
-                T2 acc[ROWS][RT];
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r)
 #pragma unroll
@@ -445,10 +454,36 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
 #pragma unroll
                     for (int u = 0; u < kCBatch; ++u) wb[u] = wn[u];
                 }
+                if constexpr (!SEQ) {
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r)
+                    for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-                    for (int q = 0; q < RT; ++q) red[((size_t)pcg * RT + q) * bsp + prow + r] = acc[r][q];
+                        for (int q = 0; q < RT; ++q) red[((size_t)pcg * RT + q) * bsp + prow + r] = acc[r][q];
+                }
+            }
+            if constexpr (SEQ) {
+                // column group c adds its rows' partial sums in round c
+                const bool has = wv < npair;
+                const int scg = wv / R, srow = ((wv % R) * 64 + lane) * ROWS;
+                for (int c = 0; c < CG; ++c) {
+                    if (has && scg == c) {
+#pragma unroll
+                        for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                            for (int q = 0; q < RT; ++q) {
+                                T2 &d = red[(size_t)q * bsp + srow + r];
+                                if (c == 0) {
+                                    d = acc[r][q];
+                                } else {
+                                    T2 o = d;
+                                    o.x += acc[r][q].x;
+                                    o.y += acc[r][q].y;
+                                    d = o;
+                                }
+                            }
+                    }
+                    __syncthreads();
+                }
             }
             if (lnext >= 0)
                 lds_prefetch<T2, PF, ROWS>(Wbase + (long long)lnext * bs2, mypf, cg, CG, bs, ld, rowc, gemv);
@@ -461,7 +496,7 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
                 const int i = e / RT, q = e % RT;
                 if (i >= bs) continue;
                 T2 sum = red[(size_t)q * bsp + i];
-                for (int c = 1; c < CG; ++c) {
+                for (int c = 1; c < (SEQ ? 1 : CG); ++c) {
                     T2 o = red[((size_t)c * RT + q) * bsp + i];
                     sum.x += o.x;
                     sum.y += o.y;
@@ -780,8 +815,9 @@ static hipError_t run_perline(ddm_handle *h, const T *g, T *x, int nrhs) {
 template <typename T2, int RT, int ROWS, int NT, int NPAIR = kCWaves>
 static size_t chain_lds(int bs_max) {
     const int R = (bs_max + 64 * ROWS - 1) / (64 * ROWS);
-    const int CG = NPAIR / R;
-    const int PF = NT == kCThreads ? kLdsCols<T2, ROWS>::value : 0;
+    constexpr bool SEQ = RT >= 16 && NT == kCThreads;
+    const int CG = SEQ ? 1 : NPAIR / R;  // partial-sum buffers
+    const int PF = NT == kCThreads && !SEQ ? kLdsCols<T2, ROWS>::value : 0;
     return (size_t)R * 64 * ROWS * RT * (1 + CG) * sizeof(T2) + (size_t)(NT / 64) * PF * 64 * ROWS * sizeof(T2);
 }
 
@@ -830,15 +866,16 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
         if (nrhs <= 1) return run_chain<T, 1, 1>(h, g, x, nrhs);
         if (nrhs <= 2) return run_chain<T, 2, 1>(h, g, x, nrhs);
         if (nrhs <= 4) return run_chain<T, 4, 1>(h, g, x, nrhs);
-        // more RHS: 512-thread workgroups (256 VGPRs per lane) hold 8 or 16
-        // RHS per tile; a twisted launch needs every workgroup resident (one
-        // per CU here).  Batches of 16 or more take 16-RHS tiles, which stream
-        // each inverse once per 16 RHS (2048^2 layered, 16 RHS: 18.5 against
-        // 22.5 ms per local solve in 8-RHS tiles); their partial sums fit in
-        // LDS only on the 8-pair partition, so such batches round differently
-        // from batches of up to 15, which keep the 16-pair partition of every
-        // smaller tile (a RHS alone or in any such batch: the same bits)
+        // more RHS: 8-RHS tiles on 512-thread workgroups (256 VGPRs per lane);
+        // a twisted launch needs every workgroup resident (one per CU here).
+        // Batches of 16 or more take 16-RHS tiles, which stream each inverse
+        // once per 16 RHS: on 1024-thread workgroups with the 16-pair
+        // partition and the column groups' partial sums added in order (the
+        // same bits as every smaller tile), else on 512-thread workgroups with
+        // 8 pairs (fewer waves; rounding differs from smaller batches)
         const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= h->plan.ncu;
+        if (coop_ok && nrhs >= 16 && chain_lds<T, 16, 1, kCThreads>(h->plan.bs_max) <= kLdsMax)
+            return run_chain<T, 16, 1>(h, g, x, nrhs);
         if (coop_ok && nrhs >= 16 && chain_lds<T, 16, 1, 512, 8>(h->plan.bs_max) <= kLdsMax)
             return run_chain<T, 16, 1, 512, 8>(h, g, x, nrhs);
         if (coop_ok && chain_lds<T, 8, 1, 512>(h->plan.bs_max) <= kLdsMax) return run_chain<T, 8, 1, 512>(h, g, x, nrhs);

@@ -225,10 +225,11 @@ def test_chain_mixed_matches_oracle():
 
 @pytest.mark.parametrize("case", ["2d-3x3-layered", "2d-2x2-146"])
 def test_chain_16_rhs_tiles_fp64(case):
-    """Complex128 batches of 16 or more RHS take 16-RHS tiles (8-pair
-    partition), on blocks of two (75-98 nodes) and three (146 nodes) 64-row
-    tiles: oracle parity for 16 RHS, and every RHS gives the same bits in a
-    batch of 20 (reordered, the last 4 in a ragged second tile)."""
+    """Complex128 batches of 16 or more RHS take 16-RHS tiles (1024-thread
+    workgroups, the column groups' partial sums added in order), on blocks of
+    two (75-98 nodes) and three (146 nodes) 64-row tiles: oracle parity for
+    16 RHS; every RHS gives the same bits in a batch of 20 (reordered, the
+    last 4 in a ragged second tile) and alone."""
     w = CASES[case]() if case in CASES else di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4, nrhs=1)
     o, g = make_pair(w, nrhs_max=20)
     try:
@@ -239,6 +240,7 @@ def test_chain_16_rhs_tiles_fp64(case):
         x20 = _n(g.local_solve(_t(np.concatenate([gin[::-1], gin[:4]]))))
         assert np.array_equal(x20[:16], x16[::-1])
         assert np.array_equal(x20[16:], x16[:4])
+        assert np.array_equal(_n(g.local_solve(_t(gin[5:6])))[0], x16[5])
     finally:
         g.close()
 
