@@ -198,6 +198,10 @@ constexpr int kXcds = 8;
 // blocks of the row-per-block stencil launches: grid rows padded to a
 // multiple of the XCD count
 inline int stencil_blocks(const Plan &P) { return (P.G[1] * P.G[2] + kXcds - 1) / kXcds * kXcds; }
+// The assembly kernel gives every global node a thread: a grid row is cut
+// into pieces of kRowPiece nodes, one workgroup each.
+constexpr int kRowPiece = 256;
+inline int row_pieces(const Plan &P) { return (P.G[0] + kRowPiece - 1) / kRowPiece; }
 size_t chain2_xbuf_bytes(const Plan &P);
 bool chain2_fits(const Plan &P);
 

@@ -14,6 +14,7 @@
 namespace ddm {
 
 constexpr int kBlock = 256;
+static_assert(kBlock == kRowPiece, "one thread per node of a row piece");
 
 // ---------------------------------------------------------------------------
 // block-wide sum of doubles (fixed tree)
@@ -420,7 +421,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(const SubDesc *__restrict__
                                                      int N0, int N1, const TIN *__restrict__ U,
                                                      double2 *__restrict__ u, PackArgs A, int accumulate,
                                                      const int *__restrict__ active, int nrhs) {
-    // one thread per global node and tile of up to RQ right-hand sides: the
+    // one thread per global node (pieces of kRowPiece nodes of a grid row per
+    // workgroup) and tile of up to RQ right-hand sides: the
     // node's owners (at most 2 per axis), their cut-off weights and packed
     // offsets are found once and applied to every RHS of the tile
     const int r0 = blockIdx.y * RQ;
@@ -433,42 +435,43 @@ __global__ __launch_bounds__(kBlock) void k_assemble(const SubDesc *__restrict__
         any = any || act[q];
     }
     if (!any) return;
-    const int rowi = blockIdx.x;  // gy + G1 * gz
+    const int nch = (A.G0 + kRowPiece - 1) / kRowPiece;
+    const int rowi = (int)blockIdx.x / nch;  // gy + G1 * gz
+    const int gx = ((int)blockIdx.x % nch) * kRowPiece + (int)threadIdx.x;
+    if (gx >= A.G0) return;
     const int gy = rowi % A.G1, gz = rowi / A.G1;
     const AxisOwn ey = aown[o1 + gy], ez = aown[o2 + gz];
-    for (int gx = threadIdx.x; gx < A.G0; gx += kBlock) {
-        const AxisOwn ex = aown[o0 + gx];
-        // owner k = c0 + 2 c1 + 4 c2 (weight 0 past an axis' owner count);
-        // fixed bounds keep the tables in registers
-        long long off[8];
-        double wt[8];
+    const AxisOwn ex = aown[o0 + gx];
+    // owner k = c0 + 2 c1 + 4 c2 (weight 0 past an axis' owner count);
+    // fixed bounds keep the tables in registers
+    long long off[8];
+    double wt[8];
 #pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2)
+    for (int c2 = 0; c2 < 2; ++c2)
 #pragma unroll
-            for (int c1 = 0; c1 < 2; ++c1) {
-                const bool yz = c2 < ez.cnt && c1 < ey.cnt;
-                const int ayz = yz ? N0 * (ey.i[c1] + N1 * ez.i[c2]) : 0;
-                const long long lyz = yz ? (long long)ey.lc[c1] + (long long)ey.n[c1] * ez.lc[c2] : 0;
+        for (int c1 = 0; c1 < 2; ++c1) {
+            const bool yz = c2 < ez.cnt && c1 < ey.cnt;
+            const int ayz = yz ? N0 * (ey.i[c1] + N1 * ez.i[c2]) : 0;
+            const long long lyz = yz ? (long long)ey.lc[c1] + (long long)ey.n[c1] * ez.lc[c2] : 0;
 #pragma unroll
-                for (int c0 = 0; c0 < 2; ++c0) {
-                    const int k = c0 + 2 * c1 + 4 * c2;
-                    const bool ok = yz && c0 < ex.cnt;
-                    wt[k] = ok ? ex.beta[c0] * ey.beta[c1] * ez.beta[c2] : 0.0;
-                    off[k] = ok ? subs[ex.i[c0] + ayz].off + (long long)ex.lc[c0] + (long long)ex.n[c0] * lyz : 0;
-                }
+            for (int c0 = 0; c0 < 2; ++c0) {
+                const int k = c0 + 2 * c1 + 4 * c2;
+                const bool ok = yz && c0 < ex.cnt;
+                wt[k] = ok ? ex.beta[c0] * ey.beta[c1] * ez.beta[c2] : 0.0;
+                off[k] = ok ? subs[ex.i[c0] + ayz].off + (long long)ex.lc[c0] + (long long)ex.n[c0] * lyz : 0;
             }
-        const long long gi = (long long)rowi * A.G0 + gx;
-#pragma unroll
-        for (int q = 0; q < RQ; ++q) {
-            if (!act[q]) continue;
-            const TIN *Ur = U + (long long)(r0 + q) * A.etot;
-            double2 acc = make_double2(0, 0);
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (wt[k] != 0.0) acc = cadd(acc, cscale(to_d2(Ur[off[k]]), wt[k]));
-            double2 *uq = u + (long long)(r0 + q) * A.nglob + gi;
-            *uq = accumulate ? cadd(*uq, acc) : acc;
         }
+    const long long gi = (long long)rowi * A.G0 + gx;
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        if (!act[q]) continue;
+        const TIN *Ur = U + (long long)(r0 + q) * A.etot;
+        double2 acc = make_double2(0, 0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (wt[k] != 0.0) acc = cadd(acc, cscale(to_d2(Ur[off[k]]), wt[k]));
+        double2 *uq = u + (long long)(r0 + q) * A.nglob + gi;
+        *uq = accumulate ? cadd(*uq, acc) : acc;
     }
 }
 
@@ -527,7 +530,7 @@ hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TI
 template <typename TIN>
 hipError_t launch_assemble(ddm_handle *h, const TIN *U, double2 *u, int nrhs, bool accumulate, const int *d_active) {
     const Plan &P = h->plan;
-    dim3 grid((unsigned)(P.G[1] * P.G[2]), (nrhs + kAsmRQ - 1) / kAsmRQ);
+    dim3 grid((unsigned)(P.G[1] * P.G[2] * row_pieces(P)), (nrhs + kAsmRQ - 1) / kAsmRQ);
     // local solutions read once per global node, u read (if accumulating) and written
     ProfScope ps(h, DDM_K_ASSEMBLE, (double)P.nglob * nrhs * (sizeof(TIN) + (accumulate ? 32.0 : 16.0)));
     k_assemble<TIN, kAsmRQ><<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_aown, P.aoff[0], P.aoff[1], P.aoff[2],
