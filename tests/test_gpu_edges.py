@@ -10,7 +10,10 @@
   workgroups, one per CU, all resident) and on its largest blocks (255 and
   256 unknowns) against the oracle, and the one-workgroup variant as the
   default beyond the grid (9 x 9);
-* the default substitution variant for block size and RHS count.
+* the default substitution variant for block size and RHS count;
+* grid rows wider than 256 nodes with a ragged last piece (the assembly
+  gives every node a thread over 256-node row pieces): assembly and
+  residual against the oracle.
 """
 import numpy as np
 import pytest
@@ -157,3 +160,27 @@ def test_default_variant_choice():
             assert relerr(_n(g.local_solve(_t(gin))), o.local_solve(gin), axis=1) < 1e-10
         finally:
             g.close()
+
+
+@pytest.mark.parametrize("M,N", [(300, (2, 2)), (520, (4, 2))])
+def test_assembly_and_residual_on_rows_wider_than_256(M, N):
+    """Rows of 311 and 531 nodes: 2 and 3 row pieces, the last one ragged
+    (55 and 19 nodes). Assembly (1e-14) and residual with its norms (1e-13)
+    against the oracle, as on the narrower grids."""
+    w = di.small_2d(M=M, N=N, n_pml=6, n_ov=4, nrhs=2, seed=7)
+    o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
+    G0 = int(round(o.nglob ** 0.5))
+    assert G0 * G0 == o.nglob and G0 > 256 and G0 % 256 != 0
+    g = ddm.HelmholtzDDM(ddm.Problem.from_workload(w), _t(w.k2.reshape(-1)), 3)
+    try:
+        U = di.random_field((3, o.etot), seed=31)
+        assert relerr(_n(g.assemble(_t(U))), o.assemble(U)) < 1e-14
+        u = di.random_field((3, o.nglob), seed=32)
+        f = di.random_field((3, o.nglob), seed=33)
+        r, rn, fn = g.residual(_t(f), _t(u))
+        ro = f - o.apply(u)
+        assert relerr(_n(r), ro) < 1e-13
+        np.testing.assert_allclose(np.sqrt(rn), np.linalg.norm(ro, axis=1), rtol=1e-13)
+        np.testing.assert_allclose(np.sqrt(fn), np.linalg.norm(f, axis=1), rtol=1e-13)
+    finally:
+        g.close()
