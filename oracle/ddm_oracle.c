@@ -407,6 +407,16 @@ void or_apply_local(const or_ctx *c, int a, const cplx *u, cplx *out) {
 }
 
 /* Dense 1D coefficient dump used by tests: sigma at node and half nodes. */
+/* PML strength for a target reflection R (the profile sigma~ of Sec. 2.1 is
+ * left open by the paper; reading: a wave of wave number k_ref crossing the
+ * layer of width delta twice is damped by R).  With sigma0 (t/delta)^2 the
+ * attenuation exponent is 2 k_ref times the layer integral of sigma,
+ * 2 k_ref sigma0 delta / 3. */
+double or_sigma0_for_reflection(double R, double k_ref, double delta) {
+    double layer_integral_per_sigma0 = delta / 3.0;
+    return log(1.0 / R) / (2.0 * k_ref * layer_integral_per_sigma0);
+}
+
 double or_sigma_local(const or_ctx *c, int a, int ax, double x) { return sigma_local(c, a, ax, x); }
 double or_sigma_global(const or_ctx *c, int ax, double x) { return sigma_global(c, ax, x); }
 double or_beta0(double t) { return beta0(t); }

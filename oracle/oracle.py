@@ -43,6 +43,8 @@ def _lib():
         lib.or_sigma_local.argtypes = [P, i32, i32, f64]
         lib.or_sigma_global.restype = f64
         lib.or_sigma_global.argtypes = [P, i32, f64]
+        lib.or_sigma0_for_reflection.restype = f64
+        lib.or_sigma0_for_reflection.argtypes = [f64, f64, f64]
         lib.or_beta0.restype = f64
         lib.or_beta0.argtypes = [f64]
         lib.or_global_solve.restype = i32
@@ -119,6 +121,13 @@ class Oracle:
 
     def sigma_global(self, ax, x):
         return _lib().or_sigma_global(self._c, ax, float(x))
+
+    @staticmethod
+    def sigma0_for_reflection(R, k2, n_pml, h):
+        """PML strength for target reflection R with k_ref = sqrt(min k^2)
+        (the smallest wave number of the medium) and layer width n_pml h."""
+        k_ref = float(np.sqrt(np.min(np.asarray(k2, dtype=np.float64))))
+        return _lib().or_sigma0_for_reflection(float(R), k_ref, float(n_pml * h))
 
     @staticmethod
     def beta0(t):

@@ -183,3 +183,57 @@ def test_exact_3d_gradient_matches_differences():
             ul = bench.gaussian_free_space_3d([lo[0]], [lo[1]], [lo[2]], k, c0)[0][0, 0, 0]
             uh = bench.gaussian_free_space_3d([hi[0]], [hi[1]], [hi[2]], k, c0)[0][0, 0, 0]
             assert abs((uh - ul) / (2 * d) - g[1 + ax][0, 0, 0]) < 1e-6 * abs(g[1 + ax][0, 0, 0])
+
+
+def _probe_operator_3d(o, G):
+    """The oracle's 7-point operator as a sparse matrix, read column by column
+    from its apply: unit vectors on the nodes of one of 27 colour classes
+    (nodes 3 apart on every axis) have disjoint stencils."""
+    import scipy.sparse as sp
+    idx = np.arange(G ** 3).reshape(G, G, G)
+    rows, cols, vals = [], [], []
+    for c in range(27):
+        mask = np.zeros((G, G, G), bool)
+        mask[c // 9::3, (c // 3) % 3::3, c % 3::3] = True
+        y = o.apply(mask.reshape(1, -1).astype(np.complex128)).reshape(G, G, G)
+        zz, yy, xx = np.nonzero(mask)
+        for dz, dy, dx in ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            z2, y2, x2 = zz + dz, yy + dy, xx + dx
+            ok = (z2 >= 0) & (z2 < G) & (y2 >= 0) & (y2 < G) & (x2 >= 0) & (x2 < G)
+            rows.append(idx[z2[ok], y2[ok], x2[ok]])
+            cols.append(idx[zz[ok], yy[ok], xx[ok]])
+            vals.append(y[z2[ok], y2[ok], x2[ok]])
+    return sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(G ** 3, G ** 3))
+
+
+def _small_copy_errors_3d(M, n_pml):
+    # Table 2's setting shrunk: k/2pi = 2 on a box of L = 1/2 (one wavelength)
+    # with a PML of n_pml cells, the paper's 3D Gaussian (Sec. 4.1.2) off
+    # centre, sigma0 for a reflection of 1e-8
+    import scipy.sparse.linalg as spl
+    k = 2 * math.pi * 2
+    L = 0.5
+    h = L / M
+    c0 = (L / 2 + 0.03, L / 2 - 0.02, L / 2 + 0.01)
+    k2 = di.constant_k2(3, (M, M, M), n_pml, k)
+    s0 = Oracle.sigma0_for_reflection(1e-8, k2, n_pml, h)
+    f = di.paper_gaussian_source(3, (M, M, M), n_pml, h, L, c0, k).reshape(-1)
+    o = Oracle(3, (M, M, M), h, n_pml, s0, (1, 1, 1), 2, k2)
+    G = M + 2 * n_pml - 1
+    u = spl.spsolve(_probe_operator_3d(o, G), f)
+    # the probed matrix is the oracle's operator: its solution zeroes the
+    # oracle's own residual
+    assert o.relres(f.reshape(1, -1), u.reshape(1, -1))[0] < 1e-12
+    return bench.l2_h1_errors(u.reshape(G, G, G), di.node_coords(M, n_pml, h), h, L, k, c0)
+
+
+def test_discrete_3d_solution_converges_at_second_order():
+    """The 3D twin of the 2D rate pin: the oracle's seven-point PML solution
+    of the paper's 3D Gaussian source converges to the exact free-space
+    solution at the second order printed in Table 2 (meshes of 12 and 18
+    cells with a PML of fixed width: error ratio 1.5^2 = 2.25, order 2)."""
+    (l2a, h1a), (l2b, h1b) = _small_copy_errors_3d(12, 4), _small_copy_errors_3d(18, 6)
+    for a, b in ((l2a, l2b), (h1a, h1b)):
+        order = math.log(a / b) / math.log(1.5)
+        assert 1.8 < order < 2.3, (a, b, order)
+    assert l2b < 3e-3

@@ -170,3 +170,21 @@ def test_point_source_matches_hankel_second_order():
 
 def test_flipped_pml_sign_fails_hankel():
     assert _hankel_error(48, sign=-1.0) > 0.5
+
+
+@pytest.mark.parametrize("R,layered", [(1e-6, False), (1e-8, True), (1e-3, False)])
+def test_sigma0_from_reflection_damps_round_trip_by_R(R, layered):
+    """PML strength for a target reflection R (the round-trip reading of the
+    sigma~ the paper leaves open, Sec. 2.1): integrate the oracle's own global
+    profile across the layer (scipy quadrature of sigma_global over the PML
+    cells) and check that a wave of the smallest wave number of the medium,
+    crossing the layer twice, is damped by exactly R."""
+    from scipy.integrate import quad
+    w = di.small_2d(M=32, N=(2, 2), n_pml=5, n_ov=3, layered=layered, seed=3)
+    s0 = Oracle.sigma0_for_reflection(R, w.k2, w.n_pml, w.h)
+    o = Oracle(w.dim, w.M, w.h, w.n_pml, s0, w.N, w.n_ov, w.k2)
+    k_ref = np.sqrt(w.k2.min())
+    for lo, hi in ((w.M[0], w.M[0] + w.n_pml), (-w.n_pml, 0)):
+        cells, _ = quad(lambda x: o.sigma_global(0, x), lo, hi, epsabs=0, epsrel=1e-13)
+        damping = np.exp(-2.0 * k_ref * w.h * cells)
+        assert damping == pytest.approx(R, rel=1e-10)
