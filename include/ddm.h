@@ -64,7 +64,8 @@ typedef struct {
     int M[3];                 /* interior cells per axis (unused axes ignored)   */
     double h;                 /* mesh size (equal on all axes)                   */
     int n_pml;                /* PML cells, >= 2                                  */
-    double sigma0;            /* PML strength (alpha = 1 + i sigma), >= 0        */
+    double sigma0;            /* PML strength (alpha = 1 + i sigma), >= 0; must
+                                 be 0 when reflection > 0                       */
     int N[3];                 /* subdomains per axis; M[d] % N[d] == 0            */
     int n_ov;                 /* overlap cells (the d~ of Sec. 2.2), >= 2;
                                  core width M/N >= n_ov + 2 when N > 1          */
@@ -74,6 +75,18 @@ typedef struct {
                                  the outer Krylov / refinement in FP64.          */
     size_t hbm_budget_bytes;  /* 0 = no limit; else ddm_setup refuses a plan
                                  larger than this (DDM_ENOMEM)                   */
+    double reflection;        /* 0: use sigma0 as given.  In (0, 1): the PML
+                                 strength is derived from this target reflection
+                                 of the quadratic profile (the sigma~ of Sec.
+                                 2.1 is left open by the paper; this is the
+                                 round-trip reading): a wave of the smallest
+                                 wave number k_ref = sqrt(min k^2) crossing the
+                                 layer twice is damped by exp(-2 k_ref sigma0
+                                 n_pml h / 3) = reflection, i.e.
+                                 sigma0 = 3 ln(1/reflection) / (2 k_ref n_pml h).
+                                 ddm_pml_strength returns the value used.       */
+    int k2_on_host;           /* ddm_setup's k2 is a HOST pointer when != 0, a
+                                 DEVICE pointer when 0                           */
 } ddm_problem;
 
 typedef struct {
@@ -90,6 +103,15 @@ typedef struct {
                             FP64 residual after this many steps without a 2x
                             gain (0 = never; the residual-corrected sources
                             make restarts unnecessary in practice)             */
+    int check_every;     /* DDM_STATIONARY: test the stopping criterion (and
+                            synchronise with the host) after every
+                            check_every-th step only (0 or 1 = every step).
+                            A right-hand side that meets tol stops at the
+                            first checked step at or after that point; the
+                            iteration count reported is that step.  Between
+                            checks the steps are only enqueued: the host
+                            neither waits for nor reads the residual norms.
+                            The last step (maxiter) is always checked.        */
 } ddm_solve_opts;
 
 typedef struct {
@@ -102,17 +124,28 @@ typedef struct {
 
 typedef struct ddm_handle ddm_handle;
 
-/* Device bytes that ddm_setup + ddm_factor will allocate for at most
- * nrhs_max right-hand sides per call (factors + workspaces), for admission
- * control.  Returns DDM_EINVAL for an invalid problem. */
+/* Peak device bytes of a handle for at most nrhs_max right-hand sides per
+ * call, for admission control: everything ddm_setup allocates (tables,
+ * factors, step workspaces, the handle-owned copies of f and u used by the
+ * step graphs and the slots) plus the factorisation workspace that
+ * ddm_factor holds while it runs.  DDM_FGMRES solves allocate their Krylov
+ * basis (2 restart + 1 global vectors per RHS) on first use, on top of this,
+ * and refuse it with DDM_ENOMEM when it would exceed hbm_budget_bytes.
+ * Returns DDM_EINVAL for an invalid problem. */
 int ddm_memory_required(const ddm_problem *p, int nrhs_max, size_t *bytes);
 
 /* Build the discretisation and partition tables (Sec. 3.1, Sec. 2.2) and
  * allocate device memory for up to nrhs_max right-hand sides per call.
- * k2: DEVICE pointer to k(x)^2 (double, nglob entries) -- copied, so the
- * caller may free it afterwards.  stream: hipStream_t (NULL = default
- * stream).  On success *out receives a handle. */
+ * k2: k(x)^2 on the global unknown grid (double, nglob entries, row-major
+ * [z][y][x]), a DEVICE pointer, or a HOST pointer when p->k2_on_host != 0;
+ * copied, so the caller may free it afterwards.  DDM_EINVAL for non-finite
+ * entries, and for reflection > 0 with sigma0 != 0, reflection >= 1 or a
+ * non-positive minimum of k2.  stream: hipStream_t (NULL = default stream).
+ * On success *out receives a handle. */
 int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream, ddm_handle **out);
+
+/* PML strength sigma0 the handle uses (given, or derived from reflection). */
+int ddm_pml_strength(const ddm_handle *h, double *sigma0);
 
 /* Factor every subdomain operator L_{i,j} of Algorithm 3.1 once (the direct
  * local solver of Sec. 4) as a block-tridiagonal LU with grid-line (2D) /
@@ -142,6 +175,11 @@ const char *ddm_last_error(const ddm_handle *h);
 void ddm_destroy(ddm_handle *h);
 
 /* ---- geometry and single-row entry points (Sec. 2.2 / Alg. 3.1 steps) ---- */
+
+/* Device memory of the handle (host pointers, may be NULL): *held = bytes it
+ * holds now, *peak = the most it held at once since ddm_setup (the
+ * factorisation workspace included). */
+int ddm_device_bytes(const ddm_handle *h, size_t *held, size_t *peak);
 
 /* Sizes: out[0] = nglob, out[1] = packed size per RHS (sum of |E_a|),
  * out[2] = number of subdomains, out[3] = factor bytes. */

@@ -17,12 +17,14 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "EHIP"
 class DdmProblem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("M", ctypes.c_int * 3), ("h", ctypes.c_double),
                 ("n_pml", ctypes.c_int), ("sigma0", ctypes.c_double), ("N", ctypes.c_int * 3),
-                ("n_ov", ctypes.c_int), ("precision", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t)]
+                ("n_ov", ctypes.c_int), ("precision", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("reflection", ctypes.c_double), ("k2_on_host", ctypes.c_int)]
 
 
 class DdmSolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
-                ("restart", ctypes.c_int), ("K", ctypes.c_int), ("refine_every", ctypes.c_int)]
+                ("restart", ctypes.c_int), ("K", ctypes.c_int), ("refine_every", ctypes.c_int),
+                ("check_every", ctypes.c_int)]
 
 
 class DdmRhsInfo(ctypes.Structure):
@@ -69,6 +71,8 @@ def lib():
     L.ddm_destroy.argtypes = [H]
     L.ddm_destroy.restype = None
     L.ddm_sizes.argtypes = [H, LP]
+    L.ddm_pml_strength.argtypes = [H, DP]
+    L.ddm_device_bytes.argtypes = [H, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     L.ddm_geometry.argtypes = [H, I, LP]
     L.ddm_apply.argtypes = [H, P, P, I]
     L.ddm_residual.argtypes = [H, P, P, P, I, DP, DP]
@@ -94,7 +98,7 @@ def lib():
     for name in ("ddm_slot_admit", "ddm_slots_step", "ddm_slots_poll", "ddm_slot_retire", "ddm_set_graphs", "ddm_set_factor_layout", "ddm_set_solve_variant", "ddm_get_solve_variant", "ddm_autotune", "ddm_set_spin_limit", "ddm_set_transfer_form",
                  "ddm_profile_enable", "ddm_profile_read", "ddm_memory_required", "ddm_setup", "ddm_factor", "ddm_iterate", "ddm_solve", "ddm_sizes",
                  "ddm_geometry", "ddm_apply", "ddm_residual", "ddm_restrict_core", "ddm_local_solve",
-                 "ddm_transfer", "ddm_assemble"):
+                 "ddm_transfer", "ddm_assemble", "ddm_pml_strength", "ddm_device_bytes"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

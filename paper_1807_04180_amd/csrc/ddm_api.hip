@@ -74,12 +74,29 @@ int hip_fail(ddm_handle *h, const HipFail &f) {
     return fail(h, f.e == hipErrorOutOfMemory ? DDM_ENOMEM : DDM_EHIP, buf);
 }
 
+// device bytes of one allocation of count elements (zero-sized tables still
+// take a 16-byte allocation)
+template <typename T> size_t abytes(size_t count) {
+    size_t bytes = count * sizeof(T);
+    return bytes == 0 ? 16 : bytes;
+}
+
+// every device allocation of a handle goes through here, so h->bytes is the
+// device memory it holds (and peak_bytes the most it held at once)
 template <typename T>
 void dalloc(ddm_handle *h, T **p, size_t count) {
-    size_t bytes = count * sizeof(T);
-    if (bytes == 0) bytes = 16;
+    const size_t bytes = abytes<T>(count);
     HIPCHK(hipMalloc((void **)p, bytes));
     h->bytes += bytes;
+    h->peak_bytes = std::max(h->peak_bytes, h->bytes);
+}
+
+template <typename T>
+void dfree(ddm_handle *h, T **p, size_t count) {
+    if (!*p) return;
+    HIPCHK(hipFree(*p));
+    *p = nullptr;
+    h->bytes -= abytes<T>(count);
 }
 
 size_t elem_size(bool mixed) { return mixed ? sizeof(float2) : sizeof(double2); }
@@ -95,23 +112,45 @@ size_t part_doubles(const Plan &P, int nrhs, int m) {
     return std::max(a, std::max(b, c));
 }
 
-// device bytes of a plan for nrhs right-hand sides (factors, tables and step
-// workspaces; the FGMRES basis for restart m if m > 0)
-size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
-    size_t es = elem_size(mixed);
+// Device bytes that ddm_setup allocates for nrhs right-hand sides: the same
+// allocations, in the same order and with the same rounding, as ddm_setup
+// makes through dalloc (checked there).
+size_t setup_bytes(const Plan &P, bool mixed, int nrhs) {
+    const size_t es = elem_size(mixed);
     size_t b = 0;
-    b += P.subs.size() * sizeof(SubDesc) + (P.coef.size() + P.gcoef.size()) * sizeof(Coef);
-    b += P.aown.size() * sizeof(AxisOwn) + P.btab.size() * sizeof(double) + P.items.size() * sizeof(SolveItem);
-    b += P.strip.size() * sizeof(int2);
-    b += (size_t)P.nglob * sizeof(double);                         // k2
-    b += (size_t)P.fel * es;                                       // factors
-    b += factor_ws_bytes(P);                                       // factor workspace (freed after factor)
-    b += (size_t)(1 + P.ring) * nrhs * P.etot * es;                // g + ring
-    b += (size_t)nrhs * P.nglob * sizeof(double2);                 // residual / operator output
-    if (mixed) b += (size_t)nrhs * P.etot * sizeof(double2);       // widening scratch
-    b += part_doubles(P, nrhs, m > 0 ? m : 30) * sizeof(double);
-    if (chain2_fits(P)) b += chain2_xbuf_bytes(P) + (size_t)8 * P.nsub * sizeof(int);
-    if (m > 0) b += (size_t)(2 * m + 1) * nrhs * P.nglob * sizeof(double2) + (size_t)nrhs * P.nglob * sizeof(double2);
+    b += abytes<SubDesc>(P.subs.size()) + abytes<Coef>(P.coef.size()) + abytes<Coef>(P.gcoef.size());
+    b += abytes<AxisOwn>(P.aown.size()) + abytes<int2>(P.strip.size() > 0 ? P.strip.size() : 1);
+    b += abytes<double>(P.btab.size()) + abytes<SolveItem>(P.items.size()) + abytes<double>((size_t)P.nglob);
+    b += abytes<int>((size_t)3 * P.nsub);                           // factorisation status flags
+    b += abytes<char>((size_t)P.fel * es);                          // factors
+    b += (size_t)(1 + P.ring) * abytes<char>((size_t)nrhs * P.etot * es);  // g + ring
+    b += abytes<double2>((size_t)nrhs * P.nglob);                   // residual / operator output
+    if (mixed) b += abytes<double2>((size_t)nrhs * P.etot);         // widening scratch
+    b += abytes<double>(part_doubles(P, nrhs, 30));
+    b += abytes<double>((size_t)4 * nrhs) + abytes<int>((size_t)nrhs);  // norms, active flags
+    b += abytes<int>((size_t)4 * P.nsub + 1);                       // meeting / read-done / abort flags
+    if (chain2_fits(P)) b += abytes<int>((size_t)12 * P.nsub) + abytes<char>(chain2_xbuf_bytes(P));
+    b += 2 * abytes<double2>((size_t)nrhs * P.nglob);               // handle-owned f and u (graphs, slots)
+    return b;
+}
+
+// device bytes of the FGMRES(m) storage for nrhs right-hand sides beyond
+// what ddm_setup allocates: the bases V (m + 1 vectors) and Z (m), the dot
+// products and coefficients, and the growth of the partial-sum buffer
+size_t krylov_bytes(const Plan &P, int nrhs_max, int m) {
+    size_t b = abytes<double2>((size_t)(m + 1) * nrhs_max * P.nglob) + abytes<double2>((size_t)m * nrhs_max * P.nglob);
+    b += abytes<double2>((size_t)3 * (m + 1) * nrhs_max) + abytes<double2>((size_t)(m + 1) * nrhs_max);
+    const size_t need = part_doubles(P, nrhs_max, m), have = part_doubles(P, nrhs_max, 30);
+    if (need > have) b += abytes<double>(need) - abytes<double>(have);
+    return b;
+}
+
+// peak device bytes of a handle: its setup allocations plus the
+// factorisation workspace (held during ddm_factor only); plus the FGMRES
+// storage for restart m when m > 0
+size_t plan_bytes(const Plan &P, bool mixed, int nrhs, int m) {
+    size_t b = setup_bytes(P, mixed, nrhs) + factor_ws_bytes(P);
+    if (m > 0) b += krylov_bytes(P, nrhs, m);
     return b;
 }
 
@@ -119,14 +158,12 @@ void free_all(ddm_handle *h) {
     void *ptrs[] = {h->d_subs, h->d_coef, h->d_gcoef, h->d_aown, h->d_strip, h->d_btab, h->d_k2, h->d_items, h->d_W,
                     h->d_scratch, h->d_flags, h->d_g, h->d_ring[0], h->d_ring[1], h->d_ring[2], h->d_ring[3],
                     h->d_r, h->d_wide, h->d_part, h->d_norm, h->d_active, h->d_V, h->d_Z, h->d_dots,
-                    h->d_coef_y, h->d_sync, h->d_sync2, h->d_xbuf};
+                    h->d_coef_y, h->d_sync, h->d_sync2, h->d_xbuf, h->d_fin, h->d_uin};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < 4; ++k)
         if (h->step_graph[k]) (void)hipGraphExecDestroy(h->step_graph[k]);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    if (h->d_fin) (void)hipFree(h->d_fin);
-    if (h->d_uin) (void)hipFree(h->d_uin);
     for (auto &r : h->prof_recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
@@ -273,10 +310,10 @@ void residual_host(ddm_handle *h, const double2 *f, const double2 *u, double2 *r
 // chain exceeded its spin bound; read and clear it (synchronises the stream).
 int check_abort(ddm_handle *h) {
     int flag = 0;
-    HIPCHK(hipMemcpyAsync(&flag, h->d_sync + 2 * h->plan.nsub, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&flag, abort_flag_ptr(h), sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     if (flag) {
-        HIPCHK(hipMemsetAsync(h->d_sync + 2 * h->plan.nsub, 0, sizeof(int), h->stream));
+        HIPCHK(hipMemsetAsync(abort_flag_ptr(h), 0, sizeof(int), h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         return fail(h, DDM_EHIP, "substitution: the wait for the partner chain exceeded its spin bound; results invalid");
     }
@@ -318,8 +355,6 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
     double2 *uout = u;
     const size_t vbytes = (size_t)nrhs * P.nglob * sizeof(double2);
     if (graphs) {
-        if (!h->d_fin) HIPCHK(hipMalloc((void **)&h->d_fin, (size_t)h->nrhs_max * P.nglob * sizeof(double2)));
-        if (!h->d_uin) HIPCHK(hipMalloc((void **)&h->d_uin, (size_t)h->nrhs_max * P.nglob * sizeof(double2)));
         HIPCHK(hipMemcpyAsync(h->d_fin, f, vbytes, hipMemcpyDeviceToDevice, h->stream));
         f = h->d_fin;
         u = h->d_uin;
@@ -334,7 +369,10 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
     // (opt-in: the residual-corrected sources of the mixed path do not stall)
     const int refine_every = o.refine_every;
     double2 *rsrc = h->d_r;  // residual (corrected sources) / restart source
+    const int check_every = std::max(1, o.check_every);
     auto check = [&](int it, const double2 **restart) -> bool {
+        // between checks the steps are only enqueued (no host synchronisation)
+        if (it % check_every != 0 && it < o.maxiter) return true;
         fetch_norms(h, nrhs, rel, &fn);
         bool all = true, changed = false;
         bool stalled = false;
@@ -390,23 +428,34 @@ int solve_stationary(ddm_handle *h, const double2 *f, double2 *u, int nrhs, cons
 // ---------------------------------------------------------------------------
 void ensure_krylov(ddm_handle *h, int m, int nrhs) {
     if (h->d_V && h->krylov_m >= m && h->krylov_nrhs >= nrhs) return;
-    if (h->d_V) { HIPCHK(hipFree(h->d_V)); h->d_V = nullptr; }
-    if (h->d_Z) { HIPCHK(hipFree(h->d_Z)); h->d_Z = nullptr; }
-    if (h->d_dots) { HIPCHK(hipFree(h->d_dots)); h->d_dots = nullptr; }
-    if (h->d_coef_y) { HIPCHK(hipFree(h->d_coef_y)); h->d_coef_y = nullptr; }
+    const Plan &P = h->plan;
+    const int km = h->krylov_m, kn = h->krylov_nrhs;
+    dfree(h, &h->d_V, (size_t)(km + 1) * kn * P.nglob);
+    dfree(h, &h->d_Z, (size_t)km * kn * P.nglob);
+    dfree(h, &h->d_dots, (size_t)3 * (km + 1) * kn);
+    dfree(h, &h->d_coef_y, (size_t)(km + 1) * kn);
     if (h->h_dots) { HIPCHK(hipHostFree(h->h_dots)); h->h_dots = nullptr; }
-    long long n = h->plan.nglob;
-    size_t need = part_doubles(h->plan, std::max(nrhs, h->nrhs_max), m);
+    h->krylov_m = h->krylov_nrhs = 0;
+    long long n = P.nglob;
+    size_t need = part_doubles(P, std::max(nrhs, h->nrhs_max), m);
+    // the basis lives beside the factors: respect the handle's HBM budget
+    size_t grow = abytes<double2>((size_t)(m + 1) * nrhs * n) + abytes<double2>((size_t)m * nrhs * n) +
+                  abytes<double2>((size_t)3 * (m + 1) * nrhs) + abytes<double2>((size_t)(m + 1) * nrhs) +
+                  (need > h->part_cap ? abytes<double>(need) - abytes<double>(h->part_cap) : 0);
+    if (h->prob.hbm_budget_bytes > 0 && h->bytes + grow > h->prob.hbm_budget_bytes)
+        throw HipFail{hipErrorOutOfMemory, "FGMRES basis beyond the HBM budget"};
     if (need > h->part_cap) {
-        HIPCHK(hipFree(h->d_part));
-        h->d_part = nullptr;
-        HIPCHK(hipMalloc((void **)&h->d_part, need * sizeof(double)));
+        dfree(h, &h->d_part, h->part_cap);
+        dalloc(h, &h->d_part, need);
         h->part_cap = need;
     }
-    HIPCHK(hipMalloc((void **)&h->d_V, (size_t)(m + 1) * nrhs * n * sizeof(double2)));
-    HIPCHK(hipMalloc((void **)&h->d_Z, (size_t)m * nrhs * n * sizeof(double2)));
-    HIPCHK(hipMalloc((void **)&h->d_dots, (size_t)3 * (m + 1) * nrhs * sizeof(double2)));
-    HIPCHK(hipMalloc((void **)&h->d_coef_y, (size_t)(m + 1) * nrhs * sizeof(double2)));
+    dalloc(h, &h->d_V, (size_t)(m + 1) * nrhs * n);
+    dalloc(h, &h->d_Z, (size_t)m * nrhs * n);
+    dalloc(h, &h->d_dots, (size_t)3 * (m + 1) * nrhs);
+    dalloc(h, &h->d_coef_y, (size_t)(m + 1) * nrhs);
+    // the update x += Z y reads only the basis vectors a cycle formed, but
+    // start from zeros so no stale bits can ever reach it
+    HIPCHK(launch_fill_zero(h->d_Z, (long long)m * nrhs * n * sizeof(double2), h->stream));
     HIPCHK(hipHostMalloc((void **)&h->h_dots, (size_t)3 * (m + 1) * nrhs * sizeof(double2), hipHostMallocDefault));
     h->krylov_m = m;
     h->krylov_nrhs = nrhs;
@@ -515,7 +564,10 @@ int solve_fgmres(ddm_handle *h, const double2 *f, double2 *x, int nrhs, const dd
             }
             if (cycle_done) break;
         }
-        // x_q += Z y_q, y from the triangular system of the cycle
+        // x_q += Z y_q, y from the triangular system of the cycle; only the
+        // nvec basis vectors this cycle formed enter the update
+        int nvec = 0;
+        for (int q = 0; q < nrhs; ++q) nvec = std::max(nvec, done[q] ? 0 : jr[q]);
         for (int q = 0; q < nrhs; ++q) {
             std::vector<cd> y(m, cd(0));
             int jq = done[q] ? 0 : jr[q];
@@ -526,10 +578,13 @@ int solve_fgmres(ddm_handle *h, const double2 *f, double2 *x, int nrhs, const dd
                 for (int k = i + 1; k < jq; ++k) s -= Hq[i * m + k] * y[k];
                 y[i] = s / Hq[i * m + i];
             }
-            for (int i = 0; i < m; ++i) yh[(size_t)q * m + i] = make_double2(y[i].real(), y[i].imag());
+            for (int i = 0; i < nvec; ++i) yh[(size_t)q * nvec + i] = make_double2(y[i].real(), y[i].imag());
         }
-        HIPCHK(hipMemcpyAsync(h->d_coef_y, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, h->stream));
-        HIPCHK(launch_axpy_multi(x, Z, m, vstride, h->d_coef_y, 1.0, n, nrhs, n, h->stream));
+        if (nvec > 0) {
+            HIPCHK(hipMemcpyAsync(h->d_coef_y, yh.data(), (size_t)nrhs * nvec * sizeof(double2), hipMemcpyHostToDevice,
+                                  h->stream));
+            HIPCHK(launch_axpy_multi(x, Z, nvec, vstride, h->d_coef_y, 1.0, n, nrhs, n, h->stream));
+        }
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     double t1 = now_s();
@@ -717,8 +772,6 @@ static int slots_init(ddm_handle *h) {
     if (!h->slot_steps.empty()) return DDM_OK;
     const Plan &P = h->plan;
     const size_t vb = (size_t)h->nrhs_max * P.nglob * sizeof(double2);
-    if (!h->d_fin) HIPCHK(hipMalloc((void **)&h->d_fin, vb));
-    if (!h->d_uin) HIPCHK(hipMalloc((void **)&h->d_uin, vb));
     HIPCHK(launch_fill_zero(h->d_fin, (long long)vb, h->stream));
     HIPCHK(launch_fill_zero(h->d_uin, (long long)vb, h->stream));
     HIPCHK(launch_fill_zero(h->d_r, (long long)vb, h->stream));
@@ -856,13 +909,52 @@ int ddm_memory_required(const ddm_problem *p, int nrhs_max, size_t *bytes) {
     return DDM_OK;
 }
 
+// PML strength for a target reflection R of the quadratic profile
+// sigma0 (t/delta)^2: a wave of wave number k crossing the layer twice is
+// damped by exp(-2 k int_0^delta sigma) = exp(-2 k sigma0 delta / 3).
+static double sigma0_from_reflection(double R, double k_ref, double delta) {
+    return 3.0 * std::log(1.0 / R) / (2.0 * k_ref * delta);
+}
+
 int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream, ddm_handle **out) {
-    if (!out || !k2 || nrhs_max < 1) return fail(nullptr, DDM_EINVAL, "out and k2 must be non-null, nrhs_max >= 1");
+    if (!out || !k2 || !p || nrhs_max < 1)
+        return fail(nullptr, DDM_EINVAL, "p, out and k2 must be non-null, nrhs_max >= 1");
     *out = nullptr;
+    ddm_problem pv = *p;
+    if (!(pv.reflection >= 0 && pv.reflection < 1))
+        return fail(nullptr, DDM_EINVAL, "reflection must lie in [0, 1)");
+    if (pv.reflection > 0 && pv.sigma0 != 0)
+        return fail(nullptr, DDM_EINVAL, "give sigma0 or reflection, not both");
+    std::vector<double> hk2;
+    {
+        // the grid size, then k2 (host copy: finiteness check, k_ref)
+        Plan P0;
+        std::string e0;
+        ddm_problem pz = pv;
+        pz.sigma0 = 0;
+        int s0 = build_plan(&pz, &P0, &e0);
+        if (s0) return fail(nullptr, s0, e0);
+        hk2.resize(P0.nglob);
+        if (pv.k2_on_host) {
+            memcpy(hk2.data(), k2, P0.nglob * sizeof(double));
+        } else if (hipMemcpy(hk2.data(), k2, P0.nglob * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(nullptr, DDM_EINVAL, "k2 could not be read as a device pointer (set k2_on_host for host memory)");
+        }
+        double kmin2 = INFINITY;
+        for (double v : hk2) {
+            if (!std::isfinite(v)) return fail(nullptr, DDM_EINVAL, "k2 has non-finite entries");
+            kmin2 = std::min(kmin2, v);
+        }
+        if (pv.reflection > 0) {
+            if (!(kmin2 > 0)) return fail(nullptr, DDM_EINVAL, "reflection needs k2 > 0 everywhere (k_ref = sqrt(min k2))");
+            pv.sigma0 = sigma0_from_reflection(pv.reflection, std::sqrt(kmin2), pv.n_pml * pv.h);
+        }
+    }
     ddm_handle *h = new (std::nothrow) ddm_handle();
     if (!h) return fail(nullptr, DDM_ENOMEM, "host allocation failed");
     std::string err;
-    int st = build_plan(p, &h->plan, &err);
+    int st = build_plan(&pv, &h->plan, &err);
     if (st) { delete h; return fail(nullptr, st, err); }
     {
         // the chain launches need every workgroup resident: bound them by this
@@ -874,7 +966,7 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
             if (h->plan.twisted && !plan_twist_fits(h->plan)) plan_set_twist(&h->plan, false);
         }
     }
-    h->prob = *p;
+    h->prob = pv;
     h->mixed = p->precision == DDM_MIXED;
     h->nrhs_max = nrhs_max;
     h->stream = (hipStream_t)stream;
@@ -887,11 +979,6 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         return fail(nullptr, DDM_ENOMEM, buf);
     }
     try {
-        // k2 must be finite
-        std::vector<double> hk2(P.nglob);
-        HIPCHK(hipMemcpy(hk2.data(), k2, P.nglob * sizeof(double), hipMemcpyDeviceToHost));
-        for (double v : hk2)
-            if (!std::isfinite(v)) { free_all(h); delete h; return fail(nullptr, DDM_EINVAL, "k2 has non-finite entries"); }
         dalloc(h, &h->d_subs, P.subs.size());
         dalloc(h, &h->d_coef, P.coef.size());
         dalloc(h, &h->d_gcoef, P.gcoef.size());
@@ -911,23 +998,30 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         HIPCHK(hipMemcpy(h->d_items, P.items.data(), P.items.size() * sizeof(SolveItem), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(h->d_k2, hk2.data(), P.nglob * sizeof(double), hipMemcpyHostToDevice));
         size_t es = elem_size(h->mixed);
-        HIPCHK(hipMalloc(&h->d_W, (size_t)P.fel * es));
-        h->bytes += (size_t)P.fel * es;
-        HIPCHK(hipMalloc(&h->d_g, (size_t)nrhs_max * P.etot * es));
-        for (int k = 0; k < P.ring; ++k) HIPCHK(hipMalloc(&h->d_ring[k], (size_t)nrhs_max * P.etot * es));
-        h->bytes += (size_t)(1 + P.ring) * nrhs_max * P.etot * es;
+        dalloc(h, (char **)&h->d_W, (size_t)P.fel * es);
+        dalloc(h, (char **)&h->d_g, (size_t)nrhs_max * P.etot * es);
+        for (int k = 0; k < P.ring; ++k) dalloc(h, (char **)&h->d_ring[k], (size_t)nrhs_max * P.etot * es);
         dalloc(h, &h->d_r, (size_t)nrhs_max * P.nglob);
         if (h->mixed) dalloc(h, &h->d_wide, (size_t)nrhs_max * P.etot);
         h->part_cap = part_doubles(P, nrhs_max, 30);
         dalloc(h, &h->d_part, h->part_cap);
         dalloc(h, &h->d_norm, (size_t)4 * nrhs_max);
         dalloc(h, &h->d_active, (size_t)nrhs_max);
-        dalloc(h, &h->d_sync, (size_t)2 * P.nsub + 1);
-        HIPCHK(hipMemset(h->d_sync, 0, (2 * P.nsub + 1) * sizeof(int)));
+        dalloc(h, &h->d_sync, (size_t)4 * P.nsub + 1);
+        HIPCHK(hipMemset(h->d_sync, 0, (4 * P.nsub + 1) * sizeof(int)));
         if (chain2_fits(P)) {
-            dalloc(h, &h->d_sync2, (size_t)8 * P.nsub);
-            HIPCHK(hipMalloc(&h->d_xbuf, chain2_xbuf_bytes(P)));
-            h->bytes += chain2_xbuf_bytes(P);
+            dalloc(h, &h->d_sync2, (size_t)12 * P.nsub);
+            dalloc(h, (char **)&h->d_xbuf, chain2_xbuf_bytes(P));
+        }
+        dalloc(h, &h->d_fin, (size_t)nrhs_max * P.nglob);
+        dalloc(h, &h->d_uin, (size_t)nrhs_max * P.nglob);
+        if (h->bytes != setup_bytes(P, h->mixed, nrhs_max)) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "internal: setup allocated %zu bytes, the plan counts %zu", h->bytes,
+                     setup_bytes(P, h->mixed, nrhs_max));
+            free_all(h);
+            delete h;
+            return fail(nullptr, DDM_EHIP, buf);
         }
         h->solve_variant = default_variant(h);
         HIPCHK(hipHostMalloc((void **)&h->h_norm, 4 * nrhs_max * sizeof(double), hipHostMallocDefault));
@@ -949,6 +1043,19 @@ void ddm_destroy(ddm_handle *h) {
     else (void)hipDeviceSynchronize();
     free_all(h);
     delete h;
+}
+
+int ddm_pml_strength(const ddm_handle *h, double *sigma0) {
+    if (!h || !sigma0) return DDM_EINVAL;
+    *sigma0 = h->plan.sigma0;
+    return DDM_OK;
+}
+
+int ddm_device_bytes(const ddm_handle *h, size_t *held, size_t *peak) {
+    if (!h) return DDM_EINVAL;
+    if (held) *held = h->bytes;
+    if (peak) *peak = h->peak_bytes;
+    return DDM_OK;
 }
 
 int ddm_sizes(const ddm_handle *h, long *out) {
@@ -978,16 +1085,13 @@ int ddm_factor(ddm_handle *h) {
     if (!h) return DDM_EINVAL;
     const Plan &P = h->plan;
     try {
-        if (!h->d_scratch) {
-            HIPCHK(hipMalloc(&h->d_scratch, factor_ws_bytes(P)));
-        }
+        if (!h->d_scratch) dalloc(h, (char **)&h->d_scratch, factor_ws_bytes(P));
         if (h->mixed) HIPCHK(launch_factor<float2>(h, h->d_scratch));
         else HIPCHK(launch_factor<double2>(h, h->d_scratch));
         std::vector<int> flags(3 * P.nsub);
         HIPCHK(hipMemcpyAsync(flags.data(), h->d_flags, 3 * P.nsub * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
-        HIPCHK(hipFree(h->d_scratch));
-        h->d_scratch = nullptr;
+        dfree(h, (char **)&h->d_scratch, factor_ws_bytes(P));
         for (int q = 0; q < 3 * P.nsub; ++q)
             if (flags[q]) {
                 char buf[160];

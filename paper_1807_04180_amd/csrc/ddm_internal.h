@@ -122,7 +122,8 @@ struct ddm_handle {
     double *h_norm = nullptr;       // pinned host copy
     int *d_active = nullptr;        // per-RHS flags for the assembly
     int nblk_norm = 0;
-    size_t bytes = 0;
+    size_t bytes = 0;               // device bytes held (every allocation counted)
+    size_t peak_bytes = 0;          // most device bytes held at once
     // FGMRES storage (allocated on first use)
     double2 *d_V = nullptr, *d_Z = nullptr;
     int krylov_m = 0, krylov_nrhs = 0;
@@ -131,8 +132,9 @@ struct ddm_handle {
     double2 *d_coef_y = nullptr;    // Krylov combination coefficients
     // substitution kernel variant (autotuned) and persistent-launch sync state
     int solve_variant = 0;
-    int *d_sync = nullptr;          // 2 nsub meeting flags + 1 abort flag
-    int *d_sync2 = nullptr;         // split substitution: 4 nsub meeting + 4 nsub exchange flags
+    int *d_sync = nullptr;          // 2 nsub meeting flags, 2 nsub read-done flags, 1 abort flag
+    int *d_sync2 = nullptr;         // split substitution: 4 nsub meeting, 4 nsub exchange and
+                                    // 4 nsub read-done flags
     void *d_xbuf = nullptr;         // split substitution: double-buffered partial-sum exchange
     int spin_limit = 1 << 22;
     int transfer_form = 0;          // DDM_TRANSFER_DIRECT / DDM_TRANSFER_PHI
@@ -156,6 +158,9 @@ struct ddm_handle {
 };
 
 namespace ddm {
+
+// sticky abort flag of the bounded waits in the substitution kernels
+inline int *abort_flag_ptr(ddm_handle *h) { return h->d_sync + 4 * h->plan.nsub; }
 
 // Bracket one launch with a pair of events when profiling is on.
 struct ProfScope {

@@ -254,7 +254,7 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
                                                            const Coef *__restrict__ coef, const T2 *__restrict__ W,
                                                            const T2 *__restrict__ g, T2 *__restrict__ x, int nrhs,
                                                            long long etot, int dim, int twisted, int *flags,
-                                                           int *abort_flag, int spin_limit) {
+                                                           int *rflags, int *abort_flag, int spin_limit) {
     extern __shared__ unsigned char lds_raw[];
     using LT = typename LaneT<T2, ROWS>::type;
     // 512-thread workgroups (256 VGPRs) keep 8 columns per batch, also for
@@ -305,6 +305,9 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
 
     for (int r0 = 0; r0 < nrhs; r0 += RT) {
         const int nr = nrhs - r0 < RT ? nrhs - r0 : RT;
+        // flags count RHS tiles: tile k publishes k + 1 (no reset inside the
+        // launch, so a fast chain cannot erase a signal)
+        const int epoch = r0 / RT + 1;
         // initial v = g_{lfirst} (the middle step builds its own v)
         if (nf > 0) {
             const int l0 = lfirst;
@@ -346,9 +349,6 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
                 __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are complete
                 __syncthreads();
                 if (twisted) {
-                    // flags count RHS tiles: tile k publishes k + 1 (no reset
-                    // inside the launch, so a fast chain cannot erase a signal)
-                    const int epoch = r0 / RT + 1;
                     if (threadIdx.x == 0)
                         __hip_atomic_store(flags + 2 * a + chain, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     wait_flag_relaxed(flags + 2 * a + (1 - chain), epoch, abort_flag, spin_limit);
@@ -366,6 +366,11 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
                     vs[e] = from_d2<T2>(v);
                 }
                 __syncthreads();
+                // every read of the partner's last y block has returned (its
+                // value is in LDS): the partner may now overwrite that block
+                // with its first backward result
+                if (twisted && threadIdx.x == 0)
+                    __hip_atomic_store(rflags + 2 * a + chain, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             // ---- prefetch the block-vector entries the reduction will need
             // (forward: g of the next block; backward: this block's y) ----
@@ -488,6 +493,10 @@ __global__ __launch_bounds__(NT) void k_solve_chain(const SubDesc *__restrict__ 
             if (lnext >= 0)
                 lds_prefetch<T2, PF, ROWS>(Wbase + (long long)lnext * bs2, mypf, cg, CG, bs, ld, rowc, gemv);
             __syncthreads();
+            // the first backward step overwrites the y block the partner read
+            // at the middle: wait until the partner has finished reading it
+            if (twisted && t == nf + 1)
+                wait_flag_relaxed(rflags + 2 * a + (1 - chain), epoch, abort_flag, spin_limit);
             // ---- reduce over column groups; update x; build the next v ----
 #pragma unroll
             for (int u = 0; u < kPre; ++u) {
@@ -556,7 +565,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__res
                                                             const Coef *__restrict__ coef, const T2 *__restrict__ W,
                                                             const T2 *__restrict__ g, T2 *__restrict__ x, int nrhs,
                                                             long long etot, int dim, int nunits, int *mflags,
-                                                            int *xflags, int *abort_flag, int spin_limit,
+                                                            int *xflags, int *rflags, int *abort_flag, int spin_limit,
                                                             T2 *__restrict__ xbuf) {
     static_assert(RT <= 4, "exchange slots hold tiles of up to 4 RHS");
     extern __shared__ unsigned char lds_raw[];
@@ -603,6 +612,7 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__res
 
     for (int r0 = 0; r0 < nrhs; r0 += RT) {
         const int nr = nrhs - r0 < RT ? nrhs - r0 : RT;
+        const int epoch = r0 / RT + 1;  // meeting epoch of this RHS tile
         if (nf > 0 && own_ok)
             vs[io * RT + qo] = qo < nr ? g[(long long)(r0 + qo) * etot + off + (long long)lfirst * bs + io] : czero<T2>();
         __syncthreads();
@@ -631,7 +641,6 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__res
                 // middle: v = g_mid - cm y_{mid-1} - cp y_{mid+1} on the own rows; the
                 // other chain's same half wrote y_{mid+1} there
                 const Coef cmid = coef[s.coff[ax] + mid];
-                const int epoch = r0 / RT + 1;
                 __builtin_amdgcn_s_waitcnt(0);  // this wave's stores of the last y block are complete
                 __syncthreads();
                 if (threadIdx.x == 0)
@@ -650,6 +659,11 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__res
                     vs[io * RT + qo] = from_d2<T2>(v);
                 }
                 __syncthreads();
+                // the reads of the other chain's last y block have returned:
+                // its first backward step may overwrite that block now
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(rflags + 4 * a + 2 * chain + half, epoch, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
             const int tn = t + 1;
             const int lnv = tn < nsteps && tn != nf ? step_l(tn) : -1;
@@ -742,6 +756,9 @@ __global__ __launch_bounds__(kCThreads) void k_solve_chain2(const SubDesc *__res
                 }
             }
             wait_flag_relaxed(px, ep, abort_flag, spin_limit);
+            // the first backward step overwrites the y block that the other
+            // chain's same half read at the middle: wait for its reads
+            if (t == nf + 1) wait_flag_relaxed(rflags + 4 * a + 2 * (1 - chain) + half, epoch, abort_flag, spin_limit);
             if (own_ok) {
                 const T2 o = xload(slot + (size_t)(1 - half) * kXSlot + eo);
                 T2 sum = own;
@@ -837,7 +854,8 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (P.twisted) {
-        e = launch_fill_zero(h->d_sync, (long long)(2 * P.nsub) * sizeof(int), h->stream);
+        // meeting flags and read-done flags (4 nsub) start at zero
+        e = launch_fill_zero(h->d_sync, (long long)(4 * P.nsub) * sizeof(int), h->stream);
         if (e != hipSuccess) return e;
         const SubDesc *a0 = h->d_subs;
         const Coef *a1 = h->d_coef;
@@ -847,16 +865,17 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
         int a5 = nrhs;
         long long a6 = P.etot;
         int a7 = P.dim, a8 = 1;
-        int *a9 = h->d_sync, *a10 = h->d_sync + 2 * P.nsub;
+        int *a9 = h->d_sync, *a9r = h->d_sync + 2 * P.nsub, *a10 = abort_flag_ptr(h);
         int a11 = h->spin_limit;
-        void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11};
+        void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a9r, &a10, &a11};
         // the two chains of a subdomain meet once: they must be co-resident
         return hipLaunchCooperativeKernel((const void *)k_solve_chain<T2, RT, ROWS, NT, NPAIR>, dim3(2 * P.nsub), dim3(NT),
                                           args, lds, h->stream);
     }
     k_solve_chain<T2, RT, ROWS, NT, NPAIR><<<P.nsub, NT, lds, h->stream>>>(h->d_subs, h->d_coef, (const T2 *)h->d_W, g, x,
                                                                  nrhs, P.etot, P.dim, 0, h->d_sync,
-                                                                 h->d_sync + 2 * P.nsub, h->spin_limit);
+                                                                 h->d_sync + 2 * P.nsub, abort_flag_ptr(h),
+                                                                 h->spin_limit);
     return hipGetLastError();
 }
 
@@ -922,8 +941,9 @@ static hipError_t run_chain2(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     hipError_t e = hipFuncSetAttribute((const void *)k_solve_chain2<T2, RT, ROWS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    // meeting flags [4 nsub] and exchange flags [4 nsub] start at zero
-    e = launch_fill_zero(h->d_sync2, (long long)(8 * P.nsub) * sizeof(int), h->stream);
+    // meeting flags [4 nsub], exchange flags [4 nsub] and read-done flags
+    // [4 nsub] start at zero
+    e = launch_fill_zero(h->d_sync2, (long long)(12 * P.nsub) * sizeof(int), h->stream);
     if (e != hipSuccess) return e;
     const SubDesc *a0 = h->d_subs;
     const Coef *a1 = h->d_coef;
@@ -933,10 +953,11 @@ static hipError_t run_chain2(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     int a5 = nrhs;
     long long a6 = P.etot;
     int a7 = P.dim, a8 = 2 * P.nsub;
-    int *a9 = h->d_sync2, *a10 = h->d_sync2 + 4 * P.nsub, *a11 = h->d_sync + 2 * P.nsub;
+    int *a9 = h->d_sync2, *a10 = h->d_sync2 + 4 * P.nsub, *a10r = h->d_sync2 + 8 * P.nsub;
+    int *a11 = abort_flag_ptr(h);
     int a12 = h->spin_limit;
     T2 *a13 = (T2 *)h->d_xbuf;
-    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11, &a12, &a13};
+    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a10r, &a11, &a12, &a13};
     // the halves and chains of a subdomain wait on each other: all co-resident
     return hipLaunchCooperativeKernel((const void *)k_solve_chain2<T2, RT, ROWS>, dim3(chain2_grid(P)),
                                       dim3(kCThreads), args, lds, h->stream);

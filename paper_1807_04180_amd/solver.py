@@ -35,8 +35,9 @@ class Problem:
     n_ov: int
     mixed: bool = False
     hbm_budget_bytes: int = 0
+    reflection: float = 0.0   # > 0: the library derives sigma0 (then 0) from it
 
-    def to_c(self) -> _ffi.DdmProblem:
+    def to_c(self, k2_on_host: bool = False) -> _ffi.DdmProblem:
         p = _ffi.DdmProblem()
         p.dim = self.dim
         M = list(self.M) + [0] * (3 - len(self.M))
@@ -50,6 +51,8 @@ class Problem:
         p.n_ov = int(self.n_ov)
         p.precision = _ffi.DDM_MIXED if self.mixed else _ffi.DDM_FP64
         p.hbm_budget_bytes = int(self.hbm_budget_bytes)
+        p.reflection = float(self.reflection)
+        p.k2_on_host = 1 if k2_on_host else 0
         return p
 
     @classmethod
@@ -85,19 +88,22 @@ def _check_c128(t: torch.Tensor, n: int, name: str) -> int:
 
 
 class HelmholtzDDM:
-    """Handle on one factored problem (ddm_setup + ddm_factor)."""
+    """Handle on one factored problem (ddm_setup + ddm_factor).  k2 (float64,
+    nglob entries) may be a device tensor or host memory (a CPU tensor)."""
 
     def __init__(self, problem: Problem, k2: torch.Tensor, nrhs_max: int, factor: bool = True):
         self.lib = _ffi.lib()
         self.problem = problem
-        self.device = k2.device
         if k2.dtype != torch.float64:
             raise TypeError("k2 must be float64")
         k2 = k2.contiguous()
+        on_host = not k2.is_cuda
+        self.device = torch.device("cuda", torch.cuda.current_device()) if on_host else k2.device
         self.stream = torch.cuda.current_stream(self.device)
-        p = problem.to_c()
+        p = problem.to_c(k2_on_host=on_host)
         h = ctypes.c_void_p()
-        st = self.lib.ddm_setup(ctypes.byref(p), _ptr(k2), int(nrhs_max), ctypes.c_void_p(self.stream.cuda_stream),
+        kp = ctypes.c_void_p(k2.data_ptr()) if on_host else _ptr(k2)
+        st = self.lib.ddm_setup(ctypes.byref(p), kp, int(nrhs_max), ctypes.c_void_p(self.stream.cuda_stream),
                                 ctypes.byref(h))
         if st != 0:
             raise DDMError(st, self.lib.ddm_last_error(None).decode())
@@ -130,6 +136,17 @@ class HelmholtzDDM:
     def factor(self):
         self._check(self.lib.ddm_factor(self._h))
         self.factored = True
+
+    def pml_strength(self) -> float:
+        v = ctypes.c_double(0.0)
+        self._check(self.lib.ddm_pml_strength(self._h, ctypes.byref(v)))
+        return v.value
+
+    def device_bytes(self) -> Tuple[int, int]:
+        """(bytes held now, most bytes held at once) on the device."""
+        held, peak = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        self._check(self.lib.ddm_device_bytes(self._h, ctypes.byref(held), ctypes.byref(peak)))
+        return held.value, peak.value
 
     # -- geometry ----------------------------------------------------------
     def geometry(self, a: int) -> dict:
@@ -259,13 +276,15 @@ class HelmholtzDDM:
         return u, rel
 
     def solve(self, f: torch.Tensor, method: str = "stationary", tol: float = 1e-6, maxiter: int = 500,
-              restart: int = 30, K: int = 0, refine_every: int = 0, u: Optional[torch.Tensor] = None):
+              restart: int = 30, K: int = 0, refine_every: int = 0, u: Optional[torch.Tensor] = None,
+              check_every: int = 1):
         nrhs = _check_c128(f, self.nglob, "f")
         if u is None:
             u = torch.empty_like(f)
         o = _ffi.DdmSolveOpts()
         o.method = _ffi.DDM_FGMRES if method == "fgmres" else _ffi.DDM_STATIONARY
         o.tol, o.maxiter, o.restart, o.K, o.refine_every = tol, maxiter, restart, K, refine_every
+        o.check_every = check_every
         info = (_ffi.DdmRhsInfo * nrhs)()
         st = self._check(self.lib.ddm_solve(self._h, _ptr(f), _ptr(u), nrhs, ctypes.byref(o), info))
         infos = [dict(iters=i.iters, local_solves=i.local_solves, relres=i.relres, seconds=i.seconds,

@@ -62,3 +62,56 @@ def test_product_path_has_no_cpu_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(_ffi, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _ffi.lib()
+
+
+# ---- ddm_setup's host-side refusals (no device memory is touched) ----------
+
+def _setup_host_k2(prob, k2):
+    """ddm_setup with k2 in host memory; returns (status, message)."""
+    import numpy as np
+    L = ddm.lib()
+    k2 = np.ascontiguousarray(k2, dtype=np.float64)
+    p = prob.to_c(k2_on_host=True)
+    h = ctypes.c_void_p()
+    st = L.ddm_setup(ctypes.byref(p), k2.ctypes.data_as(ctypes.c_void_p), 1, None, ctypes.byref(h))
+    if st == 0:
+        L.ddm_destroy(h)
+    return st, L.ddm_last_error(None).decode()
+
+
+def _k2(prob, value=2500.0):
+    import numpy as np
+    G = [m + 2 * prob.n_pml - 1 for m in prob.M]
+    return np.full(int(np.prod(G)), value)
+
+
+def test_setup_rejects_non_finite_k2():
+    import numpy as np
+    p = _prob()
+    for bad in (float("nan"), float("inf")):
+        k2 = _k2(p)
+        k2[1234] = bad
+        st, msg = _setup_host_k2(p, k2)
+        assert st == _ffi.DDM_EINVAL and "non-finite" in msg
+
+
+@pytest.mark.parametrize("kw,value,needle", [
+    (dict(sigma0=3.3, reflection=1e-6), 2500.0, "not both"),
+    (dict(sigma0=0.0, reflection=1.0), 2500.0, "reflection"),
+    (dict(sigma0=0.0, reflection=-0.5), 2500.0, "reflection"),
+    (dict(sigma0=0.0, reflection=1e-6), 0.0, "k2 > 0"),
+])
+def test_setup_rejects_bad_pml_request(kw, value, needle):
+    p = _prob(**kw)
+    st, msg = _setup_host_k2(p, _k2(p, value))
+    assert st == _ffi.DDM_EINVAL and needle in msg
+
+
+def test_setup_refuses_plan_beyond_budget():
+    """SURVEY failure mode (iv): a plan larger than hbm_budget_bytes is refused
+    with DDM_ENOMEM before any device allocation."""
+    p = _prob()
+    need = p.memory_required(1)
+    p.hbm_budget_bytes = need - 1
+    st, msg = _setup_host_k2(p, _k2(p))
+    assert st == _ffi.DDM_ENOMEM and "budget" in msg
