@@ -198,6 +198,19 @@ int ddm_apply(ddm_handle *h, const void *u, void *out, int nrhs);
 int ddm_residual(ddm_handle *h, const void *f, const void *u, void *r, int nrhs,
                  double *rnorm2, double *fnorm2);
 
+/* ddm_residual for callers that cannot allocate device memory or synchronise
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * allocation): the same kernels and results (bit for bit), but it allocates
+ * nothing, creates no events and does not wait.  norms is a DEVICE array of
+ * 2 nrhs doubles: norms[q] = ||r_q||^2, norms[nrhs + q] = ||f_q||^2, written
+ * on the handle's stream.  The block partial sums live in one static device
+ * array of the library (1 MiB, 2 nrhs x (grid rows rounded up to 8) doubles
+ * at most; larger calls return DDM_EINVAL and say the limit), held by every
+ * GPU the library has run on until the process ends and shared by all calls
+ * on that GPU: calls that overlap on one GPU race.  Never profiled. */
+int ddm_residual_noalloc(ddm_handle *h, const void *f, const void *u, void *r, int nrhs,
+                         double *norms);
+
 /* Step-1 sources: g_a = f restricted to the core of a (f_{i,j} of Sec. 2.2),
  * written to the packed vector g (zero outside the cores). */
 int ddm_restrict_core(ddm_handle *h, const void *f, void *g, int nrhs);

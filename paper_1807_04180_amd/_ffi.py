@@ -76,6 +76,7 @@ def lib():
     L.ddm_geometry.argtypes = [H, I, LP]
     L.ddm_apply.argtypes = [H, P, P, I]
     L.ddm_residual.argtypes = [H, P, P, P, I, DP, DP]
+    L.ddm_residual_noalloc.argtypes = [H, P, P, P, I, P]
     L.ddm_restrict_core.argtypes = [H, P, P, I]
     L.ddm_local_solve.argtypes = [H, P, P, I]
     L.ddm_transfer.argtypes = [H, P, P, P, P, I]
@@ -97,7 +98,7 @@ def lib():
     L.ddm_profile_read.argtypes = [H, ctypes.POINTER(DdmProfile)]
     for name in ("ddm_slot_admit", "ddm_slots_step", "ddm_slots_poll", "ddm_slot_retire", "ddm_set_graphs", "ddm_set_factor_layout", "ddm_set_solve_variant", "ddm_get_solve_variant", "ddm_autotune", "ddm_set_spin_limit", "ddm_set_transfer_form",
                  "ddm_profile_enable", "ddm_profile_read", "ddm_memory_required", "ddm_setup", "ddm_factor", "ddm_iterate", "ddm_solve", "ddm_sizes",
-                 "ddm_geometry", "ddm_apply", "ddm_residual", "ddm_restrict_core", "ddm_local_solve",
+                 "ddm_geometry", "ddm_apply", "ddm_residual", "ddm_residual_noalloc", "ddm_restrict_core", "ddm_local_solve",
                  "ddm_transfer", "ddm_assemble", "ddm_pml_strength", "ddm_device_bytes"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L

@@ -32,8 +32,8 @@ static hipEvent_t pool_get(ddm_handle *h) {
     return e;
 }
 
-ProfScope::ProfScope(ddm_handle *h_, int cls_, double bytes_) : h(h_), cls(cls_), bytes(bytes_) {
-    if (!h->prof_on) return;
+ProfScope::ProfScope(ddm_handle *h_, int cls_, double bytes_, bool on) : h(h_), cls(cls_), bytes(bytes_) {
+    if (!on || !h->prof_on) return;
     a = pool_get(h);
     b = pool_get(h);
     if (a && b) (void)hipEventRecord(a, h->stream);
@@ -965,6 +965,7 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
             h->plan.ncu = ncu;
             if (h->plan.twisted && !plan_twist_fits(h->plan)) plan_set_twist(&h->plan, false);
         }
+        h->device = dev;
     }
     h->prob = pv;
     h->mixed = p->precision == DDM_MIXED;
@@ -977,6 +978,18 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         snprintf(buf, sizeof buf, "plan needs %zu bytes, budget is %zu", need, p->hbm_budget_bytes);
         delete h;
         return fail(nullptr, DDM_ENOMEM, buf);
+    }
+    {
+        // the static scratch of the allocation-free entry points: its device
+        // address on this device, looked up once
+        hipError_t se = scratch_init(h->device);
+        if (se != hipSuccess) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "static scratch lookup failed on device %d: %s", h->device,
+                     hipGetErrorString(se));
+            delete h;
+            return fail(nullptr, DDM_EHIP, buf);
+        }
     }
     try {
         dalloc(h, &h->d_subs, P.subs.size());

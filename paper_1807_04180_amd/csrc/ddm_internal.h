@@ -84,6 +84,10 @@ struct Plan {
 };
 
 int build_plan(const ddm_problem *p, Plan *plan, std::string *err);
+// Device address of the library's static scratch array on device dev (which
+// must be current); resolved once per device.  Returns hipSuccess or the
+// error of the symbol lookup.
+hipError_t scratch_init(int dev);
 // choose the elimination layout (sets mid of every subdomain)
 void plan_set_twist(Plan *plan, bool twisted);
 bool plan_twist_fits(const Plan &P);
@@ -94,6 +98,7 @@ struct ddm_handle {
     ddm_problem prob;
     ddm::Plan plan;
     hipStream_t stream = nullptr;
+    int device = 0;                 // HIP device current at ddm_setup
     std::string err;
     int nrhs_max = 0;
     bool mixed = false;
@@ -168,7 +173,8 @@ struct ProfScope {
     int cls;
     double bytes;
     hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(ddm_handle *h_, int cls_, double bytes_);
+    // on = false: never profile (the allocation-free entry points create no events)
+    ProfScope(ddm_handle *h_, int cls_, double bytes_, bool on = true);
     ~ProfScope();
 };
 
@@ -176,6 +182,10 @@ struct ProfScope {
 hipError_t launch_apply(ddm_handle *h, const double2 *u, double2 *out, int nrhs);
 hipError_t launch_residual(ddm_handle *h, const double2 *f, const double2 *u, double2 *r, int nrhs,
                            double *d_rn2, double *d_fn2);
+// the same with the block partial sums (2 nrhs stencil_blocks doubles, every
+// entry written before it is read) in a buffer of the caller's
+hipError_t launch_residual_parts(ddm_handle *h, const double2 *f, const double2 *u, double2 *r, int nrhs,
+                                 double *part, double *d_rn2, double *d_fn2, bool profile = true);
 hipError_t launch_norm2(ddm_handle *h, const double2 *x, long long n, int nrhs, long long ld, double *d_out);
 
 template <typename TIN, typename TOUT>

@@ -156,12 +156,17 @@ hipError_t launch_apply(ddm_handle *h, const double2 *u, double2 *out, int nrhs)
 
 hipError_t launch_residual(ddm_handle *h, const double2 *f, const double2 *u, double2 *r, int nrhs, double *d_rn2,
                            double *d_fn2) {
+    return launch_residual_parts(h, f, u, r, nrhs, h->d_part, d_rn2, d_fn2);
+}
+
+hipError_t launch_residual_parts(ddm_handle *h, const double2 *f, const double2 *u, double2 *r, int nrhs,
+                                 double *part, double *d_rn2, double *d_fn2, bool profile) {
     const Plan &P = h->plan;
     int nblk = stencil_blocks(P);
     dim3 grid(nblk, nrhs);
-    double *part_r = h->d_part, *part_f = h->d_part + (long long)nrhs * nblk;
+    double *part_r = part, *part_f = part + (long long)nrhs * nblk;
     // f and u read, r written (if requested), k^2 read
-    ProfScope ps(h, DDM_K_RESIDUAL, (double)P.nglob * (nrhs * (r ? 48.0 : 32.0) + 8.0));
+    ProfScope ps(h, DDM_K_RESIDUAL, (double)P.nglob * (nrhs * (r ? 48.0 : 32.0) + 8.0), profile);
     k_stencil<0><<<grid, kBlock, 0, h->stream>>>(f, u, r, h->d_k2, h->d_gcoef, grid_args(P), part_r, part_f);
     k_sum_partials<<<nrhs, kBlock, 0, h->stream>>>(part_r, nblk, d_rn2);
     k_sum_partials<<<nrhs, kBlock, 0, h->stream>>>(part_f, nblk, d_fn2);

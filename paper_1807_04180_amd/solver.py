@@ -177,6 +177,19 @@ class HelmholtzDDM:
         self._check(self.lib.ddm_residual(self._h, _ptr(f), _ptr(u), _ptr(r), nrhs, rn, fn))
         return r, list(rn), list(fn)
 
+    def residual_noalloc(self, f: torch.Tensor, u: torch.Tensor, r: Optional[torch.Tensor] = None,
+                         norms: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """ddm_residual_noalloc: r (if given) = f - L_h u; returns the device
+        tensor norms = [||r_q||^2 ..., ||f_q||^2 ...] (float64, 2 nrhs),
+        written asynchronously on the handle's stream."""
+        nrhs = _check_c128(f, self.nglob, "f")
+        if norms is None:
+            norms = torch.empty(2 * nrhs, dtype=torch.float64, device=f.device)
+        if norms.dtype != torch.float64 or norms.numel() < 2 * nrhs:
+            raise ValueError("norms must be float64 with at least 2 nrhs entries")
+        self._check(self.lib.ddm_residual_noalloc(self._h, _ptr(f), _ptr(u), _ptr(r), nrhs, _ptr(norms)))
+        return norms
+
     def restrict_core(self, f: torch.Tensor) -> torch.Tensor:
         nrhs = _check_c128(f, self.nglob, "f")
         g = self.zeros_packed(nrhs)
