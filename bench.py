@@ -67,7 +67,8 @@ def pct(v, p):
     return float(np.percentile(np.asarray(v, dtype=float), p)) if len(v) else None
 
 
-SUBST_KERNELS = {"chain": "k_solve_chain", "chain2": "k_solve_chain2", "perline": "k_solve_line"}
+SUBST_KERNELS = {"chain": "k_solve_chain", "chain2": "k_solve_chain2", "perline": "k_solve_line",
+                 "mma": "k_solve_mma"}
 
 
 def recorded_traffic(kernel_variant):

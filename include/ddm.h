@@ -289,8 +289,15 @@ int ddm_profile_read(ddm_handle *h, ddm_profile *out);
  *      every block's columns and exchanging partial sums with its partner
  *      once per block (block size <= 256, all 4 nsub workgroups resident:
  *      at most 64 subdomains on a 256-CU MI355X, RHS in tiles of up to 4):
- *      for problems with fewer chains than CUs. */
-enum { DDM_SOLVE_PERLINE = 0, DDM_SOLVE_CHAIN = 1, DDM_SOLVE_CHAIN2 = 2, DDM_SOLVE_NVARIANTS = 3 };
+ *      for problems with fewer chains than CUs;
+ *   3  one workgroup per chain as in 1, one wave per 16-row tile of every
+ *      block, the products W_l V on the matrix cores (MFMA 16x16x4, f32 for
+ *      DDM_MIXED, f64 for DDM_FP64) for tiles of 16 right-hand sides (fewer
+ *      are padded with zeros): each inverse is read once per sweep and 16
+ *      RHS.  The inverses are stored in this kernel's operand order, so
+ *      selecting it (or leaving it) re-runs the factorisation of a factored
+ *      handle.  Block size <= 256; default when nrhs_max >= 8. */
+enum { DDM_SOLVE_PERLINE = 0, DDM_SOLVE_CHAIN = 1, DDM_SOLVE_CHAIN2 = 2, DDM_SOLVE_MMA = 3, DDM_SOLVE_NVARIANTS = 4 };
 
 /* Factor layout: twisted != 0 eliminates every subdomain from both ends
  * towards a middle block (two chains per subdomain), 0 from the first block
@@ -299,14 +306,17 @@ enum { DDM_SOLVE_PERLINE = 0, DDM_SOLVE_CHAIN = 1, DDM_SOLVE_CHAIN2 = 2, DDM_SOL
  * discards the factors (call ddm_factor again). */
 int ddm_set_factor_layout(ddm_handle *h, int twisted);
 
-/* Select a variant; DDM_EINVAL if it does not apply to this problem. */
+/* Select a variant; DDM_EINVAL if it does not apply to this problem.  A
+ * switch to or from DDM_SOLVE_MMA re-factorises a factored handle (its
+ * status is returned: DDM_ESINGULAR etc.). */
 int ddm_set_solve_variant(ddm_handle *h, int variant);
 
 /* Currently selected variant. */
 int ddm_get_solve_variant(const ddm_handle *h);
 
 /* Time every applicable variant on nrhs right-hand sides (reps local solves
- * each, after one warm-up) and keep the fastest.  times_ms (host, may be
+ * each, after one warm-up) and keep the fastest (re-factorising when the
+ * layout of the inverses changes, see DDM_SOLVE_MMA).  times_ms (host, may be
  * NULL, DDM_SOLVE_NVARIANTS entries) receives the mean time per local solve,
  * -1 for variants that do not apply or could not be launched. */
 int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms);

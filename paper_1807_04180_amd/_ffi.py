@@ -37,7 +37,7 @@ class DdmProfile(ctypes.Structure):
 
 
 KERNEL_CLASSES = ("substitution", "transfer", "assembly", "residual")
-SOLVE_VARIANTS = ("perline", "chain", "chain2")
+SOLVE_VARIANTS = ("perline", "chain", "chain2", "mma")
 TRANSFER_FORMS = ("direct", "phi")   # DDM_TRANSFER_DIRECT, DDM_TRANSFER_PHI
 
 _lib = None

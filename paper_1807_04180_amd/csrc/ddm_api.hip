@@ -640,6 +640,7 @@ int ddm_profile_read(ddm_handle *h, ddm_profile *out) {
 // the plan admits them; else one workgroup per chain (its 8 / 16-RHS tiles
 // stream every inverse once for up to 16 RHS); else the per-line launches.
 static int default_variant(const ddm_handle *h) {
+    if (h->nrhs_max >= kMmaMinRhs && solve_variant_ok(h->plan, kSolveMma)) return kSolveMma;
     if (h->nrhs_max <= 4 && h->plan.bs_max >= 128 && h->d_xbuf && solve_variant_ok(h->plan, kSolveChain2))
         return kSolveChain2;
     return solve_variant_ok(h->plan, kSolveChain) ? kSolveChain : kSolvePerLine;
@@ -652,13 +653,25 @@ static void drop_step_graphs(ddm_handle *h) {
         if (h->step_graph[k]) { (void)hipGraphExecDestroy(h->step_graph[k]); h->step_graph[k] = nullptr; }
 }
 
+// Select a substitution variant.  The matrix-core variant reads the inverses
+// in its own operand order: switching to or from it re-runs the
+// factorisation in the other order (when the handle was factored).
+static int select_variant(ddm_handle *h, int variant) {
+    if (variant != h->solve_variant) drop_step_graphs(h);
+    h->solve_variant = variant;
+    const bool mma = variant == kSolveMma;
+    if (mma == h->plan.mma) return DDM_OK;
+    h->plan.mma = mma;
+    if (!h->factored) return DDM_OK;
+    h->factored = false;
+    return ddm_factor(h);
+}
+
 int ddm_set_solve_variant(ddm_handle *h, int variant) {
     if (!h) return DDM_EINVAL;
     if (variant < 0 || variant >= kSolveNVariants || !solve_variant_ok(h->plan, variant))
         return fail(h, DDM_EINVAL, "substitution variant does not apply to this problem");
-    if (variant != h->solve_variant) drop_step_graphs(h);
-    h->solve_variant = variant;
-    return DDM_OK;
+    return select_variant(h, variant);
 }
 
 int ddm_set_transfer_form(ddm_handle *h, int form) {
@@ -692,6 +705,7 @@ int ddm_set_factor_layout(ddm_handle *h, int twisted) {
     for (int k = 0; k < 4; ++k)
         if (h->step_graph[k]) { (void)hipGraphExecDestroy(h->step_graph[k]); h->step_graph[k] = nullptr; }
     if (!solve_variant_ok(h->plan, h->solve_variant)) h->solve_variant = default_variant(h);
+    h->plan.mma = h->solve_variant == kSolveMma;
     return DDM_OK;
 }
 
@@ -726,10 +740,20 @@ int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms) {
         HIPCHK(hipEventCreate(&e1));
         size_t es = elem_size(h->mixed);
         HIPCHK(launch_fill_zero(h->d_g, (long long)nrhs * P.etot * es, h->stream));
-        for (int v = 0; v < kSolveNVariants; ++v) {
+        // the variants that read the current layout of the inverses first,
+        // then the others (one re-factorisation between the two groups)
+        std::vector<int> order;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int v = 0; v < kSolveNVariants; ++v)
+                if (((v == kSolveMma) == h->plan.mma) == (pass == 0)) order.push_back(v);
+        for (int v : order) {
             if (times_ms) times_ms[v] = -1.0;
             if (!solve_variant_ok(P, v)) continue;
-            h->solve_variant = v;
+            int sv = select_variant(h, v);
+            if (sv != DDM_OK) {
+                (void)select_variant(h, keep);
+                return sv;
+            }
             hipError_t e = h->mixed ? launch_local_solve<float2>(h, (const float2 *)h->d_g, (float2 *)h->d_ring[0], nrhs)
                                     : launch_local_solve<double2>(h, (const double2 *)h->d_g, (double2 *)h->d_ring[0], nrhs);
             if (e != hipSuccess) { (void)hipGetLastError(); continue; }
@@ -751,11 +775,11 @@ int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms) {
     } catch (const HipFail &e) {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        h->solve_variant = keep;
-        return hip_fail(h, e);
+        int r = hip_fail(h, e);
+        (void)select_variant(h, keep);
+        return r;
     }
-    h->solve_variant = best >= 0 ? best : kSolvePerLine;
-    return DDM_OK;
+    return select_variant(h, best >= 0 ? best : keep);
 }
 
 // ---------------------------------------------------------------------------
@@ -1037,6 +1061,7 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
             return fail(nullptr, DDM_EHIP, buf);
         }
         h->solve_variant = default_variant(h);
+        h->plan.mma = h->solve_variant == kSolveMma;
         HIPCHK(hipHostMalloc((void **)&h->h_norm, 4 * nrhs_max * sizeof(double), hipHostMallocDefault));
         std::vector<int> ones(nrhs_max, 1);
         HIPCHK(hipMemcpy(h->d_active, ones.data(), nrhs_max * sizeof(int), hipMemcpyHostToDevice));

@@ -36,6 +36,7 @@
 
 #include "cplx.h"
 #include "ddm_internal.h"
+#include "ddm_mma.h"
 
 namespace ddm {
 
@@ -855,7 +856,8 @@ template <typename T2>
 __global__ __launch_bounds__(kEThreads) void k_factor_store(const SubDesc *__restrict__ subs,
                                                             const Coef *__restrict__ coef,
                                                             const double *__restrict__ k2, FactArgs A, FactWs w,
-                                                            int s, int mid, int groups, T2 *__restrict__ W) {
+                                                            int s, int mid, int groups, int mma,
+                                                            T2 *__restrict__ W) {
     const int c = blockIdx.x / groups, grp = blockIdx.x % groups;
     const ChainPos q = chain_pos(subs, c, s, mid != 0);
     if (!q.active) return;
@@ -865,7 +867,9 @@ __global__ __launch_bounds__(kEThreads) void k_factor_store(const SubDesc *__res
     double2 *Mn = chain_M(w, c, q.cur ^ 1);
     const int *ppos = w.ppos + (long long)c * w.bsp, *piv = w.piv + (long long)c * w.bsp;
     const int ld = sd.ld;
-    T2 *Wl = W + sd.foff + (long long)q.l * bs * ld;
+    // column-major with stride ld, or the matrix-core operand order (blocks
+    // of bs x mpad)
+    T2 *Wl = W + sd.foff + (long long)q.l * bs * (mma ? sd.mpad : ld);
     const bool next = !mid && !q.last;
     const int ln = q.dir == 0 ? q.l + 1 : q.l - 1;
     Coef cln = coef[sd.coff[ax] + (next ? ln : q.l)];
@@ -876,8 +880,15 @@ __global__ __launch_bounds__(kEThreads) void k_factor_store(const SubDesc *__res
     for (long long e = (long long)grp * kEThreads + threadIdx.x; e < n2; e += (long long)groups * kEThreads) {
         const int i = (int)(e % bs), j = (int)(e / bs);
         const double2 v = N[(long long)ppos[j] * bs + piv[i]];
-        Wl[(long long)j * ld + i] = from_d2<T2>(v);
-        if (ld > bs && i == bs - 1) Wl[(long long)j * ld + bs] = czero<T2>();  // padding row
+        if (mma) {
+            mma_store<T2>(Wl, bs, sd.mpad, i, j, from_d2<T2>(v));
+            // padding columns of the last group: zeros
+            if (j == bs - 1)
+                for (int jp = bs; jp < sd.mpad; ++jp) mma_store<T2>(Wl, bs, sd.mpad, i, jp, czero<T2>());
+        } else {
+            Wl[(long long)j * ld + i] = from_d2<T2>(v);
+            if (ld > bs && i == bs - 1) Wl[(long long)j * ld + bs] = czero<T2>();  // padding row
+        }
         if (!mid) {
             const double2 mv = next ? csub(block_entry(sd, coef, k2, A, ln, i, j, cln), cmul(cc, v)) : v;
             Mn[e] = mv;
@@ -961,7 +972,7 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
             k_factor_update<<<nc * tpd * tpd, kUThreads, 0, h->stream>>>(h->d_subs, w, ss, p, mid, tpd);
         }
         k_factor_store<T><<<nc * groups, kEThreads, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, w, ss, mid,
-                                                                    groups, (T *)h->d_W);
+                                                                    groups, P.mma ? 1 : 0, (T *)h->d_W);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -26,6 +26,9 @@ struct SubDesc {
     int bs;                // block size (n[0] in 2D, n[0]*n[1] in 3D)
     int ld;                // column stride of the stored block inverses: bs, or bs + 1 for
                            // odd complex64 blocks (16-byte aligned pairs of rows)
+    int mpad;              // matrix-core layout of the inverses: columns rounded up to a
+                           // whole operand group (8 for complex64, 4 for complex128);
+                           // 0 where that layout does not apply (bs > 256)
     long long foff;        // factor offset (elements)
     int coff[3];           // offsets of this box's per-axis coefficient tables
     int nbr[26];           // neighbour ids for the 26 offsets (-1: none)
@@ -78,6 +81,8 @@ struct Plan {
     std::vector<double> btab;   // side cut-off factor b(m), m = 0 .. n_ov
     std::vector<SolveItem> items;
     bool twisted = false;           // factor layout: both-ends elimination
+    bool mma = false;               // inverses stored in matrix-core operand order (else column-major)
+    int mpad_max = 0;               // largest SubDesc.mpad
     int ncu = 256;                  // compute units of the device: co-residency bound of the chain launches
     std::vector<double> w_el_by_l;  // sum over subdomains with > l blocks of bs^2
     std::vector<double> v_el_by_l;  // same, of bs
@@ -205,8 +210,19 @@ template <typename T>
 hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs);
 
 // substitution variants
-enum { kSolvePerLine = 0, kSolveChain = 1, kSolveChain2 = 2, kSolveNVariants = 3 };
+enum { kSolvePerLine = 0, kSolveChain = 1, kSolveChain2 = 2, kSolveMma = 3, kSolveNVariants = 4 };
+// the matrix-core substitution reads the inverses in its own operand order:
+// a handle's stored layout follows its variant (P.mma == (variant == kSolveMma))
+constexpr int kMmaMaxBs = 256;
 bool solve_variant_ok(const Plan &P, int variant);
+// matrix-core substitution (ddm_solve_mma.hip): applies to blocks of at most
+// kMmaMaxBs unknowns (and, two-ended, one resident workgroup per chain);
+// needs the inverses in its operand order (P.mma)
+bool mma_fits(const Plan &P);
+template <typename T2>
+hipError_t run_mma(ddm_handle *h, const T2 *g, T2 *x, int nrhs);
+// right-hand sides per handle from which the matrix-core substitution is the default
+constexpr int kMmaMinRhs = 8;
 
 // XCDs of the chip: workgroups are placed on them round-robin by index
 constexpr int kXcds = 8;

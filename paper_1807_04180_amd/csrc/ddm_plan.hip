@@ -13,6 +13,7 @@
 //    Sec. 2.2 requires.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -151,8 +152,16 @@ int build_plan(const ddm_problem *p, Plan *plan, std::string *err) {
         s.nb = s.n[p->dim - 1];
         s.bs = (int)(cnt / s.nb);
         s.ld = (p->precision == DDM_MIXED && (s.bs & 1)) ? s.bs + 1 : s.bs;
+        {
+            const int grp = p->precision == DDM_MIXED ? 8 : 4;
+            s.mpad = s.bs <= kMmaMaxBs ? (s.bs + grp - 1) / grp * grp : 0;
+        }
         s.foff = foff;
-        foff += (long long)s.nb * s.bs * s.ld;
+        // room for either layout of the inverses (column-major with stride ld,
+        // or the matrix-core order with mpad columns), so the substitution
+        // variant can change without a new allocation
+        foff += (long long)s.nb * s.bs * std::max(s.ld, s.mpad);
+        if (s.mpad > P.mpad_max) P.mpad_max = s.mpad;
         if (s.bs > P.bs_max) P.bs_max = s.bs;
         if (s.nb > P.nb_max) P.nb_max = s.nb;
         for (int d = 0; d < 3; ++d) {

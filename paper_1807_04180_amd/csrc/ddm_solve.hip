@@ -15,6 +15,7 @@
 
 #include "cplx.h"
 #include "ddm_internal.h"
+#include "ddm_sync.h"
 
 namespace ddm {
 
@@ -138,53 +139,6 @@ __global__ __launch_bounds__(kSThreads) void k_solve_line(const SubDesc *__restr
 constexpr int kCThreads = 1024;
 constexpr int kCWaves = 16;
 constexpr size_t kLdsMax = 160 * 1024;  // LDS per workgroup on gfx950
-
-// Meetings of workgroups without cache maintenance: an agent-scope fence on
-// this chip writes back and invalidates the whole L2 (at one exchange per
-// block and 256 workgroups that costs more than the block itself; at the one
-// meeting per launch of the two chains of a subdomain it cost 0.19 ms of a
-// 2.46 ms split local solve).  The exchanged words and the flags are instead
-// relaxed agent-scope atomics (coherent at the agent level without touching
-// other cached data); the writer waits for its stores to complete (s_waitcnt
-// 0: stores count in vmcnt here) before a barrier and the flag store, and
-// the reader loads the words only after it has seen the flag (and a
-// barrier).  Every wait is bounded (spin_limit) and stops at once after a
-// sticky abort.
-__device__ inline void wait_flag_relaxed(int *f, int target, int *abort_flag, int spin_limit) {
-    if (threadIdx.x == 0) {
-        int spins = 0;
-        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins >= spin_limit) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-        }
-    }
-    __syncthreads();
-}
-
-__device__ inline void xstore(double2 *p, double2 v) {
-    unsigned long long *q = (unsigned long long *)p;
-    __hip_atomic_store(q, __double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(q + 1, __double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void xstore(float2 *p, float2 v) {
-    const unsigned long long w = (unsigned long long)__float_as_uint(v.x) |
-                                 ((unsigned long long)__float_as_uint(v.y) << 32);
-    __hip_atomic_store((unsigned long long *)p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double2 xload(double2 *p) {
-    unsigned long long *q = (unsigned long long *)p;
-    return make_double2(__longlong_as_double(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
-                        __longlong_as_double(__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-}
-__device__ inline float2 xload(float2 *p) {
-    const unsigned long long w =
-        __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return make_float2(__uint_as_float((unsigned)w), __uint_as_float((unsigned)(w >> 32)));
-}
 
 // Rows per lane: complex64 lanes take two consecutive rows so that every
 // load is 16 bytes (8-byte lane loads stream at about 60% of the per-CU
@@ -983,6 +937,7 @@ bool solve_variant_ok(const Plan &P, int variant) {
         case kSolvePerLine: return !P.twisted;
         case kSolveChain: return P.bs_max <= 256;
         case kSolveChain2: return P.twisted && chain2_fits(P);  // one workgroup per CU
+        case kSolveMma: return mma_fits(P);
         default: return false;
     }
 }
@@ -990,6 +945,9 @@ bool solve_variant_ok(const Plan &P, int variant) {
 // g and x must not alias (the substitution reads g_l while x_l is written).
 template <typename T>
 hipError_t launch_local_solve(ddm_handle *h, const T *g, T *x, int nrhs) {
+    // the stored inverses are in the matrix-core order exactly when that
+    // variant is selected
+    if (h->plan.mma) return run_mma<T>(h, g, x, nrhs);
     int v = h->solve_variant;
     if (!solve_variant_ok(h->plan, v)) v = solve_variant_ok(h->plan, kSolveChain) ? kSolveChain : kSolvePerLine;
     if (v == kSolveChain2 && h->d_xbuf) return run_chain2_rt<T>(h, g, x, nrhs);

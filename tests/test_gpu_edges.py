@@ -148,9 +148,12 @@ def test_beyond_full_grid_uses_one_workgroup_per_chain():
 
 def test_default_variant_choice():
     """Defaults: split chains for at most 4 RHS on blocks of >= 128 unknowns,
-    one workgroup per chain for small blocks or more RHS."""
+    one workgroup per chain for small blocks and 5-7 RHS, the matrix-core
+    kernel from 8 RHS on."""
     cases = [(di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4, nrhs=1), 2, "chain2"),
-             (di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4, nrhs=1), 8, "chain"),
+             (di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4, nrhs=1), 6, "chain"),
+             (di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4, nrhs=1), 8, "mma"),
+             (di.small_2d(M=64, N=(2, 2), n_pml=4, n_ov=3, nrhs=1), 16, "mma"),
              (di.small_2d(M=64, N=(2, 2), n_pml=4, n_ov=3, nrhs=1), 2, "chain")]
     for w, nrhs_max, want in cases:
         o, g = _pair(w, nrhs_max)

@@ -4,8 +4,9 @@ oracle through the C-ABI:
 * the one-directional factor layout (every subdomain eliminated from its
   first block on, as with more subdomains than the twisted layout can keep
   co-resident, e.g. 16 x 16) with 16 and 20 right-hand sides: the 16-RHS
-  substitution tiles (and a ragged second tile of 4) in FP64 and complex64,
-  local solves and six DDM steps (Algorithm 3.1);
+  substitution tiles (and a ragged second tile of 4) of the vector chain
+  kernel and of the matrix-core kernel, in FP64 and complex64, local solves
+  and six DDM steps (Algorithm 3.1);
 * FGMRES(30) preconditioned by K DDM steps (Sec. 4.2.2) in 3D and with
   K = 1 and K = 2, FP64 and mixed, against the oracle's global solve, with
   n_Local_Solve = K n_GMRES_Iter (the identity of Tables 5 and 6).
@@ -56,15 +57,17 @@ ONEDIR = {
 }
 
 
+@pytest.mark.parametrize("variant", ["chain", "mma"])
 @pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("case", sorted(ONEDIR))
-def test_onedir_16_and_20_rhs(case, mixed):
+def test_onedir_16_and_20_rhs(case, mixed, variant):
     w = ONEDIR[case](20)
     o, g = _pair(w, 20, mixed=mixed)
     tol = 5e-5 if mixed else 1e-10
     try:
         g.set_factor_layout(False)
-        assert g.solve_variant() == "chain", g.solve_variant()
+        assert g.solve_variant() == "mma", g.solve_variant()   # the default from 8 RHS on
+        g.set_solve_variant(variant)
         for nrhs in (16, 20):
             gin = di.random_field((nrhs, o.etot), seed=300 + nrhs)
             xg = _n(g.local_solve(_t(gin)))
@@ -113,5 +116,77 @@ def test_fgmres_small_K(K, mixed):
         assert all(i["local_solves"] == K * i["iters"] for i in info), info
         # fewer DDM steps per application need more Arnoldi steps
         assert all(i["iters"] > 2 for i in info), info
+    finally:
+        g.close()
+
+
+# the matrix-core substitution: block sizes 1-3 row tiles of 16 with ragged
+# last tiles and odd and even widths (column groups of 8 / 4 with padding);
+# 3D planes of 49-100 unknowns; both layouts
+MMA_CASES = {
+    "2d-3x3-layered": lambda n: di.small_2d(M=192, N=(3, 3), n_pml=7, n_ov=5, nrhs=n, layered=True, seed=4),
+    "2d-2x2-small": lambda n: di.small_2d(M=40, N=(2, 2), n_pml=3, n_ov=2, nrhs=n, seed=7),
+    "3d-2x2x2": lambda n: di.small_3d(M=16, N=(2, 2, 2), n_pml=3, n_ov=2, nrhs=n, seed=1),
+}
+
+
+@pytest.mark.parametrize("twisted", [True, False])
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("case", sorted(MMA_CASES))
+def test_mma_substitution(case, mixed, twisted):
+    w = MMA_CASES[case](20)
+    o, g = _pair(w, 20, mixed=mixed)
+    tol = 5e-5 if mixed else 1e-10
+    try:
+        g.set_factor_layout(twisted)
+        g.set_solve_variant("mma")
+        for nrhs in (1, 5, 16, 20):
+            gin = di.random_field((nrhs, o.etot), seed=400 + nrhs)
+            xg = _n(g.local_solve(_t(gin)))
+            assert relerr(xg, o.local_solve(gin), axis=1) < tol, nrhs
+            assert np.array_equal(_n(g.local_solve(_t(gin))), xg), nrhs
+            # a right-hand side gives the same bits alone and in any position
+            assert np.array_equal(_n(g.local_solve(_t(gin[-1:])))[0], xg[-1]), nrhs
+        f = w.f[:16]
+        uo, _ = o.ddm_run(f, 6)
+        ug, _ = g.iterate(_t(f.reshape(16, -1)), 6)
+        assert relerr(_n(ug), uo.reshape(16, -1), axis=1) < tol
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_mma_largest_blocks(mixed):
+    """Blocks of 255 and 256 unknowns (16 row tiles: 1024-thread workgroups,
+    the widest the kernel takes) against the oracle, and a switch back to the
+    vector kernel (the factorisation re-runs in column-major order)."""
+    w = di.small_2d(M=474, N=(2, 2), n_pml=8, n_ov=4, nrhs=1)
+    o, g = _pair(w, 16, mixed=mixed)
+    tol = 5e-5 if mixed else 1e-10
+    try:
+        assert g.solve_variant() == "mma"
+        gin = di.random_field((16, o.etot), seed=410)
+        xo = o.local_solve(gin)
+        assert relerr(_n(g.local_solve(_t(gin))), xo, axis=1) < tol
+        g.set_solve_variant("chain")
+        assert relerr(_n(g.local_solve(_t(gin))), xo, axis=1) < tol
+        g.set_solve_variant("mma")
+        assert relerr(_n(g.local_solve(_t(gin))), xo, axis=1) < tol
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_mma_stationary_and_fgmres(mixed):
+    w = di.small_2d(M=192, N=(3, 3), n_pml=7, n_ov=5, nrhs=8, layered=True, seed=4)
+    o, g = _pair(w, 8, mixed=mixed)
+    try:
+        assert g.solve_variant() == "mma"
+        uref = o.global_solve(w.f).reshape(8, -1)
+        f = _t(w.f.reshape(8, -1))
+        for method in ("stationary", "fgmres"):
+            u, info, st = g.solve(f, method=method, tol=1e-10, maxiter=400)
+            assert st == 0, (method, info)
+            assert relerr(_n(u), uref, axis=1) < (1e-7 if mixed else 1e-8), method
     finally:
         g.close()

@@ -168,7 +168,7 @@ def test_deterministic_bitwise(pair):
     assert torch.equal(u1, u2) and r1 == r2
 
 
-LAYOUTS = {"twisted": (True, ["chain", "chain2"]), "onedir": (False, ["perline", "chain"])}
+LAYOUTS = {"twisted": (True, ["chain", "chain2", "mma"]), "onedir": (False, ["perline", "chain", "mma"])}
 
 
 @pytest.mark.parametrize("layout", sorted(LAYOUTS))
@@ -213,6 +213,7 @@ def test_iterate_layouts_match_oracle(pair, layout):
 def test_chain_mixed_matches_oracle():
     w = CASES["2d-3x3-layered"]()
     o, g = make_pair(w, nrhs_max=20, mixed=True)
+    g.set_solve_variant("chain")
     # block sizes (x extents) include odd ones: complex64 inverses are stored
     # with an even column stride and read two rows per lane
     bsz = [g.geometry(a)["ext_hi"][0] - g.geometry(a)["ext_lo"][0] + 1 for a in range(9)]
@@ -233,6 +234,7 @@ def test_chain_16_rhs_tiles_fp64(case):
     w = CASES[case]() if case in CASES else di.small_2d(M=256, N=(2, 2), n_pml=8, n_ov=4, nrhs=1)
     o, g = make_pair(w, nrhs_max=20)
     try:
+        g.set_solve_variant("chain")
         assert g.solve_variant() == "chain"
         gin = di.random_field((16, o.etot), seed=54)
         x16 = _n(g.local_solve(_t(gin)))
