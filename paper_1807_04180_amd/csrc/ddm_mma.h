@@ -36,8 +36,17 @@ template <> struct Mma<double2> {
 constexpr int kMmaRhs = 16;    // RHS per tile
 constexpr int kMmaRing = 8;    // operand loads in flight per lane
 
-__device__ inline float shfl_xor1(float v) { return __shfl_xor(v, 1); }
-__device__ inline double shfl_xor1(double v) { return __shfl_xor(v, 1); }
+// the value of the neighbouring lane (lane ^ 1), by a DPP quad permutation
+// [1, 0, 3, 2] (no LDS crossbar)
+__device__ inline float shfl_xor1(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ inline double shfl_xor1(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 // Position of element (i, j) of a block's inverse in the matrix-core order
 // (T2 offset of its real part; the imaginary part is rows_t lanes further).

@@ -86,6 +86,9 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
         if (t == nf) return mid;
         return mid - dirf * (t - nf);
     };
+    // the block whose V step t forms (none at the last step, nor before the
+    // two-ended meeting, which forms its own)
+    auto lnv_of = [&](int t) { return (t + 1 < nsteps && !(twisted && t + 1 == nf)) ? step_l(t + 1) : -1; };
 
     // both V buffers start at zero: the padding columns [bs, mpad) stay zero
     for (int e = threadIdx.x; e < 2 * vcap * kMmaRhs; e += blockDim.x) vbuf[e] = czero<T2>();
@@ -106,6 +109,31 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
 #pragma unroll
             for (int u = 0; u < kMmaRing; ++u) ring[u] = *(const LT *)(b0 + (long long)(u < NG ? u : NG - 1) * grp_b);
         }
+
+        // per lane: its 4 rows x 2 RHS (one per half) of component p of
+        // g_lnv (forward) or of y_l (backward) for step st_, one load per
+        // entry whatever the step (clamped addresses, the value zeroed where
+        // unused).  The y block of the first backward step of the two-ended
+        // layout was stored by this same lane with an atomic store at the
+        // last forward step and has not been read through this CU's cache
+        // since: a plain load returns it.
+        R pre[2][4];
+        unsigned pok = 0;  // bit 4 hf + r: entry (hf, r) used (applied where it is read, so the
+                           // loads are not waited for where they are issued)
+#define DDM_MMA_PRE(st_)                                                                                  \
+    {                                                                                                     \
+        const int kd = (st_) < nf ? 0 : ((st_) == nf ? 1 : 2), lp = step_l(st_), ln = lnv_of(st_);        \
+        const R *psrc = (const R *)(kd == 2 ? x + (long long)lp * bs : g + (long long)(ln >= 0 ? ln : lp) * bs) + p; \
+        const bool puse = kd == 2 || (kd == 0 && ln >= 0);                                                \
+        _Pragma("unroll") for (int hf = 0; hf < 2; ++hf) _Pragma("unroll") for (int r = 0; r < 4; ++r) {  \
+            const int i = 16 * wv + M::row(lane, r), q = 8 * hf + qq;                                     \
+            const bool ok = puse && active && i < bs && q < nr;                                           \
+            const int ic = i < bs ? i : bs - 1, qc = q < nr ? q : nr - 1;                                 \
+            pre[hf][r] = psrc[2 * ((long long)(r0 + qc) * etot + off + ic)];                              \
+            pok = ok ? pok | (1u << (4 * hf + r)) : pok & ~(1u << (4 * hf + r));                          \
+        }                                                                                                 \
+    }
+        DDM_MMA_PRE(0)
 
         for (int st = 0; st < nsteps; ++st) {
             const int l = step_l(st);
@@ -142,25 +170,15 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
             }
             // the block index whose V this step forms (none before the
             // two-ended meeting, which forms its own)
-            const int lnv = (st + 1 < nsteps && !(twisted && st + 1 == nf)) ? step_l(st + 1) : -1;
-            // per lane: its 4 rows x 2 RHS (one per half), component p of
-            // g_lnv (forward) or of y_l (backward)
-            // (one load per entry whatever the step: clamped addresses, the
-            // value zeroed where unused; the y blocks of the backward sweep,
-            // the first of them stored by atomics, are read the same way)
-            R pre[2][4];
-            const T2 *psrc = kind == 2 ? x + (long long)l * bs : g + (long long)(lnv >= 0 ? lnv : l) * bs;
-            const bool puse = kind == 2 || (kind == 0 && lnv >= 0);
+            const int lnv = lnv_of(st);
+            // the g / y entries of this step were loaded at the end of the
+            // previous one: make sure they are in before the ring loads of
+            // this step pile up behind them (their wait is then not mixed up
+            // with the ring's)
 #pragma unroll
             for (int hf = 0; hf < 2; ++hf)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = 16 * wv + M::row(lane, r), q = 8 * hf + qq;
-                    const bool ok = puse && active && i < bs && q < nr;
-                    const int ic = i < bs ? i : bs - 1, qc = q < nr ? q : nr - 1;
-                    const T2 y = xload(const_cast<T2 *>(psrc) + (long long)(r0 + qc) * etot + off + ic);
-                    pre[hf][r] = ok ? (p ? y.y : y.x) : R(0);
-                }
+                for (int r = 0; r < 4; ++r) asm volatile("" ::"v"(pre[hf][r]));
             // ---- D = W_l V on the matrix cores ----
             Acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
             const R *vb = (const R *)vcur + boff;
@@ -202,7 +220,8 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
                 for (int r = 0; r < 4; ++r) {
                     const int i = 16 * wv + M::row(lane, r), q = 8 * hf + qq;
                     const R y = hf == 0 ? acc0[r] : acc1[r];
-                    const R res = kind == 2 ? pre[hf][r] - y : y;  // forward y_l, middle x_mid, backward x_l
+                    const R pv = (pok >> (4 * hf + r)) & 1u ? pre[hf][r] : R(0);
+                    const R res = kind == 2 ? pv - y : y;  // forward y_l, middle x_mid, backward x_l
                     const R oth = shfl_xor1(res);                  // the other part of the same entry
                     if (!(active && i < bs)) continue;
                     const double re = p ? (double)oth : (double)res, im = p ? (double)res : (double)oth;
@@ -215,7 +234,7 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
                         double v = 0.0;
                         if (q < nr) {
                             if (kind == 0) {  // g_lnv - cf y_l, rounded as cmsub_fixed
-                                const double gp = (double)pre[hf][r];
+                                const double gp = (double)pv;
                                 v = p ? fma(-cf.x, im, fma(-cf.y, re, gp)) : fma(-cf.x, re, fma(cf.y, im, gp));
                             } else {          // cf x_l, rounded as cmul_fixed
                                 v = p ? fma(cf.x, im, cf.y * re) : fma(cf.x, re, -(cf.y * im));
@@ -224,8 +243,11 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
                         ((R *)(vnext + i * kMmaRhs + q))[p] = (R)v;
                     }
                 }
+            // the next step's g / y entries, in flight over the barrier
+            if (st + 1 < nsteps) DDM_MMA_PRE(st + 1)
             __syncthreads();
         }
+#undef DDM_MMA_PRE
     }
 }
 
