@@ -1,26 +1,31 @@
 #!/usr/bin/env python3
 """Helmholtz solves/s of the additive overlapping DDM on one MI355X.
 
-Workload (one "step" = one batch solve): the 2D constant-medium problem on
-the unit square, 1024^2 interior cells (h = 1/1024, omega = 2 pi 102.4, 10
-points per wavelength), 5-point PML operator with a 16-cell PML (sigma0 for
-1e-6 reflection), 8x8 subdomains of 128^2 cells with 8-cell overlap, four
-seeded unit-mass Gaussian sources (std 2h); the batch of 4 right-hand sides is
-solved by the DDM as a stationary iteration to FP64 relative residual 1e-6 in
-complex128.  Factorisation happens once before the timed region (reported
-separately), as in the paper's timings.
+Headline workload (one "step" = one batch solve): the 2D layered medium on
+the unit square, 2048^2 interior cells (8 flat layers with velocities
+1.5-4.5 plus a 10% smoothed perturbation, 8 points per wavelength at the
+slowest velocity), 5-point PML operator with a 20-cell PML (sigma0 for 1e-6
+reflection), 16x16 subdomains of 128^2 cells with 8-cell overlap, 16 seeded
+unit-mass Gaussian sources (std 2h) solved together.  `value`: the mixed
+path as the workload states it -- block inverses and local solves in
+complex64, FGMRES(30) right-preconditioned by K = N1 + N2 DDM steps with the
+Krylov vectors, residual and assembly in FP64 -- to FP64 relative residual
+1e-6, counting only the right-hand sides that reached it.  The same solve in
+plain FP64 (complex128 everywhere) is timed beside it (`fp64`), with each
+result's difference to it, and both as stationary iterations.  The
+factorisation runs once before the timed region (reported separately), as in
+the paper's timings.  The 1024^2 constant-medium workload (8x8 subdomains,
+4 RHS) is measured briefly as a sub-record (`const_1024`).
 
-Also measured on the same workload (outside `value`): the DDM as FGMRES(30)
-preconditioner (K = N1 + N2 = 16 steps) in FP64, and the mixed path
-(complex64 factors / local solves / transfers, FP64 residual, assembly and
-refinement), with each result's error against the FP64 solution.
-
-`roofline` is for the dominant kernel, the block substitution, from a live
-pass with HIP events around every substitution launch on the library's
-stream: algorithmic bytes (every stored block inverse read once per sweep,
-plus the block vectors) / summed launch time.  `cpu_baseline` runs the CPU
-oracle (unchanged) on a 4x4-subdomain cut of the same workload and scales the
-per-step time to the 64 subdomains and the step count of the full solve.
+`roofline` is for the dominant kernel of `value`, the complex64 block
+substitution, from a live pass with HIP events around every substitution
+launch on the library's stream: algorithmic bytes (every stored block
+inverse read once per sweep, plus the block vectors) / summed launch time;
+`traffic` is the HBM traffic per launch from the committed rocprofv3 counter
+record of the same kernel source.  `cpu_baseline` runs the CPU oracle
+(unchanged, FP64) on a 4x4-subdomain cut of the same medium and scales its
+per-step time to the 256 subdomains and to the local-solve steps of the
+measured solve.
 """
 import argparse
 import json
@@ -71,20 +76,33 @@ SUBST_KERNELS = {"chain": "k_solve_chain", "chain2": "k_solve_chain2", "perline"
                  "mma": "k_solve_mma"}
 
 
-def recorded_traffic(kernel_variant):
-    """HBM traffic per launch of the substitution kernel from the committed
-    rocprofv3 counter summary, only if the kernel source is unchanged since."""
+# kernel sources whose hash a counter record of the variant is valid for
+SUBST_SOURCES = {"mma": ["ddm_solve_mma.hip", "ddm_mma.h", "ddm_sync.h"]}
+
+
+def kernel_sha(kernel_variant):
     import hashlib
+    hsh = hashlib.sha256()
+    for f in SUBST_SOURCES.get(kernel_variant, ["ddm_solve.hip", "ddm_sync.h"]):
+        with open(os.path.join(ROOT, "paper_1807_04180_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def recorded_traffic(kernel_variant, tag, profiles_dir=None):
+    """HBM traffic per launch of the substitution kernel from the committed
+    rocprofv3 counter record profiles/<kernel>_<tag>_traffic.json, only if the
+    kernel source is unchanged since the counters were taken."""
     name = SUBST_KERNELS.get(kernel_variant)
-    path = os.path.join(ROOT, "profiles", "%s_2d1024_traffic.json" % name)
-    src = os.path.join(ROOT, "paper_1807_04180_amd", "csrc", "ddm_solve.hip")
-    if name is None or not os.path.exists(path):
+    if name is None:
+        return None
+    path = os.path.join(profiles_dir or os.path.join(ROOT, "profiles"), "%s_%s_traffic.json" % (name, tag))
+    if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    with open(src, "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != rec.get("source_sha256"):
-            return None
+    if rec.get("source_sha256") != kernel_sha(kernel_variant):
+        return None
     return rec["traffic_bytes_per_launch"]
 
 
@@ -120,6 +138,274 @@ def run_cpu_baseline(nrhs_full, nsub_full, steps_full, tol):
                    % (w.nrhs, t_fac, nsteps, t_run, t_step, conv, scale, nsub_full, steps_full)),
         "factor_s_sample": t_fac, "step_s_sample": t_step,
     }
+
+
+def run_cpu_baseline_layered(nrhs_full, nsub_full, local_steps_full):
+    """Oracle on the 4x4-subdomain cut of the layered 2048^2 medium (same h,
+    omega, PML, overlap and 128^2 cores, 16 RHS): per-step time (one local
+    solve of every subdomain for every RHS, plus transfers and assembly)
+    scaled by the subdomain count and by the local-solve steps of the full
+    solve."""
+    import ddm_inputs as di
+    from oracle import Oracle
+
+    w = di.layered_2d_2048_cut(4, nrhs=nrhs_full)
+    o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
+    t0 = time.perf_counter()
+    o.factor()
+    t_fac = time.perf_counter() - t0
+    nsteps = 3
+    t0 = time.perf_counter()
+    o.ddm_run(w.f, nsteps)
+    t_run = time.perf_counter() - t0
+    t_step = t_run / nsteps
+    scale = nsub_full / o.nsub
+    value = nrhs_full / (t_step * scale * local_steps_full)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": value, "unit": "solves/s", "cores": threads, "kind": "oracle",
+        "sample": ("oracle (FP64 banded-LU local solves, OpenMP) on the 4x4-subdomain cut of the layered 2048^2 "
+                   "medium around its centre (M=512, same h, omega, PML 20, overlap 8, 128^2 cores, %d seeded "
+                   "Gaussians): factor %.2f s, %d DDM steps in %.2f s (%.3f s/step); per-step time scaled x%.0f to "
+                   "the %d subdomains and x%d local-solve steps of the measured solve"
+                   % (w.nrhs, t_fac, nsteps, t_run, t_step, scale, nsub_full, local_steps_full)),
+        "factor_s_sample": t_fac, "step_s_sample": t_step,
+    }
+
+
+def _rel(a, b):
+    import torch
+    return (torch.linalg.vector_norm(a - b, dim=1) / torch.linalg.vector_norm(b, dim=1)).tolist()
+
+
+def _timed_solves(s, f, reps, warmup, **kw):
+    """warmup + reps batch solves; per-rep wall time, per-RHS info of the
+    last, the solution (u of the last)."""
+    import torch
+    u = torch.empty_like(f)
+    for _ in range(warmup):
+        s.solve(f, u=u, **kw)
+    torch.cuda.synchronize()
+    times, lat, info, st = [], [], None, 0
+    conv = 0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, info, st = s.solve(f, u=u, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        lat += [x["seconds"] * 1e3 for x in info]
+        conv += sum(1 for x in info if x["status"] == "OK")
+    return u, info, st, times, lat, conv
+
+
+def _roofline(s, f, **kw):
+    """live event-profiled solve: the substitution kernel's achieved bytes/s"""
+    import torch
+    s.profile_enable(True)
+    s.solve(f, u=torch.empty_like(f), **kw)
+    prof = s.profile_read()
+    s.profile_enable(False)
+    sub = prof["substitution"]
+    achieved = sub["bytes"] / (sub["ms"] * 1e-3) / 1e9 if sub["ms"] > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": SUBST_KERNELS[s.solve_variant()], "avg_launch_us": sub["ms"] / max(sub["launches"], 1) * 1e3,
+            "launches": sub["launches"], "bytes_per_launch": sub["bytes"] / max(sub["launches"], 1)}, prof
+
+
+def run_headline(args):
+    """The layered 2048^2, 16-RHS workload: mixed FGMRES (value) beside
+    plain FP64, stationary legs, the 1024^2 sub-record and the oracle."""
+    import numpy as np
+    import torch
+
+    import ddm_inputs as di
+    import paper_1807_04180_amd as ddm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = di.layered_2d_2048(nrhs=16)
+    nrhs = w.nrhs
+    tol = args.tol if args.tol is not None else 1e-6
+    K = int(sum(w.N))
+    log("bench: workload %s nglob=%d nrhs=%d on %s" % (w.name, int(np.prod(w.grid_shape)), nrhs,
+                                                        torch.cuda.get_device_name(0)))
+    k2 = torch.from_numpy(w.k2.reshape(-1)).to(dev)
+    f = torch.from_numpy(w.f.reshape(nrhs, -1)).to(dev)
+    fg = dict(method="fgmres", tol=tol, maxiter=200, restart=30, K=K)
+    stat = dict(method="stationary", tol=tol, maxiter=600)
+    side_reps = max(1, min(args.steps, 3))
+
+    # ---- mixed: complex64 inverses / local solves, FP64 Krylov ----------
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    smx = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=True), k2, nrhs, factor=False)
+    try:
+        smx.factor()
+        torch.cuda.synchronize()
+        t_fac_mx = time.perf_counter() - t0
+        log("bench: mixed setup+factor %.3f s (%.2f GB of complex64 block inverses), substitution %s"
+            % (t_fac_mx, smx.factor_bytes / 1e9, smx.solve_variant()))
+        if args.probe == "traffic":
+            g = torch.zeros((nrhs, smx.etot), dtype=torch.complex128, device=dev)
+            g[:, ::7] = 1.0
+            for _ in range(3):
+                smx.local_solve(g)
+            src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log("bench: traffic probe done (3 complex64 local solves, 1 GiB copy)")
+            return
+        umx, info_mx, st_mx, t_mx, lat_mx, conv_mx = _timed_solves(smx, f, args.steps, args.warmup, **fg)
+        roof_mx, prof_mx = _roofline(smx, f, **fg)
+        roof_mx["traffic"] = recorded_traffic(smx.solve_variant(), "layered2048_c64")
+        us_mx, info_smx, st_smx, t_smx, lat_smx, conv_smx = _timed_solves(smx, f, side_reps, 1, **stat)
+    finally:
+        smx.close()
+    torch.cuda.empty_cache()
+    t_timed = sum(t_mx)
+    value = conv_mx / t_timed
+    log("bench: mixed FGMRES(30)+DDM(K=%d): %.2f solves/s (%d of %d RHS converged), %.1f ms/batch, iters %s"
+        % (K, value, conv_mx, nrhs * args.steps, 1e3 * t_timed / args.steps, sorted({x["iters"] for x in info_mx})))
+
+    # ---- plain FP64 -------------------------------------------------------
+    t0 = time.perf_counter()
+    s64 = ddm.HelmholtzDDM(ddm.Problem.from_workload(w), k2, nrhs, factor=False)
+    try:
+        s64.factor()
+        torch.cuda.synchronize()
+        t_fac_64 = time.perf_counter() - t0
+        u64, info_64, st_64, t_64, lat_64, conv_64 = _timed_solves(s64, f, side_reps, 1, **fg)
+        roof_64, prof_64 = _roofline(s64, f, **fg)
+        us_64, info_s64, st_s64, t_s64, lat_s64, conv_s64 = _timed_solves(s64, f, side_reps, 1, **stat)
+    finally:
+        s64.close()
+    torch.cuda.empty_cache()
+    v64 = conv_64 / sum(t_64)
+    log("bench: FP64 FGMRES: %.2f solves/s; mixed x%.2f; substitution mixed %.0f GB/s, FP64 %.0f GB/s"
+        % (v64, value / v64, roof_mx["achieved"], roof_64["achieved"]))
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_timed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": ("2D layered medium, 2048^2 interior (8 layers 1.5-4.5 plus 10%% smoothed "
+                                "perturbation, 8 ppw at c=1.5), 5-point FD, PML 20 (R=1e-6), 16x16 subdomains of "
+                                "128^2, overlap 8, 16 seeded Gaussian sources (std 2h) in one batch; complex64 block "
+                                "inverses and local solves, FP64 FGMRES(30) + DDM(K=%d) to relres %.0e" % (K, tol)),
+                   "global_batch": nrhs, "grid": list(w.M), "subdomains": list(w.N), "method": "fgmres",
+                   "precision": "mixed"},
+        "latency_ms": {"p50": pct(lat_mx, 50), "p99": pct(lat_mx, 99)},
+        "converged": conv_mx, "solved": nrhs * args.steps,
+        "relres": [x["relres"] for x in info_mx], "gmres_iters": [x["iters"] for x in info_mx],
+        "local_solves": [x["local_solves"] for x in info_mx], "status": st_mx,
+        "rel_diff_vs_fp64": _rel(umx, u64), "factor_s": t_fac_mx,
+        "roofline": roof_mx,
+        "kernel_time_ms_per_solve_batch": {k: v["ms"] for k, v in prof_mx.items()},
+        "kernel_achieved_GBs": {k: (v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None)
+                                for k, v in prof_mx.items()},
+        "fp64": {"solves_per_s": v64, "ms_per_batch": sum(t_64) / side_reps * 1e3, "converged": conv_64,
+                 "gmres_iters": [x["iters"] for x in info_64], "relres": [x["relres"] for x in info_64],
+                 "status": st_64, "factor_s": t_fac_64, "mixed_speedup": value / v64, "roofline": roof_64},
+        "stationary": {
+            "mixed": {"solves_per_s": conv_smx / sum(t_smx), "steps": [x["iters"] for x in info_smx],
+                      "relres": [x["relres"] for x in info_smx], "status": st_smx,
+                      "rel_diff_vs_fp64": _rel(us_mx, u64)},
+            "fp64": {"solves_per_s": conv_s64 / sum(t_s64), "steps": [x["iters"] for x in info_s64],
+                     "relres": [x["relres"] for x in info_s64], "status": st_s64,
+                     "rel_diff_vs_fp64_fgmres": _rel(us_64, u64)},
+        },
+    }
+    log("bench: stationary: mixed %.2f, FP64 %.2f solves/s" % (out["stationary"]["mixed"]["solves_per_s"],
+                                                              out["stationary"]["fp64"]["solves_per_s"]))
+    if not args.no_extras:
+        out["const_1024"] = run_const_1024_brief(side_reps)
+    if not args.no_cpu_baseline:
+        log("bench: CPU baseline (oracle) ...")
+        local_steps = max(x["local_solves"] for x in info_mx)
+        out["cpu_baseline"] = run_cpu_baseline_layered(nrhs, int(np.prod(w.N)), local_steps)
+        log("bench: CPU baseline %.5f solves/s" % out["cpu_baseline"]["value"])
+    print(json.dumps(out), flush=True)
+
+
+def run_const_1024_brief(reps):
+    """the 1024^2 constant-medium workload (8x8, 4 RHS), stationary DDM to
+    1e-6: FP64 (split substitution) and mixed, a few batches each"""
+    import torch
+
+    import ddm_inputs as di
+    import paper_1807_04180_amd as ddm
+
+    dev = torch.device("cuda:0")
+    w = di.const_2d_1024(nrhs=4)
+    k2 = torch.from_numpy(w.k2.reshape(-1)).to(dev)
+    f = torch.from_numpy(w.f.reshape(w.nrhs, -1)).to(dev)
+    rec = {"workload": "2D constant medium, 1024^2, 8x8 subdomains of 128^2, overlap 8, PML 16, 4 Gaussians; "
+                       "stationary DDM to relres 1e-6"}
+    u64 = None
+    for mixed in (False, True):
+        s = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=mixed), k2, w.nrhs)
+        try:
+            u, info, st, times, lat, conv = _timed_solves(s, f, reps, 1, method="stationary", tol=1e-6, maxiter=400)
+            roof, _ = _roofline(s, f, method="stationary", tol=1e-6, maxiter=400)
+        finally:
+            s.close()
+        key = "mixed" if mixed else "fp64"
+        rec[key] = {"solves_per_s": conv / sum(times), "steps": [x["iters"] for x in info], "status": st,
+                    "substitution": {"kernel": roof["kernel"], "avg_launch_us": roof["avg_launch_us"],
+                                     "achieved_GBs": roof["achieved"], "frac": roof["frac"]}}
+        if mixed:
+            rec[key]["rel_diff_vs_fp64"] = _rel(u, u64)
+        else:
+            u64 = u
+        log("bench: 1024^2 %s: %.1f solves/s, substitution %.0f GB/s" % (key, rec[key]["solves_per_s"], roof["achieved"]))
+    torch.cuda.empty_cache()
+    return rec
+
+
+def make_traffic_record(fetch_dir, write_dir, tag, variant="mma", profiles_dir=None):
+    """profiles/<kernel>_<tag>_traffic.json from two rocprofv3 --pmc runs of
+    `bench.py --probe traffic` (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch): each counter is scaled by what it reads for the probe's 1 GiB
+    device copy (the largest copy dispatch of the run)."""
+    import csv
+    import glob
+
+    kname = SUBST_KERNELS[variant]
+
+    def read(d, counter):
+        rows = []
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    if r.get("Counter_Name") == counter:
+                        rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        per = {}
+        for did, name, v in rows:
+            per.setdefault(did, [name, 0.0])[1] += v
+        disp = sorted((did, nv[0], nv[1]) for did, nv in per.items())
+        sub = [v for _, n, v in disp if kname in n]
+        copies = [v for _, n, v in disp if "copy" in n.lower() and kname not in n]
+        if not sub or not copies:
+            raise SystemExit("no %s or copy dispatches with %s under %s" % (kname, counter, d))
+        return sub, max(copies)
+
+    fsub, fcopy = read(fetch_dir, "FETCH_SIZE")
+    wsub, wcopy = read(write_dir, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    fscale, wscale = gib_kib / fcopy, gib_kib / wcopy
+    fb = sum(fsub) / len(fsub) * 1024.0 * fscale
+    wb = sum(wsub) / len(wsub) * 1024.0 * wscale
+    rec = {"kernel": kname, "workload": tag, "source_sha256": kernel_sha(variant),
+           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "traffic_bytes_per_launch": fb + wb,
+           "fetch_scale": fscale, "write_scale": wscale, "fetch_kib_raw": fsub, "write_kib_raw": wsub,
+           "copy_fetch_kib": fcopy, "copy_write_kib": wcopy}
+    path = os.path.join(profiles_dir or os.path.join(ROOT, "profiles"), "%s_%s_traffic.json" % (kname, tag))
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print("wrote %s: reads %.3f GB + writes %.3f GB = %.3f GB per launch (scales %.4f / %.4f, %d launches)"
+          % (path, fb / 1e9, wb / 1e9, (fb + wb) / 1e9, fscale, wscale, len(fsub)))
 
 
 def run_serving(args):
@@ -499,9 +785,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["2d-1024", "2d-80", "2d-2048-layered", "serve", "3d-96"], default="2d-1024",
-                    help="2d-1024 (default): 2D 1024^2 8x8, 4 RHS; 2d-80: 2D 80^2 2x2; 2d-2048-layered: 2D layered "
-                         "2048^2 16x16, 16 RHS; serve: serving stream; 3d-96: 3D 96^3 3x3x3")
+    ap.add_argument("--workload", choices=["layered-2048", "2d-1024", "2d-80", "2d-2048-layered", "serve", "3d-96"],
+                    default="layered-2048",
+                    help="layered-2048 (default, the headline): 2D layered 2048^2 16x16, 16 RHS, mixed FGMRES beside "
+                         "FP64; 2d-1024: 2D 1024^2 8x8, 4 RHS, FP64 stationary; 2d-80: 2D 80^2 2x2; "
+                         "2d-2048-layered: the layered workload as FP64 stationary; serve: serving stream; "
+                         "3d-96: 3D 96^3 3x3x3")
     ap.add_argument("--requests", type=int, default=48, help="serve: requests in the stream")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: mean arrival rate (1/s)")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serve: HBM budget for cached problems (GiB)")
@@ -517,13 +806,23 @@ def main():
                          "transferred source against the direct one on an 8x1 layout (prints one JSON line with "
                          "the table)")
     ap.add_argument("--probe", choices=["none", "traffic"], default="none",
-                    help="traffic: run 3 FP64 local solves of the workload and a 1 GiB device copy "
-                         "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print nothing else")
+                    help="traffic: run 3 local solves of the workload (complex64 for the headline, FP64 for the "
+                         "others) and a 1 GiB device copy (for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print "
+                         "nothing else")
+    ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "TAG"), default=None,
+                    help="write profiles/<kernel>_<TAG>_traffic.json from the counter CSVs of the two rocprofv3 "
+                         "--pmc runs of --probe traffic (FETCH_SIZE, then WRITE_SIZE) and print its summary; "
+                         "runs nothing on the GPU")
+    ap.add_argument("--variant", default="mma", help="--traffic-record: substitution variant the counters are of")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the DDM step here runs on one GPU (there is no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.traffic_record:
+        make_traffic_record(*args.traffic_record, variant=args.variant)
+        return
 
     if args.study != "none":
         run_study(args)
@@ -533,6 +832,10 @@ def main():
         if args.tol is None:
             args.tol = 1e-6
         run_serving(args)
+        return
+
+    if args.workload == "layered-2048":
+        run_headline(args)
         return
 
     import numpy as np
@@ -631,7 +934,7 @@ def main():
     achieved = sub["bytes"] / (sub["ms"] * 1e-3) / 1e9 if sub["ms"] > 0 else 0.0
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": recorded_traffic(s64.solve_variant()) if args.workload == "2d-1024" else None,
+                       "traffic": recorded_traffic(s64.solve_variant(), "2d1024_fp64") if args.workload == "2d-1024" else None,
                        "kernel": SUBST_KERNELS[s64.solve_variant()] + " (block substitution)",
                        "avg_launch_us": avg_us, "launches": sub["launches"],
                        "bytes_per_launch": sub["bytes"] / max(sub["launches"], 1)}

@@ -223,6 +223,29 @@ def layered_2d_2048(nrhs: int = 16, M: int = 2048, N: int = 16) -> Workload:
                     k2, f, c_min=float(c.min()), c_max=float(c.max()))
 
 
+def layered_2d_2048_cut(Ncut: int = 4, nrhs: int = 16) -> Workload:
+    """A bounded sample of layered_2d_2048: the Ncut x Ncut block of 128^2
+    cores around the centre of the same medium (same h, omega, PML 20,
+    overlap 8; the medium continued constantly into the cut's PML), nrhs
+    seeded Gaussians (s = 2h) inside it."""
+    full = layered_2d_2048(nrhs=1)
+    M_full, n_pml = 2048, 20
+    M = 128 * Ncut
+    h = 1.0 / M_full
+    L = M * h
+    x0 = (M_full - M) // 2  # first physical node of the cut in the full grid
+    c_full = full.omega / np.sqrt(full.k2.reshape(M_full + 2 * n_pml - 1, M_full + 2 * n_pml - 1))
+    g = np.arange(-n_pml + 1, M + n_pml)
+    idx = x0 + np.clip(g, 0, M) + n_pml - 1   # clamped cut node -> full array index
+    c = c_full[np.ix_(idx, idx)]
+    k2 = (full.omega / c) ** 2
+    rng = np.random.default_rng(BASE_SEED + 40 + Ncut)
+    centres = rng.uniform(0.1 * L, 0.9 * L, size=(nrhs, 2))
+    f = np.stack([gaussian_source(2, (M, M), n_pml, h, L, tuple(cc), 2 * h) for cc in centres])
+    return Workload("2d-layered-2048-cut-%dx%d" % (Ncut, Ncut), 2, (M, M), L, full.omega, n_pml, 8, (Ncut, Ncut),
+                    full.sigma0, k2, f, c_min=float(c.min()), c_max=float(c.max()))
+
+
 def _gaussian_2d_window(M: int, n_pml: int, h: float, centre, s: float, width: float = 12.0) -> np.ndarray:
     """The unit-mass 2D Gaussian of gaussian_source for a centre well inside
     the physical square, evaluated only within `width` standard deviations of

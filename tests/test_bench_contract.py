@@ -1,11 +1,14 @@
 """Host-side parts of bench.py's result line, checked without a GPU:
 
 * a request for more than one GPU exits with a message (one-GPU path only);
-* the recorded HBM traffic of the substitution kernel is reported only while
-  the kernel source matches the one the counters were taken with;
-* the CPU baseline leg times the oracle on a bounded sample and reports the
+* the HBM traffic record is built from the two counter runs (FETCH_SIZE and
+  WRITE_SIZE per dispatch, each scaled by what it reads for the 1 GiB copy)
+  and reported only while the kernel source matches the one the counters
+  were taken with;
+* the CPU baseline legs time the oracle on a bounded sample and report the
   fields of the contract (value, unit, cores, kind, sample).
 """
+import csv
 import json
 import os
 import subprocess
@@ -24,25 +27,48 @@ def test_multi_gpu_request_exits_with_message():
     assert r.stdout.strip() == ""
 
 
-def test_recorded_traffic_gated_by_kernel_source(monkeypatch):
-    with open(os.path.join(ROOT, "profiles", "k_solve_chain2_2d1024_traffic.json")) as fh:
+def _counter_csv(d, counter, rows):
+    os.makedirs(os.path.join(d, "host"), exist_ok=True)
+    with open(os.path.join(d, "host", "123_counter_collection.csv"), "w", newline="") as fh:
+        wr = csv.writer(fh)
+        wr.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for did, name, v in rows:
+            wr.writerow([did, name, counter, v])
+
+
+def test_traffic_record_from_counter_runs(tmp_path, monkeypatch):
+    k = "void ddm::k_solve_mma<HIP_vector_type<float, 2u>, 768>(...)"
+    cp = "void at::native::elementwise_kernel<copy...>"
+    # FETCH_SIZE reads half the bytes of the copy, WRITE_SIZE all of them
+    _counter_csv(str(tmp_path / "f"), "FETCH_SIZE", [(1, "fill", 10.0), (2, k, 1000.0), (3, k, 1002.0),
+                                                      (4, k, 998.0), (5, cp, 524288.0)])
+    _counter_csv(str(tmp_path / "w"), "WRITE_SIZE", [(1, "fill", 10.0), (2, k, 100.0), (3, k, 100.0),
+                                                      (4, k, 100.0), (5, cp, 1048576.0)])
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    bench.make_traffic_record(str(tmp_path / "f"), str(tmp_path / "w"), "test_c64", variant="mma",
+                              profiles_dir=str(prof))
+    with open(prof / "k_solve_mma_test_c64_traffic.json") as fh:
         rec = json.load(fh)
-    got = bench.recorded_traffic("chain2")
-    assert got is None or got == rec["traffic_bytes_per_launch"]
-    # a traffic record is never older than the algorithmic bytes it should cover
-    assert rec["traffic_bytes_per_launch"] >= 10.933e9
-    assert bench.recorded_traffic("perline") is None       # no record for that kernel
+    assert abs(rec["fetch_bytes_per_launch"] - 1000.0 * 1024 * 2) < 1e-6
+    assert abs(rec["write_bytes_per_launch"] - 100.0 * 1024) < 1e-6
+    assert rec["traffic_bytes_per_launch"] == rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    got = bench.recorded_traffic("mma", "test_c64", profiles_dir=str(prof))
+    assert got == rec["traffic_bytes_per_launch"]
+    assert bench.recorded_traffic("perline", "test_c64", profiles_dir=str(prof)) is None  # no record
+    # a changed kernel source voids the record
+    monkeypatch.setattr(bench, "kernel_sha", lambda v: "0" * 64)
+    assert bench.recorded_traffic("mma", "test_c64", profiles_dir=str(prof)) is None
 
-    import hashlib
 
-    class _H:
-        def __init__(self, *a):
-            pass
-
-        def hexdigest(self):
-            return "0" * 64
-    monkeypatch.setattr(hashlib, "sha256", _H)
-    assert bench.recorded_traffic("chain2") is None
+def test_committed_traffic_record_covers_algorithmic_bytes():
+    path = os.path.join(ROOT, "profiles", "k_solve_mma_layered2048_c64_traffic.json")
+    if not os.path.exists(path):
+        return
+    with open(path) as fh:
+        rec = json.load(fh)
+    # every complex64 inverse of the 2048^2 layered workload read once per sweep: 24.3 GB
+    assert rec["fetch_bytes_per_launch"] >= 24.0e9
 
 
 def test_cpu_baseline_fields():
@@ -50,3 +76,10 @@ def test_cpu_baseline_fields():
     assert cb["value"] > 0 and cb["unit"] == "solves/s"
     assert cb["kind"] == "oracle" and cb["cores"] >= 1
     assert "oracle" in cb["sample"] and "4x4" in cb["sample"]
+
+
+def test_cpu_baseline_layered_fields():
+    cb = bench.run_cpu_baseline_layered(16, 256, 256)
+    assert cb["value"] > 0 and cb["unit"] == "solves/s"
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1
+    assert "layered 2048^2" in cb["sample"] and "4x4" in cb["sample"]
