@@ -213,6 +213,22 @@ def _roofline(s, f, **kw):
             "launches": sub["launches"], "bytes_per_launch": sub["bytes"] / max(sub["launches"], 1)}, prof
 
 
+def tune_handle(s, nrhs, args):
+    """autotuned substitution plan (layout, variant, chain tile) of a handle,
+    from the plan cache when it holds one for this shape"""
+    if args.no_autotune:
+        return None
+    from paper_1807_04180_amd import tuning
+    t0 = time.perf_counter()
+    plan = tuning.tune(s, nrhs, reps=2, cache=tuning.PlanCache())
+    plan["seconds"] = time.perf_counter() - t0
+    log("bench: autotune %s: %s%s, tile %d, %.2f ms per local solve (%s)"
+        % ("cached" if plan["cached"] else "timed", "twisted " if plan["twisted"] else "one-directional ",
+           plan["variant"], plan["chain_tile"], plan["ms"], ", ".join("%s/%s/%d %.2f" % (
+               "tw" if r["twisted"] else "od", r["variant"], r["chain_tile"], r["ms"]) for r in plan.get("table", []))))
+    return plan
+
+
 def run_headline(args):
     """The layered 2048^2, 16-RHS workload: mixed FGMRES (value) beside
     plain FP64, stationary legs, the 1024^2 sub-record and the oracle."""
@@ -257,6 +273,7 @@ def run_headline(args):
             torch.cuda.synchronize()
             log("bench: traffic probe done (3 complex64 local solves, 1 GiB copy)")
             return
+        plan_mx = tune_handle(smx, nrhs, args)
         umx, info_mx, st_mx, t_mx, lat_mx, conv_mx = _timed_solves(smx, f, args.steps, args.warmup, **fg)
         roof_mx, prof_mx = _roofline(smx, f, **fg)
         roof_mx["traffic"] = recorded_traffic(smx.solve_variant(), "layered2048_c64")
@@ -276,6 +293,7 @@ def run_headline(args):
         s64.factor()
         torch.cuda.synchronize()
         t_fac_64 = time.perf_counter() - t0
+        plan_64 = tune_handle(s64, nrhs, args)
         u64, info_64, st_64, t_64, lat_64, conv_64 = _timed_solves(s64, f, side_reps, 1, **fg)
         roof_64, prof_64 = _roofline(s64, f, **fg)
         us_64, info_s64, st_s64, t_s64, lat_s64, conv_s64 = _timed_solves(s64, f, side_reps, 1, **stat)
@@ -308,6 +326,7 @@ def run_headline(args):
         "fp64": {"solves_per_s": v64, "ms_per_batch": sum(t_64) / side_reps * 1e3, "converged": conv_64,
                  "gmres_iters": [x["iters"] for x in info_64], "relres": [x["relres"] for x in info_64],
                  "status": st_64, "factor_s": t_fac_64, "mixed_speedup": value / v64, "roofline": roof_64},
+        "autotune": {"mixed": plan_mx, "fp64": plan_64},
         "stationary": {
             "mixed": {"solves_per_s": conv_smx / sum(t_smx), "steps": [x["iters"] for x in info_smx],
                       "relres": [x["relres"] for x in info_smx], "status": st_smx,
@@ -410,22 +429,22 @@ def make_traffic_record(fetch_dir, write_dir, tag, variant="mma", profiles_dir=N
 
 def run_serving(args):
     """Continuous-batching serving stream (Poisson arrivals of 2D solves on
-    256^2 / 512^2 / 1024^2 grids, constant or layered media, 1-32 sources per
+    256^2 / 512^2 / 1024^2 grids, four media per grid, 1-32 sources per
     request), mixed precision, factorisations cached per problem under an HBM
-    budget; whole-stream throughput and per-request latency."""
+    budget.  The capacity is measured first (a burst of requests all
+    arriving at once), then streams of args.requests requests arrive at 0.5,
+    0.8 and 1.0 x that rate; a sample of requests is solved again alone (same
+    slot count) and by the oracle's global solve."""
     import numpy as np
     import torch
 
     import ddm_inputs as di
     import paper_1807_04180_amd as ddm
+    from paper_1807_04180_amd import tuning
     from paper_1807_04180_amd.serving import Request, Server
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = di.serving_stream(n_requests=args.requests, rate=args.rate)
-    log("bench: serving stream of %d requests, %d right-hand sides, %d problem keys, last arrival %.2f s"
-        % (len(stream), sum(r.workload.nrhs for r in stream), len(set(r.key for r in stream)),
-           stream[-1].t_arrival))
     # warm-up: load the mixed-precision kernels on a small problem
     ws = di.small_2d(M=64, N=(2, 2), n_pml=6, n_ov=4, nrhs=2)
     sw = ddm.HelmholtzDDM(ddm.Problem.from_workload(ws, mixed=True), torch.from_numpy(ws.k2.reshape(-1)).to(dev), 2)
@@ -433,47 +452,125 @@ def run_serving(args):
     sw.slots_step(2)
     sw.slots_poll()
     sw.close()
+    # tuned plans for the stream's shapes (one per grid), outside the timed runs
+    plans = None
+    tuned = {}
+    if not args.no_autotune:
+        plans = tuning.PlanCache()
+        for r in di.serving_stream(n_requests=40, rate=1.0):
+            M = r.key[0]
+            if M in tuned:
+                continue
+            h = ddm.HelmholtzDDM(ddm.Problem.from_workload(r.base, mixed=True),
+                                 torch.from_numpy(r.base.k2.reshape(-1)).to(dev), args.slots)
+            try:
+                p = tuning.tune(h, args.slots, reps=2, cache=plans)
+            finally:
+                h.close()
+            tuned[M] = {k: p[k] for k in ("twisted", "variant", "chain_tile", "ms", "cached")}
+            log("bench: serve plan for %d^2: %s" % (M, tuned[M]))
     torch.cuda.synchronize()
 
-    def maker(w):
-        return lambda: (ddm.Problem.from_workload(w, mixed=True), torch.from_numpy(w.k2.reshape(-1)).to(dev))
+    def make_requests(stream, keep_ids=()):
+        def maker(w):
+            return lambda: (ddm.Problem.from_workload(w, mixed=True), torch.from_numpy(w.k2.reshape(-1)).to(dev))
 
-    reqs = [Request(r.rid, r.key, maker(r.workload), torch.from_numpy(r.workload.f.reshape(r.workload.nrhs, -1)).to(dev),
-                    tol=args.tol, max_steps=400, t_arrival=r.t_arrival) for r in stream]
-    srv = Server(hbm_budget_bytes=int(args.budget_gb * 2**30), slots=args.slots, poll_steps=args.poll_steps,
-                 device="cuda:0")
-    t0 = time.perf_counter()
-    done = srv.run(reqs, time_limit=900.0)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    rel = [x for r in done for x in r.relres]
-    steps = [x for r in done for x in r.steps]
-    lat = [r.latency * 1e3 for r in done]
+        def sources(sr):
+            return lambda: torch.from_numpy(sr.sources().reshape(sr.nrhs, -1)).to(dev)
+        return [Request(r.rid, r.key, maker(r.base), sources(r), tol=args.tol, max_steps=400, t_arrival=r.t_arrival,
+                        n_rhs=r.nrhs, keep=r.rid in keep_ids) for r in stream]
+
+    def serve(stream, keep_ids=()):
+        reqs = make_requests(stream, keep_ids)
+        srv = Server(hbm_budget_bytes=int(args.budget_gb * 2**30), slots=args.slots, poll_steps=args.poll_steps,
+                     device="cuda:0", plans=plans)
+        t0 = time.perf_counter()
+        done = srv.run(reqs, time_limit=stream[-1].t_arrival + 300.0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = [r.latency * 1e3 for r in done]
+        rel = [x for r in done for x in r.relres]
+        steps = [x for r in done for x in r.steps]
+        rec = {"requests": len(reqs), "done": len(done), "rhs": st["rhs"], "wall_s": wall,
+               "rhs_per_s": st["rhs_per_s"], "req_per_s": len(done) / max(r.t_done for r in done),
+               "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+               "cache_hit_rate": st["cache_hit_rate"], "cache_hits": st["cache_hits"],
+               "cache_misses": st["cache_misses"], "evictions": st["evictions"],
+               "hbm_peak_reserved_bytes": st["peak_hbm_bytes"], "factor_seconds": st["factor_seconds"],
+               "plans_applied": st["plans_applied"],
+               "max_relres": max(rel), "unconverged": sum(1 for x in rel if x > args.tol),
+               "ddm_steps": {"p50": pct(steps, 50), "max": max(steps)}}
+        return rec, done
+
+    # capacity: a burst (all requests arrive at once)
+    burst = di.serving_stream(n_requests=args.capacity_requests, rate=1e6, seed=1)
+    cap_rec, _ = serve(burst)
+    cap = cap_rec["req_per_s"]
+    log("bench: capacity %.2f requests/s (%.1f RHS/s), burst of %d" % (cap, cap_rec["rhs_per_s"], len(burst)))
+    runs = {}
+    sample = None
+    for i, frac in enumerate((0.5, 0.8, 1.0)):
+        stream = di.serving_stream(n_requests=args.requests, rate=frac * cap, seed=2 + i)
+        keep = ()
+        if frac == 0.8:
+            keep = tuple(r.rid for r in stream if r.key[0] == min(x.key[0] for x in stream))[:3]
+        rec, done = serve(stream, keep)
+        rec["rate_req_per_s"] = frac * cap
+        runs["%.1f" % frac] = rec
+        log("bench: lambda %.1f x capacity (%.2f req/s): %.1f RHS/s, latency p50 %.0f ms p99 %.0f ms, hit rate %.2f, "
+            "evictions %d, max relres %.1e" % (frac, frac * cap, rec["rhs_per_s"], rec["latency_ms"]["p50"],
+                                              rec["latency_ms"]["p99"], rec["cache_hit_rate"], rec["evictions"],
+                                              rec["max_relres"]))
+        if keep:
+            by_id = {r.rid: r for r in done}
+            sample = [(sr, by_id[sr.rid]) for sr in stream if sr.rid in keep]
     out = {
-        "metric": METRIC, "value": st["rhs_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": len(done),
-        "warmup": 1, "ms_per_step": wall / max(len(done), 1) * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64 factors/solves/transfers, f64 residual/assembly", "data": "synthetic",
-        "config": {"workload": ("serving stream: %d Poisson arrivals (rate %.1f/s) of 2D solves, grids 256^2/512^2/"
-                                "1024^2 with 128^2 cores (2x2/4x4/8x8), constant or layered media, 10 ppw at "
-                                "the slowest velocity, PML 16, overlap 8, 1-32 Gaussian sources each; mixed "
-                                "precision stationary DDM to relres %.0e; factorisations cached per (grid, "
-                                "medium) under a %.0f GiB HBM budget, %d RHS slots per cached problem, "
-                                "%d steps between polls"
-                                % (args.requests, args.rate, args.tol, args.budget_gb, args.slots, args.poll_steps)),
-                   "global_batch": sum(r.nrhs for r in done), "method": "stationary", "precision": "mixed"},
-        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
-        "serving": st, "requests_done": len(done), "requests": len(reqs), "wall_s": wall,
-        "max_relres": max(rel) if rel else None, "ddm_steps": {"p50": pct(steps, 50), "max": max(steps) if steps else None},
+        "metric": METRIC, "value": runs["1.0"]["rhs_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": runs["1.0"]["done"], "warmup": 1, "ms_per_step": runs["1.0"]["wall_s"] / runs["1.0"]["done"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": ("serving stream: Poisson arrivals of 2D solves, grids 256^2/512^2/1024^2 with 128^2 "
+                                "cores (2x2/4x4/8x8), a catalog of 4 media per grid (constant at 10 and 8 ppw, two "
+                                "layered), 1-32 Gaussian sources each, PML 16, overlap 8; complex64 inverses and "
+                                "local solves, FP64 residual, stationary DDM to relres %.0e; factorisations cached "
+                                "per (grid, medium) under a %.0f GiB HBM budget, %d RHS slots per cached problem"
+                                % (args.tol, args.budget_gb, args.slots)),
+                   "global_batch": runs["1.0"]["rhs"], "method": "stationary", "precision": "mixed"},
+        "latency_ms": runs["1.0"]["latency_ms"],
+        "capacity": cap_rec, "rates": runs, "plans": tuned,
         "roofline": None,
         "roofline_note": "mixed stream of problem sizes; per-kernel rooflines are reported on the fixed workloads",
     }
-    log("bench: served %d/%d requests (%d RHS) in %.2f s: %.2f solves/s, latency p50 %.0f ms p99 %.0f ms, "
-        "hits %d misses %d evictions %d, factor %.2f s, max relres %.2e"
-        % (len(done), len(reqs), st["rhs"], wall, st["rhs_per_s"] or 0, out["latency_ms"]["p50"] or 0,
-           out["latency_ms"]["p99"] or 0, st["cache_hits"], st["cache_misses"], st["evictions"],
-           st["factor_seconds"], out["max_relres"] or 0))
+    if sample:
+        from oracle import Oracle
+        checks = []
+        for i, (sr, r) in enumerate(sample):
+            w = sr.workload
+            f = r.f
+            h = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=True), torch.from_numpy(w.k2.reshape(-1)).to(dev),
+                                 args.slots, factor=False)
+            try:
+                plan = plans.get(tuning.plan_key(h, args.slots)) if plans is not None else None
+                if plan is not None:
+                    tuning.apply_plan(h, plan)  # the configuration the server's handle had
+                else:
+                    h.factor()
+                ua, info, st = h.solve(f, method="stationary", tol=args.tol, maxiter=400)
+            finally:
+                h.close()
+            d = (torch.linalg.vector_norm(ua - r.u, dim=1) / torch.linalg.vector_norm(ua, dim=1)).max().item()
+            c = {"rid": r.rid, "grid": sr.key[0], "nrhs": r.nrhs, "alone_vs_mix_rel_diff": d,
+                 "steps_equal": [x["iters"] for x in info] == r.steps}
+            if i < 2:
+                o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
+                uo = o.global_solve(w.f).reshape(r.nrhs, -1)
+                ug = r.u.cpu().numpy()
+                c["rel_err_vs_oracle"] = float(np.max(np.linalg.norm(ug - uo, axis=1) / np.linalg.norm(uo, axis=1)))
+            checks.append(c)
+            log("bench: sample request %d: %s" % (r.rid, c))
+        out["alone_vs_mix"] = checks
     print(json.dumps(out), flush=True)
 
 
@@ -791,9 +888,9 @@ def main():
                          "FP64; 2d-1024: 2D 1024^2 8x8, 4 RHS, FP64 stationary; 2d-80: 2D 80^2 2x2; "
                          "2d-2048-layered: the layered workload as FP64 stationary; serve: serving stream; "
                          "3d-96: 3D 96^3 3x3x3")
-    ap.add_argument("--requests", type=int, default=48, help="serve: requests in the stream")
-    ap.add_argument("--rate", type=float, default=4.0, help="serve: mean arrival rate (1/s)")
-    ap.add_argument("--budget-gb", type=float, default=32.0, help="serve: HBM budget for cached problems (GiB)")
+    ap.add_argument("--requests", type=int, default=500, help="serve: requests in each stream")
+    ap.add_argument("--capacity-requests", type=int, default=64, help="serve: requests of the capacity burst")
+    ap.add_argument("--budget-gb", type=float, default=24.0, help="serve: HBM budget for cached problems (GiB)")
     ap.add_argument("--poll-steps", type=int, default=2, help="serve: DDM steps enqueued per handle between polls")
     ap.add_argument("--slots", type=int, default=16, help="serve: RHS slots per cached problem")
     ap.add_argument("--tol", type=float, default=None, help="stationary/FGMRES tolerance (default per workload)")
@@ -814,6 +911,8 @@ def main():
                          "--pmc runs of --probe traffic (FETCH_SIZE, then WRITE_SIZE) and print its summary; "
                          "runs nothing on the GPU")
     ap.add_argument("--variant", default="mma", help="--traffic-record: substitution variant the counters are of")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default substitution plan instead of the autotuned / cached one")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the DDM step here runs on one GPU (there is no multi-GPU path); "

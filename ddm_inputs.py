@@ -265,51 +265,70 @@ def _gaussian_2d_window(M: int, n_pml: int, h: float, centre, s: float, width: f
 @dataclasses.dataclass
 class StreamRequest:
     """One request of the serving stream: arrival time (s), problem key
-    (grid, medium, layout) and the full problem data with its sources."""
+    (grid, medium, layout), the problem data (`base`: no sources) and the
+    source centres; the sources are evaluated on demand (`workload`), so a
+    long stream does not hold them all."""
     rid: int
     t_arrival: float
     key: Tuple
-    workload: Workload
+    base: Workload
+    centres: np.ndarray
+
+    @property
+    def nrhs(self) -> int:
+        return int(self.centres.shape[0])
+
+    def sources(self) -> np.ndarray:
+        w = self.base
+        return np.stack([_gaussian_2d_window(w.M[0], w.n_pml, w.h, tuple(cc), 2 * w.h) for cc in self.centres])
+
+    @property
+    def workload(self) -> Workload:
+        return dataclasses.replace(self.base, f=self.sources())
 
 
 def serving_stream(n_requests: int = 48, rate: float = 4.0, grids=(256, 512, 1024), max_rhs: int = 32,
-                   n_pml: int = 16, n_ov: int = 8, core: int = 128) -> List[StreamRequest]:
+                   n_pml: int = 16, n_ov: int = 8, core: int = 128, seed: int = 0) -> List[StreamRequest]:
     """Serving stream: Poisson arrivals (exponential gaps of mean 1/rate s);
-    each request draws a grid M from `grids`, a medium (constant c = 1, or the
-    grid's seeded layered medium of the 2048^2 recipe), 1..max_rhs Gaussian
-    sources (std 2h, centres uniform in [0.1, 0.9]^2).  omega gives 10 points
-    per wavelength at the slowest velocity; the layout has cores of `core`
-    cells (2x2 for 256, 4x4 for 512, 8x8 for 1024).  Requests of the same
-    (M, medium) share the problem -- the factorisation cache key."""
-    rng = np.random.default_rng(BASE_SEED + 4)
+    each request draws a grid M from `grids` and a medium from a catalog of
+    four per grid -- constant c = 1 at 10 and at 8 points per wavelength, and
+    two seeded layered media of the 2048^2 recipe at 10 points per wavelength
+    of their slowest velocity -- and 1..max_rhs Gaussian sources (std 2h,
+    centres uniform in [0.1, 0.9]^2).  The layout has cores of `core` cells
+    (2x2 for 256, 4x4 for 512, 8x8 for 1024).  Requests of the same (M,
+    medium) share the problem: the factorisation cache key."""
+    rng = np.random.default_rng(BASE_SEED + 4 + 1000 * seed)
     media = {}
+    bases = {}
     out = []
     t = 0.0
+    catalog = (("constant", 10.0, None), ("constant", 8.0, None), ("layered", 10.0, 0), ("layered", 10.0, 1))
     for rid in range(n_requests):
         t += float(rng.exponential(1.0 / rate))
         M = int(grids[rng.integers(len(grids))])
-        kind = "layered" if rng.integers(2) else "constant"
-        key = (M, kind)
+        mi = int(rng.integers(len(catalog)))
+        kind, ppw, lseed = catalog[mi]
+        key = (M, "%s-%d" % (kind, mi))
         if key not in media:
             L = 1.0
             h = L / M
             if kind == "constant":
                 c = np.ones(tuple(m + 2 * n_pml - 1 for m in (M, M)))
             else:
-                c = layered_velocity(2, (M, M), n_pml, h, L, np.random.default_rng(BASE_SEED + 40 + M),
+                c = layered_velocity(2, (M, M), n_pml, h, L, np.random.default_rng(BASE_SEED + 40 + M + 7 * lseed),
                                      smooth_cells=16.0 * M / 2048)
             c_min, c_max = float(c.min()), float(c.max())
-            omega = 2 * math.pi * c_min / (10 * h)
+            omega = 2 * math.pi * c_min / (ppw * h)
             s0 = sigma0_for_reflection(1e-6, omega / c_max, n_pml * h)
             media[key] = (L, h, omega, s0, (omega / c) ** 2, c_min, c_max)
         L, h, omega, s0, k2, c_min, c_max = media[key]
         nrhs = int(rng.integers(1, max_rhs + 1))
         centres = rng.uniform(0.1, 0.9, size=(nrhs, 2))
-        f = np.stack([_gaussian_2d_window(M, n_pml, h, tuple(cc), 2 * h) for cc in centres])
         N = max(M // core, 1)
-        w = Workload("serve-%d-%s" % (M, kind), 2, (M, M), L, omega, n_pml, n_ov, (N, N), s0, k2, f,
-                     c_min=c_min, c_max=c_max)
-        out.append(StreamRequest(rid, t, key + ((N, N),), w))
+        if key not in bases:
+            bases[key] = Workload("serve-%d-%s" % (M, key[1]), 2, (M, M), L, omega, n_pml, n_ov, (N, N), s0, k2,
+                                  np.zeros((0,) + k2.shape, dtype=np.complex128), c_min=c_min, c_max=c_max)
+        out.append(StreamRequest(rid, t, key + ((N, N),), bases[key], centres))
     return out
 
 

@@ -321,6 +321,20 @@ int ddm_get_solve_variant(const ddm_handle *h);
  * -1 for variants that do not apply or could not be launched. */
 int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms);
 
+/* RHS tile of the chain variant (DDM_SOLVE_CHAIN) for calls of more than 4
+ * right-hand sides: 4 (1024-thread workgroups), 8 (512 threads for
+ * DDM_FP64, 1024 for DDM_MIXED) or 16 (the default choice for 16 or more
+ * RHS); 0 restores the choice by batch size.  The tile can change the
+ * rounding of a result (a different order of partial sums).  Exposed for
+ * the autotuner; DDM_EINVAL for other values. */
+int ddm_set_chain_tile(ddm_handle *h, int rt);
+
+/* Mean time of one local solve (all subdomains, nrhs right-hand sides of
+ * zeros in the handle's workspace) with the current variant, layout and
+ * tile: one warm-up, then reps solves timed with HIP events on the handle's
+ * stream (host ms, synchronises).  For the autotuner. */
+int ddm_time_local_solve(ddm_handle *h, int nrhs, int reps, double *ms);
+
 /* Replay the steady-state step of the stationary solve (transfer, local
  * solves, accumulation, residual and norms) as a captured hipGraph, one per
  * generation of the ring of local solutions (default on).  The handle then

@@ -93,10 +93,12 @@ def lib():
     L.ddm_get_solve_variant.argtypes = [H]
     L.ddm_autotune.argtypes = [H, I, I, DP]
     L.ddm_set_spin_limit.argtypes = [H, I]
+    L.ddm_set_chain_tile.argtypes = [H, I]
+    L.ddm_time_local_solve.argtypes = [H, I, I, DP]
     L.ddm_set_transfer_form.argtypes = [H, I]
     L.ddm_profile_enable.argtypes = [H, I]
     L.ddm_profile_read.argtypes = [H, ctypes.POINTER(DdmProfile)]
-    for name in ("ddm_slot_admit", "ddm_slots_step", "ddm_slots_poll", "ddm_slot_retire", "ddm_set_graphs", "ddm_set_factor_layout", "ddm_set_solve_variant", "ddm_get_solve_variant", "ddm_autotune", "ddm_set_spin_limit", "ddm_set_transfer_form",
+    for name in ("ddm_slot_admit", "ddm_slots_step", "ddm_slots_poll", "ddm_slot_retire", "ddm_set_graphs", "ddm_set_factor_layout", "ddm_set_solve_variant", "ddm_get_solve_variant", "ddm_autotune", "ddm_set_spin_limit", "ddm_set_chain_tile", "ddm_time_local_solve", "ddm_set_transfer_form",
                  "ddm_profile_enable", "ddm_profile_read", "ddm_memory_required", "ddm_setup", "ddm_factor", "ddm_iterate", "ddm_solve", "ddm_sizes",
                  "ddm_geometry", "ddm_apply", "ddm_residual", "ddm_residual_noalloc", "ddm_restrict_core", "ddm_local_solve",
                  "ddm_transfer", "ddm_assemble", "ddm_pml_strength", "ddm_device_bytes"):

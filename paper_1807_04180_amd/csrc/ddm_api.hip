@@ -726,6 +726,47 @@ int ddm_set_spin_limit(ddm_handle *h, int limit) {
     return DDM_OK;
 }
 
+int ddm_set_chain_tile(ddm_handle *h, int rt) {
+    if (!h) return DDM_EINVAL;
+    if (rt != 0 && rt != 4 && rt != 8 && rt != 16) return fail(h, DDM_EINVAL, "chain RHS tile must be 0, 4, 8 or 16");
+    if (rt != h->chain_tile) drop_step_graphs(h);
+    h->chain_tile = rt;
+    return DDM_OK;
+}
+
+int ddm_time_local_solve(ddm_handle *h, int nrhs, int reps, double *ms) {
+    int st = check_args(h, nrhs);
+    if (st) return st;
+    if (!ms || reps < 1) return fail(h, DDM_EINVAL, "ms must be non-null and reps >= 1");
+    if (!h->factored) return fail(h, DDM_ESTATE, "ddm_time_local_solve before ddm_factor");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const size_t es = elem_size(h->mixed);
+        HIPCHK(launch_fill_zero(h->d_g, (long long)nrhs * h->plan.etot * es, h->stream));
+        auto once = [&]() {
+            HIPCHK(h->mixed ? launch_local_solve<float2>(h, (const float2 *)h->d_g, (float2 *)h->d_ring[0], nrhs)
+                            : launch_local_solve<double2>(h, (const double2 *)h->d_g, (double2 *)h->d_ring[0], nrhs));
+        };
+        once();  // warm-up
+        HIPCHK(hipEventRecord(e0, h->stream));
+        for (int r = 0; r < reps; ++r) once();
+        HIPCHK(hipEventRecord(e1, h->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        *ms = t / reps;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    } catch (const HipFail &e) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return hip_fail(h, e);
+    }
+    return check_abort(h);
+}
+
 int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms) {
     int st = check_args(h, nrhs);
     if (st) return st;

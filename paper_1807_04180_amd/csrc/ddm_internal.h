@@ -142,6 +142,7 @@ struct ddm_handle {
     double2 *d_coef_y = nullptr;    // Krylov combination coefficients
     // substitution kernel variant (autotuned) and persistent-launch sync state
     int solve_variant = 0;
+    int chain_tile = 0;             // chain variant, batches of > 4 RHS: RHS tile 4, 8 or 16 (0 = by batch size)
     int *d_sync = nullptr;          // 2 nsub meeting flags, 2 nsub read-done flags, 1 abort flag
     int *d_sync2 = nullptr;         // split substitution: 4 nsub meeting, 4 nsub exchange and
                                     // 4 nsub read-done flags

@@ -835,6 +835,19 @@ static hipError_t run_chain(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
 
 template <typename T>
 static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
+    const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= h->plan.ncu;
+    // a forced RHS tile (ddm_set_chain_tile) for batches of more than 4 RHS
+    if (nrhs > 4 && h->chain_tile == 4) {
+        if constexpr (sizeof(T) == sizeof(double2)) return run_chain<T, 4, 1>(h, g, x, nrhs);
+        else return run_chain<T, 4, 2>(h, g, x, nrhs);
+    }
+    if (nrhs > 4 && h->chain_tile == 8 && coop_ok) {
+        if constexpr (sizeof(T) == sizeof(double2)) {
+            if (chain_lds<T, 8, 1, 512>(h->plan.bs_max) <= kLdsMax) return run_chain<T, 8, 1, 512>(h, g, x, nrhs);
+        } else {
+            return run_chain<T, 8, 1>(h, g, x, nrhs);
+        }
+    }
     if constexpr (sizeof(T) == sizeof(double2)) {
         if (nrhs <= 1) return run_chain<T, 1, 1>(h, g, x, nrhs);
         if (nrhs <= 2) return run_chain<T, 2, 1>(h, g, x, nrhs);
@@ -846,7 +859,6 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
         // partition and the column groups' partial sums added in order (the
         // same bits as every smaller tile), else on 512-thread workgroups with
         // 8 pairs (fewer waves; rounding differs from smaller batches)
-        const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= h->plan.ncu;
         if (coop_ok && nrhs >= 16 && chain_lds<T, 16, 1, kCThreads>(h->plan.bs_max) <= kLdsMax)
             return run_chain<T, 16, 1>(h, g, x, nrhs);
         if (coop_ok && nrhs >= 16 && chain_lds<T, 16, 1, 512, 8>(h->plan.bs_max) <= kLdsMax)
@@ -860,7 +872,6 @@ static hipError_t run_chain_rt(ddm_handle *h, const T *g, T *x, int nrhs) {
         if (nrhs <= 8) return run_chain<T, 8, 1>(h, g, x, nrhs);
         // 16 RHS with 16-byte loads needs the 256-VGPR budget of 512-thread
         // workgroups (and 8 work pairs to fit the partial sums in LDS)
-        const bool coop_ok = !h->plan.twisted || 2 * h->plan.nsub <= h->plan.ncu;
         if (coop_ok && chain_lds<T, 16, 2, 512, 8>(h->plan.bs_max) <= kLdsMax)
             return run_chain<T, 16, 2, 512, 8>(h, g, x, nrhs);
         return run_chain<T, 16, 1>(h, g, x, nrhs);

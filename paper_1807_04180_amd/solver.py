@@ -235,6 +235,14 @@ class HelmholtzDDM:
         self._check(self.lib.ddm_autotune(self._h, int(nrhs or self.nrhs_max), reps, t))
         return {name: (t[i] if t[i] >= 0 else None) for i, name in enumerate(_ffi.SOLVE_VARIANTS)}
 
+    def set_chain_tile(self, rt: int):
+        self._check(self.lib.ddm_set_chain_tile(self._h, int(rt)))
+
+    def time_local_solve(self, nrhs: Optional[int] = None, reps: int = 3) -> float:
+        ms = ctypes.c_double(0.0)
+        self._check(self.lib.ddm_time_local_solve(self._h, int(nrhs or self.nrhs_max), int(reps), ctypes.byref(ms)))
+        return ms.value
+
     def set_graphs(self, on: bool):
         self._check(self.lib.ddm_set_graphs(self._h, 1 if on else 0))
 

@@ -22,15 +22,20 @@ def test_serving_stream_is_seeded_and_follows_the_recipe():
     assert all(np.array_equal(x.workload.f, y.workload.f) for x, y in zip(a, b))
     t = [r.t_arrival for r in a]
     assert all(t1 > t0 for t0, t1 in zip(t, t[1:]))
+    kinds = set()
     for r in a:
         w = r.workload
         M, kind, N = r.key
+        kinds.add(kind)
         assert w.M == (M, M) and w.N == N and N[0] * 128 == M
         assert 1 <= w.nrhs <= 32
         assert w.f.shape == (w.nrhs,) + w.grid_shape
-        # 10 points per wavelength at the slowest velocity
+        # 10 points per wavelength at the slowest velocity (8 for the second
+        # constant medium of the catalog)
         k_max = np.sqrt(w.k2.max())
-        assert abs(2 * np.pi / k_max / w.h - 10.0) < 1e-9
+        ppw = 8.0 if kind == "constant-1" else 10.0
+        assert abs(2 * np.pi / k_max / w.h - ppw) < 1e-9
+    assert kinds <= {"constant-0", "constant-1", "layered-2", "layered-3"}
     # one problem per key: requests with the same key share the medium
     by_key = {}
     for r in a:

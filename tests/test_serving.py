@@ -3,6 +3,7 @@ budget).  CPU: admission / LRU eviction logic with a stand-in solver.  GPU:
 every request's result in a Poisson mix equals the same request solved alone,
 and slots of different problems overlap on the device."""
 import math
+import time
 
 import numpy as np
 import pytest
@@ -21,7 +22,11 @@ class _FakeSolver:
         self.nrhs_max = slots
         self.steps = [-1] * slots
         self.need = int(problem.sigma0)
+        self.build_delay = getattr(problem, "build_delay", 0.0)
         _FakeSolver.live += 1
+
+    def factor(self):
+        time.sleep(self.build_delay)
 
     def slot_admit(self, slot, f):
         assert self.steps[slot] < 0
@@ -42,9 +47,10 @@ class _FakeSolver:
 
 
 class _FakeProblem:
-    def __init__(self, need, nbytes):
+    def __init__(self, need, nbytes, build_delay=0.0):
         self.sigma0 = need
         self.nbytes = nbytes
+        self.build_delay = build_delay
 
     def memory_required(self, slots):
         return self.nbytes
@@ -68,8 +74,8 @@ def _fake_env(monkeypatch):
     monkeypatch.setattr(torch.cuda, "current_stream", lambda *a: None)
 
 
-def _req(rid, key, need, nbytes, nrhs, t):
-    return serving.Request(rid, key, lambda: (_FakeProblem(need, nbytes), None), torch.zeros((nrhs, 4)),
+def _req(rid, key, need, nbytes, nrhs, t, build_delay=0.0):
+    return serving.Request(rid, key, lambda: (_FakeProblem(need, nbytes, build_delay), None), torch.zeros((nrhs, 4)),
                            tol=1e-6, t_arrival=t)
 
 
@@ -84,6 +90,23 @@ def test_admission_by_budget_and_lru_eviction(monkeypatch):
     assert st["peak_hbm_bytes"] <= 100          # never above the budget
     assert srv.evictions >= 1                   # A and B cannot be resident together
     assert st["cache_hits"] + st["cache_misses"] == 4
+    srv.close()
+    assert _FakeSolver.live == 0
+
+
+def test_cache_miss_builds_off_the_scheduling_path(monkeypatch):
+    """A miss whose factorisation takes 0.5 s must not stall the other
+    handles: requests on a resident problem finish while it builds."""
+    _fake_env(monkeypatch)
+    srv = serving.Server(hbm_budget_bytes=1000, slots=2, device="cpu")
+    reqs = [_req(0, "A", 3, 60, 1, 0.0), _req(1, "B", 2, 60, 1, 0.05, build_delay=0.5),
+            _req(2, "A", 3, 60, 2, 0.1), _req(3, "A", 3, 60, 1, 0.15)]
+    done = srv.run(reqs, time_limit=10.0)
+    assert len(done) == 4
+    by = {r.rid: r for r in done}
+    assert by[1].t_done >= 0.5
+    assert max(by[0].t_done, by[2].t_done, by[3].t_done) < by[1].t_done
+    assert srv.stats()["factor_seconds"] >= 0.5
     srv.close()
     assert _FakeSolver.live == 0
 
@@ -109,9 +132,10 @@ def _workload_request(rid, w, mixed, t, seed, nrhs):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("slots", [4, 16])
 @pytest.mark.parametrize("blocks", ["small", "large"])
 @pytest.mark.parametrize("mixed", [False, True])
-def test_alone_vs_mix(mixed, blocks):
+def test_alone_vs_mix(mixed, blocks, slots):
     # small: blocks of 84-92 unknowns (one workgroup per chain); large: blocks
     # of 148-160 unknowns, where handles of at most 4 slots use split chains
     if blocks == "small":
@@ -123,20 +147,34 @@ def test_alone_vs_mix(mixed, blocks):
     rng = np.random.default_rng(7)
     t = np.cumsum(rng.exponential(0.02, size=8))
     reqs = [_workload_request(i, wa if i % 2 == 0 else wb, mixed, float(t[i]), i, 1 + i % 3) for i in range(8)]
-    srv = serving.Server(hbm_budget_bytes=8 << 30, slots=4)
+    # 4 slots: the vector substitution kernels; 16: the matrix-core tiles
+    srv = serving.Server(hbm_budget_bytes=8 << 30, slots=slots)
     done = srv.run(reqs, time_limit=120.0)
     assert len(done) == 8
     st = srv.stats()
     assert st["cache_misses"] + st["cache_hits"] == 8 and st["cache_misses"] >= 2 and st["cache_hits"] >= 2
     srv.close()
-    # each request alone: a fresh handle, stationary solve to the same tolerance
+    # each request alone: a fresh handle of the same slot count (hence the same
+    # kernels), stationary solve to the same tolerance
     for r in reqs:
         w = wa if r.rid % 2 == 0 else wb
         s = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=mixed), torch.from_numpy(w.k2.reshape(-1)).cuda(),
-                             r.nrhs)
+                             slots)
         u, info, stt = s.solve(r.f, method="stationary", tol=r.tol, maxiter=r.max_steps)
         assert stt == 0
         assert [i["iters"] for i in info] == r.steps
         err = (torch.linalg.vector_norm(u - r.u, dim=1) / torch.linalg.vector_norm(u, dim=1)).max().item()
         assert err <= 1e-12, (r.rid, err)
         s.close()
+    # and against the oracle's global solve (one request per problem, on the
+    # small grids): the served result is the discrete solution to the
+    # stationary tolerance
+    if blocks != "small":
+        return
+    from oracle import Oracle
+    for w, r in ((wa, reqs[0]), (wb, reqs[1])):
+        o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
+        uo = o.global_solve(r.f.cpu().numpy().reshape((r.nrhs,) + tuple(w.grid_shape))).reshape(r.nrhs, -1)
+        ug = r.u.cpu().numpy()
+        err = np.max(np.linalg.norm(ug - uo, axis=1) / np.linalg.norm(uo, axis=1))
+        assert err <= 1e-6, (r.rid, err)
