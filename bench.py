@@ -427,6 +427,63 @@ def make_traffic_record(fetch_dir, write_dir, tag, variant="mma", profiles_dir=N
           % (path, fb / 1e9, wb / 1e9, (fb + wb) / 1e9, fscale, wscale, len(fsub)))
 
 
+def overlap_report(trace_csv):
+    """Concurrency of kernels from different HIP streams in a rocprofv3
+    kernel trace (CSV with Stream_Id, Kernel_Name, Start/End_Timestamp):
+    GPU busy time, time with kernels of two or more streams in flight, and
+    the share of each kernel class's time that overlaps another stream's
+    kernel."""
+    import csv
+
+    ev = []
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), int(r["Stream_Id"]), r["Kernel_Name"]))
+    # sweep over start / end points: streams in flight at every instant
+    pts = sorted([(a, 1, s) for a, b, s, _ in ev] + [(b, -1, s) for a, b, s, _ in ev])
+    active = {}
+    busy = multi = 0
+    last = None
+    multi_iv = []
+    for t, d, st in pts:
+        if last is not None and t > last:
+            n = sum(1 for v in active.values() if v > 0)
+            if n >= 1:
+                busy += t - last
+            if n >= 2:
+                multi += t - last
+                multi_iv.append((last, t))
+        active[st] = active.get(st, 0) + d
+        last = t
+
+    def cls(name):
+        for k, c in (("k_solve", "substitution"), ("k_transfer", "transfer"), ("k_assemble", "assembly"),
+                     ("k_stencil", "residual"), ("k_factor", "factorisation")):
+            if k in name:
+                return c
+        return "other"
+    # share of each class's kernel time inside a multi-stream interval
+    import bisect
+    starts = [a for a, _ in multi_iv]
+    by = {}
+    for a, b, st, name in ev:
+        c = cls(name)
+        tot, ov = by.get(c, (0, 0))
+        i = max(bisect.bisect_right(starts, a) - 1, 0)
+        o = 0
+        while i < len(multi_iv) and multi_iv[i][0] < b:
+            lo, hi = max(a, multi_iv[i][0]), min(b, multi_iv[i][1])
+            if hi > lo:
+                o += hi - lo
+            i += 1
+        by[c] = (tot + (b - a), ov + o)
+    streams = sorted({s for _, _, s, _ in ev})
+    return {"kernels": len(ev), "streams": len(streams), "busy_ms": busy / 1e6, "multi_stream_ms": multi / 1e6,
+            "multi_stream_share_of_busy": multi / busy if busy else 0.0,
+            "overlapped_share_by_class": {c: (ov / tot if tot else 0.0) for c, (tot, ov) in sorted(by.items())},
+            "ms_by_class": {c: tot / 1e6 for c, (tot, _) in sorted(by.items())}}
+
+
 def run_serving(args):
     """Continuous-batching serving stream (Poisson arrivals of 2D solves on
     256^2 / 512^2 / 1024^2 grids, four media per grid, 1-32 sources per
@@ -557,12 +614,19 @@ def run_serving(args):
                     tuning.apply_plan(h, plan)  # the configuration the server's handle had
                 else:
                     h.factor()
-                ua, info, st = h.solve(f, method="stationary", tol=args.tol, maxiter=400)
+                # alone: the request's sources in batches of at most `slots`
+                ua = torch.empty_like(f)
+                iters = []
+                for c0 in range(0, r.nrhs, args.slots):
+                    uc, info, st = h.solve(f[c0:c0 + args.slots].contiguous(), method="stationary", tol=args.tol,
+                                           maxiter=400)
+                    ua[c0:c0 + args.slots] = uc
+                    iters += [x["iters"] for x in info]
             finally:
                 h.close()
             d = (torch.linalg.vector_norm(ua - r.u, dim=1) / torch.linalg.vector_norm(ua, dim=1)).max().item()
             c = {"rid": r.rid, "grid": sr.key[0], "nrhs": r.nrhs, "alone_vs_mix_rel_diff": d,
-                 "steps_equal": [x["iters"] for x in info] == r.steps}
+                 "steps_equal": iters == r.steps}
             if i < 2:
                 o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
                 uo = o.global_solve(w.f).reshape(r.nrhs, -1)
@@ -891,7 +955,9 @@ def main():
     ap.add_argument("--requests", type=int, default=500, help="serve: requests in each stream")
     ap.add_argument("--capacity-requests", type=int, default=64, help="serve: requests of the capacity burst")
     ap.add_argument("--budget-gb", type=float, default=24.0, help="serve: HBM budget for cached problems (GiB)")
-    ap.add_argument("--poll-steps", type=int, default=2, help="serve: DDM steps enqueued per handle between polls")
+    ap.add_argument("--poll-steps", type=int, default=1,
+                    help="serve: DDM steps enqueued per handle between polls (1: a right-hand side leaves at the "
+                         "first step that meets the tolerance, as in a batch solve alone)")
     ap.add_argument("--slots", type=int, default=16, help="serve: RHS slots per cached problem")
     ap.add_argument("--tol", type=float, default=None, help="stationary/FGMRES tolerance (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -911,6 +977,8 @@ def main():
                          "--pmc runs of --probe traffic (FETCH_SIZE, then WRITE_SIZE) and print its summary; "
                          "runs nothing on the GPU")
     ap.add_argument("--variant", default="mma", help="--traffic-record: substitution variant the counters are of")
+    ap.add_argument("--overlap-from", default=None, metavar="KERNEL_TRACE_CSV",
+                    help="print the cross-stream kernel overlap of a rocprofv3 kernel trace; runs nothing on the GPU")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default substitution plan instead of the autotuned / cached one")
     args = ap.parse_args()
@@ -921,6 +989,10 @@ def main():
 
     if args.traffic_record:
         make_traffic_record(*args.traffic_record, variant=args.variant)
+        return
+
+    if args.overlap_from:
+        print(json.dumps(overlap_report(args.overlap_from)))
         return
 
     if args.study != "none":
@@ -980,6 +1052,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("bench: traffic probe done (3 local solves, 1 GiB copy)")
+        s64.close()
         return
 
     def solve_fp64(u=None):
@@ -1061,7 +1134,7 @@ def main():
         log("bench: FP64 FGMRES: %.2f solves/s, iters %s" % (nrhs / tf, [x["iters"] for x in infof]))
 
         # ---- mixed precision -------------------------------------------------
-        del s64
+        s64.close()
         torch.cuda.empty_cache()
         t0 = time.perf_counter()
         smx = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=True), k2, nrhs)
@@ -1106,7 +1179,9 @@ def main():
             "(%.1f%% of HBM peak)"
             % (nrhs * args.steps / tm, (nrhs * args.steps / tm) / value, [x["iters"] for x in infom],
                ["%.1e" % e for e in errm], achm, 100 * achm / HBM_PEAK_GBS))
-        del smx
+        smx.close()
+    else:
+        s64.close()
 
     if not args.no_cpu_baseline:
         log("bench: CPU baseline (oracle) ...")

@@ -745,6 +745,7 @@ int ddm_time_local_solve(ddm_handle *h, int nrhs, int reps, double *ms) {
         HIPCHK(hipEventCreate(&e1));
         const size_t es = elem_size(h->mixed);
         HIPCHK(launch_fill_zero(h->d_g, (long long)nrhs * h->plan.etot * es, h->stream));
+        h->g_clean_rows = 0;
         auto once = [&]() {
             HIPCHK(h->mixed ? launch_local_solve<float2>(h, (const float2 *)h->d_g, (float2 *)h->d_ring[0], nrhs)
                             : launch_local_solve<double2>(h, (const double2 *)h->d_g, (double2 *)h->d_ring[0], nrhs));
@@ -781,6 +782,7 @@ int ddm_autotune(ddm_handle *h, int nrhs, int reps, double *times_ms) {
         HIPCHK(hipEventCreate(&e1));
         size_t es = elem_size(h->mixed);
         HIPCHK(launch_fill_zero(h->d_g, (long long)nrhs * P.etot * es, h->stream));
+        h->g_clean_rows = 0;
         // the variants that read the current layout of the inverses first,
         // then the others (one re-factorisation between the two groups)
         std::vector<int> order;
@@ -842,6 +844,7 @@ static int slots_init(ddm_handle *h) {
     HIPCHK(launch_fill_zero(h->d_r, (long long)vb, h->stream));
     const size_t es = elem_size(h->mixed);
     HIPCHK(launch_fill_zero(h->d_g, (long long)h->nrhs_max * P.etot * es, h->stream));
+    h->g_clean_rows = 0;
     for (int k = 0; k < P.ring; ++k)
         HIPCHK(launch_fill_zero(h->d_ring[k], (long long)h->nrhs_max * P.etot * es, h->stream));
     h->slot_steps.assign(h->nrhs_max, -1);
@@ -1259,12 +1262,14 @@ int ddm_local_solve(ddm_handle *h, const void *g, void *uhat, int nrhs) {
     long long n = (long long)nrhs * P.etot;
     try {
         if (h->mixed) {
+            h->g_clean_rows = 0;
             HIPCHK(launch_convert_c128_to_c64((const double2 *)g, (float2 *)h->d_g, n, h->stream));
             HIPCHK(launch_local_solve<float2>(h, (const float2 *)h->d_g, (float2 *)h->d_ring[0], nrhs));
             HIPCHK(launch_convert_c64_to_c128((const float2 *)h->d_ring[0], (double2 *)uhat, n, h->stream));
         } else {
             const double2 *src = (const double2 *)g;
             if (g == uhat) {
+                h->g_clean_rows = 0;
                 HIPCHK(hipMemcpyAsync(h->d_g, g, n * sizeof(double2), hipMemcpyDeviceToDevice, h->stream));
                 src = (const double2 *)h->d_g;
             }

@@ -122,6 +122,7 @@ struct ddm_handle {
     int *d_flags = nullptr;         // per-subdomain status flags
     // step workspaces, element type T (double2 or float2), nrhs_max * etot each
     void *d_g = nullptr;
+    int g_clean_rows = 0;           // RHS rows of d_g known to be zero outside the transfer strips
     void *d_ring[4] = {nullptr, nullptr, nullptr, nullptr};
     // FP64 global workspaces
     double2 *d_r = nullptr;         // residual / operator output, nrhs_max * nglob

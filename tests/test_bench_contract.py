@@ -83,3 +83,21 @@ def test_cpu_baseline_layered_fields():
     assert cb["value"] > 0 and cb["unit"] == "solves/s"
     assert cb["kind"] == "oracle" and cb["cores"] >= 1
     assert "layered 2048^2" in cb["sample"] and "4x4" in cb["sample"]
+
+
+def test_overlap_report_on_a_synthetic_trace(tmp_path):
+    """Two streams: a substitution kernel [0, 100) on stream 1, a transfer
+    [50, 150) on stream 2, a residual [200, 300) on stream 1 alone."""
+    path = tmp_path / "trace.csv"
+    with open(path, "w", newline="") as fh:
+        wr = csv.writer(fh)
+        wr.writerow(["Kind", "Stream_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        wr.writerow(["KERNEL_DISPATCH", 1, "void ddm::k_solve_mma<float>", 0, 100])
+        wr.writerow(["KERNEL_DISPATCH", 2, "void ddm::k_transfer<float>", 50, 150])
+        wr.writerow(["KERNEL_DISPATCH", 1, "void ddm::k_stencil<0>", 200, 300])
+    rep = bench.overlap_report(str(path))
+    assert rep["kernels"] == 3 and rep["streams"] == 2
+    assert abs(rep["busy_ms"] - 250e-6) < 1e-12 and abs(rep["multi_stream_ms"] - 50e-6) < 1e-12
+    assert abs(rep["overlapped_share_by_class"]["substitution"] - 0.5) < 1e-12
+    assert abs(rep["overlapped_share_by_class"]["transfer"] - 0.5) < 1e-12
+    assert rep["overlapped_share_by_class"]["residual"] == 0.0
