@@ -22,6 +22,11 @@
 //     pivot rows become Y) over 64 x 64 tiles with FP64 MFMA
 //     (v_mfma_f64_16x16x4, complex product as four real products); every
 //     chain's tiles go into one launch;
+//   * blocks of more than 512 rows defer the update over groups of kDefer
+//     panels: each panel of a group is factored from its columns and pivot
+//     rows brought up to date by narrow products, and one update of rank
+//     kDefer * kPanel applies the group, so the block is read and written
+//     once per group instead of once per panel;
 //   * pivot rows are never swapped: row r chosen at step k is recorded
 //     (ppos[r] = k, piv[k] = r) and the inverse is read back as
 //     W(i, j) = N(piv[i], ppos[j]) when the block is stored.
@@ -132,23 +137,39 @@ constexpr int kEGroups = 64;    // max workgroups per chain for form / store
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// Blocks of more than 512 rows defer their trailing updates: kDefer panels
+// are factored against the block as it stood before the first of them (each
+// panel's columns and pivot rows brought up to date by narrow products), then
+// one update of rank kDefer * kPanel applies all of them.
+constexpr int kDefer = 4;
+constexpr int kLLRows = 8;  // rows per thread of the left-looking panel kernel
+
+// deferral goes with the left-looking panel (blocks of 513 .. kLLRows * kPThreads rows)
+static int defer_slots(const Plan &P) {
+    return P.bs_max > 512 && P.bs_max <= kLLRows * kPThreads ? kDefer : 1;
+}
+
 // Per-chain factor workspace (chain c = 2 * subdomain + direction).
 struct FactWs {
     double2 *M;         // [chain][2][bs_max^2] FP64 block buffers
-    double *X, *Y;      // [chain][re, im][kPanel][bsp] panel operands
+    double *X, *Y;      // [chain][slot][re, im][kPanel][bsp] panel operands of the deferred panels
     double2 *Pw;        // [chain][kPanel][bsp] panel work (when not in LDS)
+    double2 *C;         // [chain][kPanel][bsp] up-to-date columns of a deferred panel (slots > 1)
     int *ppos, *piv;    // [chain][bsp] pivot step of a row / row of a pivot step
     unsigned long long *mxb;  // [chain][buffer] max |entry|^2 of a block buffer (FP64 bits)
     long long mstride;  // bs_max^2
     int bsp;            // bs_max rounded up to kUTile
+    int slots;          // panels whose update can be deferred (1 or kDefer)
 };
 
 size_t factor_ws_bytes(const Plan &P) {
     const size_t bsp = (size_t)((P.bs_max + kUTile - 1) / kUTile) * kUTile;
     const size_t nc = (size_t)2 * P.nsub;
+    const size_t slots = (size_t)defer_slots(P);
     size_t b = nc * 2 * (size_t)P.bs_max * P.bs_max * sizeof(double2);
-    b += nc * 4 * kPanel * bsp * sizeof(double);
+    b += nc * slots * 4 * kPanel * bsp * sizeof(double);
     b += nc * kPanel * bsp * sizeof(double2);
+    if (slots > 1) b += nc * kPanel * bsp * sizeof(double2);
     b += nc * 2 * bsp * sizeof(int) + nc * 2 * sizeof(double);
     return b + 4096;
 }
@@ -157,17 +178,33 @@ static FactWs carve_ws(const Plan &P, void *base) {
     FactWs w;
     w.bsp = ((P.bs_max + kUTile - 1) / kUTile) * kUTile;
     w.mstride = (long long)P.bs_max * P.bs_max;
+    w.slots = defer_slots(P);
     const size_t nc = (size_t)2 * P.nsub;
     char *p = (char *)base;
     w.M = (double2 *)p;  p += nc * 2 * w.mstride * sizeof(double2);
-    w.X = (double *)p;   p += nc * 2 * kPanel * w.bsp * sizeof(double);
-    w.Y = (double *)p;   p += nc * 2 * kPanel * w.bsp * sizeof(double);
+    w.X = (double *)p;   p += nc * w.slots * 2 * kPanel * w.bsp * sizeof(double);
+    w.Y = (double *)p;   p += nc * w.slots * 2 * kPanel * w.bsp * sizeof(double);
     w.Pw = (double2 *)p; p += nc * kPanel * w.bsp * sizeof(double2);
+    w.C = nullptr;
+    if (w.slots > 1) {
+        w.C = (double2 *)p;
+        p += nc * kPanel * w.bsp * sizeof(double2);
+    }
     w.ppos = (int *)p;   p += nc * w.bsp * sizeof(int);
     w.piv = (int *)p;    p += nc * w.bsp * sizeof(int);
     p = (char *)(((uintptr_t)p + 15) & ~(uintptr_t)15);
     w.mxb = (unsigned long long *)p;
     return w;
+}
+
+// Real parts of chain c's X (or Y) of deferred slot k; the imaginary parts
+// follow kPanel * bsp doubles later.  Element (row i, panel column t) of X
+// is at t * bsp + i, element (t, column j) of Y at t * bsp + j.
+__device__ inline double *ws_x(const FactWs &w, int c, int k) {
+    return w.X + ((long long)c * w.slots + k) * 2 * kPanel * w.bsp;
+}
+__device__ inline double *ws_y(const FactWs &w, int c, int k) {
+    return w.Y + ((long long)c * w.slots + k) * 2 * kPanel * w.bsp;
 }
 
 // Where chain c stands at lock-step s (mid == false), or at its subdomain's
@@ -285,8 +322,8 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel(const SubDesc *__res
     if (k0 >= bs) return;
     const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
     const double2 *M = chain_M(w, c, q.cur);
-    double *Xr = w.X + (long long)c * 2 * kPanel * bsp, *Xi = Xr + (long long)kPanel * bsp;
-    double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
+    double *Xr = ws_x(w, c, 0), *Xi = Xr + (long long)kPanel * bsp;
+    double *Yr = ws_y(w, c, 0), *Yi = Yr + (long long)kPanel * bsp;
     int *ppos = w.ppos + (long long)c * bsp, *piv = w.piv + (long long)c * bsp;
     double2 *Ainv = lds;                      // [kPanel][kPanel]
     double2 *rowr = Ainv + kPanel * kPanel;   // [kPanel]
@@ -396,10 +433,10 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel(const SubDesc *__res
 // The pivots are those of partial pivoting on the panel.  A11^{-1} is the
 // in-place Gauss-Jordan inverse (pivots on the diagonal, in pivot order) of
 // the panel's original pivot rows; Y and X are formed as above.
-constexpr int kLLRows = 8;
 
 __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__restrict__ subs, FactWs w, int s,
-                                                                int p, int mid, int *__restrict__ flags, int nsub) {
+                                                                int p, int p0, int mid, int *__restrict__ flags,
+                                                                int nsub) {
     extern __shared__ double2 lds[];
     __shared__ double sv[kPWaves];
     __shared__ int si[kPWaves];
@@ -409,8 +446,12 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__
     const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
     if (k0 >= bs) return;
     const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
-    const double2 *M = chain_M(w, c, q.cur);
-    double *Xr = w.X + (long long)c * 2 * kPanel * bsp, *Xi = Xr + (long long)kPanel * bsp;
+    // the panel's columns: the block itself for the first panel of a
+    // deferred group, else the columns k_factor_colupd brought up to date
+    const int slot = p - p0;
+    const double2 *src = slot == 0 ? chain_M(w, c, q.cur) + (long long)k0 * bs : w.C + (long long)c * kPanel * bsp;
+    const long long sld = slot == 0 ? bs : bsp;
+    double *Xr = ws_x(w, c, slot), *Xi = Xr + (long long)kPanel * bsp;
     int *ppos = w.ppos + (long long)c * bsp, *piv = w.piv + (long long)c * bsp;
     double2 *Ainv = lds;                      // [kPanel][kPanel]
     double2 *U = Ainv + kPanel * kPanel;      // [kPanel][kPanel] pivot rows of the eliminated panel
@@ -428,7 +469,7 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__
     // X = -panel
     for (int e = tid; e < kPanel * bsp; e += kPThreads) {
         const int t = e / bsp, i = e % bsp;
-        const double2 v = (t < bw && i < bs) ? M[(long long)(k0 + t) * bs + i] : make_double2(0, 0);
+        const double2 v = (t < bw && i < bs) ? src[(long long)t * sld + i] : make_double2(0, 0);
         Xr[e] = -v.x;
         Xi[e] = -v.y;
     }
@@ -446,7 +487,7 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__
             const int i = tid + k * kPThreads;
             cv[k] = make_double2(0, 0);
             if (i < bs && ppos_s[i] < 0) {
-                double2 v = M[(long long)(k0 + t) * bs + i];
+                double2 v = src[(long long)t * sld + i];
                 for (int u = 0; u < t; ++u) v = csub(v, cmul(F[(long long)u * bsp + i], U[u * kPanel + t]));
                 cv[k] = v;
                 const double a2 = cabs2(v);
@@ -458,7 +499,7 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__
         if (!(best > tiny2) && status == 0) status = 1 + q.l * bs + k0 + t;
         // the pivot row's eliminated values in columns t .. bw-1
         if (tid >= t && tid < bw) {
-            double2 v = M[(long long)(k0 + tid) * bs + r];
+            double2 v = src[(long long)tid * sld + r];
             for (int u = 0; u < t; ++u) v = csub(v, cmul(F[(long long)u * bsp + r], U[u * kPanel + tid]));
             U[t * kPanel + tid] = v;
         }
@@ -479,7 +520,7 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__
     // A11 (original pivot rows, pivot order) and its in-place inverse by one wave
     for (int e = tid; e < bw * bw; e += kPThreads) {
         const int t = e / bw, u = e % bw;
-        Ainv[t * kPanel + u] = M[(long long)(k0 + u) * bs + R1[t]];
+        Ainv[t * kPanel + u] = src[(long long)u * sld + R1[t]];
     }
     __syncthreads();
     if (tid < 64) {
@@ -530,38 +571,139 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__
     }
 }
 
-// Y = A11^{-1} [pivot rows of S] (kPanel x bsp, zero outside bw x bs, A11^{-1}
-// itself in the panel columns) for the left-looking panel, over kYGroups
-// workgroups per chain: the pivot rows are gathered (one element per row and
-// column of the column-major block) in chunks of 32 columns through LDS.
-constexpr int kYGroups = 8;
-constexpr int kYThreads = 256;
+// Deferred groups.  Panels p0 .. p0 + nd - 1 of a block are factored against
+// the block S as it stood before panel p0; with X_n, Y_n the operands of
+// panel n, the block after panels p0 .. m - 1 is
+//   T_m(i, j) = base(i, j) + sum_{n = lo(i)}^{m-1} [j < 32 (n + 1) or j >= 32 m] X_n(i, :) Y_n(:, j)
+// where a row that is the pivot row of step t of a deferred panel n has
+// base Y_n(t, j) (kept only where the same mask holds) and lo = n + 1, and
+// every other row has base S(i, j), cleared in the columns of panels p0 ..
+// m - 1, and lo = p0: each panel's update zeroes its own columns and
+// replaces its pivot rows by Y, so panel n's product is cleared from the
+// columns of every later panel and a pivot row keeps only what came after
+// its own panel.  m = p0 + nd gives the block after the whole group.
 
-__global__ __launch_bounds__(kYThreads) void k_factor_formy(const SubDesc *__restrict__ subs, FactWs w, int s, int p,
-                                                             int mid) {
-    __shared__ double2 Ai[kPanel * kPanel];
-    __shared__ double2 rows[kPanel * kPanel];  // [u][jj]
-    __shared__ int R1[kPanel];
-    const int c = blockIdx.x / kYGroups, grp = blockIdx.x % kYGroups;
+// Columns of panel p (p0 < p) of T_p, into the chain's C (column t at
+// t * bsp + i): 64 rows x 4 groups of 8 columns per workgroup.
+constexpr int kCThreads = 256;
+
+__global__ __launch_bounds__(kCThreads) void k_factor_colupd(const SubDesc *__restrict__ subs, FactWs w, int s, int p,
+                                                              int p0, int mid) {
+    __shared__ double2 Ys[(kDefer - 1) * kPanel * kPanel];  // [n][v][t] panel p's columns of Y_n
+    const int nrb = w.bsp / 64;
+    const int c = blockIdx.x / nrb, rb = blockIdx.x % nrb;
     const ChainPos q = chain_pos(subs, c, s, mid != 0);
     if (!q.active) return;
     const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
+    if (k0 >= bs || rb * 64 >= bs) return;
+    const int nd = p - p0;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nd * kPanel * kPanel; e += kCThreads) {
+        const int n = e / (kPanel * kPanel), v = (e / kPanel) % kPanel, t = e % kPanel;
+        const double *yr = ws_y(w, c, n);
+        const long long o = (long long)v * bsp + k0 + t;  // k0 + t < bsp
+        Ys[e] = make_double2(yr[o], yr[o + (long long)kPanel * bsp]);
+    }
+    __syncthreads();
+    const int i = rb * 64 + (tid & 63), tg = tid >> 6;
+    if (i >= bs) return;
+    const double2 *M = chain_M(w, c, q.cur);
+    const int pp = w.ppos[(long long)c * bsp + i];
+    const int pn = (pp >= p0 * kPanel && pp < k0) ? pp / kPanel : -1;  // deferred panel the row is a pivot row of
+    double2 acc[8];
+    if (pn >= 0) {
+        const double *yr = ws_y(w, c, pn - p0);
+        const long long o = (long long)(pp - pn * kPanel) * bsp + k0 + 8 * tg;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = make_double2(yr[o + k], yr[o + k + (long long)kPanel * bsp]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int j = k0 + 8 * tg + k;
+            acc[k] = j < bs ? M[(long long)j * bs + i] : make_double2(0, 0);
+        }
+    }
+    for (int n = pn >= 0 ? pn - p0 + 1 : 0; n < nd; ++n) {
+        const double *xr = ws_x(w, c, n), *xi = xr + (long long)kPanel * bsp;
+        const double2 *Yn = Ys + n * kPanel * kPanel + 8 * tg;
+        for (int v = 0; v < kPanel; ++v) {
+            const double2 x = make_double2(xr[(long long)v * bsp + i], xi[(long long)v * bsp + i]);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cfma(acc[k], x, Yn[v * kPanel + k]);
+        }
+    }
+    double2 *C = w.C + (long long)c * kPanel * bsp;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) C[(long long)(8 * tg + k) * bsp + i] = acc[k];
+}
+
+// Y_p = A11^{-1} [pivot rows of T_p] (kPanel x bsp, zero outside bw x bs,
+// A11^{-1} itself in the panel columns) for the left-looking panel, over
+// kYGroups workgroups per chain: the pivot rows of S are gathered (one
+// element per row and column of the column-major block) in chunks of 32
+// columns through LDS, and the products of the deferred panels p0 .. p - 1
+// added to them.
+constexpr int kYGroups = 8;
+constexpr int kYThreads = 256;
+
+static size_t formy_lds_bytes(int nd) {
+    return (size_t)(3 + nd) * kPanel * kPanel * sizeof(double2) + kPanel * sizeof(int);
+}
+
+__global__ __launch_bounds__(kYThreads) void k_factor_formy(const SubDesc *__restrict__ subs, FactWs w, int s, int p,
+                                                             int p0, int mid) {
+    extern __shared__ double2 lds[];
+    const int nd = p - p0;
+    double2 *Ai = lds;                      // [t][u]
+    double2 *rows = Ai + kPanel * kPanel;   // [u][jj]
+    double2 *Ys = rows + kPanel * kPanel;   // [v][jj] a chunk of one deferred panel's Y
+    double2 *Xs = Ys + kPanel * kPanel;     // [n][u][v] deferred panels' X at the pivot rows
+    int *R1 = (int *)(Xs + nd * kPanel * kPanel);
+    const int c = blockIdx.x / kYGroups, grp = blockIdx.x % kYGroups;
+    const ChainPos q = chain_pos(subs, c, s, mid != 0);
+    if (!q.active) return;
+    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel, kd = p0 * kPanel;
     if (k0 >= bs) return;
     const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
     const double2 *M = chain_M(w, c, q.cur);
     const double2 *Ainv = w.Pw + (long long)c * kPanel * bsp;
     const int *piv = w.piv + (long long)c * bsp;
-    double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
+    double *Yr = ws_y(w, c, nd), *Yi = Yr + (long long)kPanel * bsp;
     const int tid = threadIdx.x;
     for (int e = tid; e < kPanel * kPanel; e += kYThreads) Ai[e] = Ainv[e];
     if (tid < kPanel) R1[tid] = tid < bw ? piv[k0 + tid] : 0;
-    const int nch = bsp / kPanel;  // 32-column chunks (bsp is a multiple of 64)
+    __syncthreads();
+    for (int e = tid; e < nd * kPanel * kPanel; e += kYThreads) {
+        const int n = e / (kPanel * kPanel), u = (e / kPanel) % kPanel, v = e % kPanel;
+        const double *xr = ws_x(w, c, n);
+        const long long o = (long long)v * bsp + R1[u];
+        Xs[e] = make_double2(xr[o], xr[o + (long long)kPanel * bsp]);
+    }
+    const int nch = bsp / kPanel;  // 32-column chunks (bsp is a multiple of 64), chunk ch = panel ch's columns
     for (int ch = grp; ch < nch; ch += kYGroups) {
         const int j0 = ch * kPanel;
-        __syncthreads();  // Ai / R1 loaded; the previous chunk's rows consumed
+        __syncthreads();  // Ai / R1 / Xs loaded; the previous chunk's rows consumed
+        const bool in_group = j0 >= kd && j0 < k0;  // columns of a deferred panel: S's entries are cleared
         for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
             const int u = e / kPanel, jj = e % kPanel, j = j0 + jj;
-            rows[e] = (u < bw && j < bs) ? M[(long long)j * bs + R1[u]] : make_double2(0, 0);
+            rows[e] = (u < bw && j < bs && !in_group) ? M[(long long)j * bs + R1[u]] : make_double2(0, 0);
+        }
+        for (int n = 0; n < nd; ++n) {
+            // panel p0 + n's product stands in chunk ch unless p0 + n < ch < p
+            if (ch > p0 + n && ch < p) continue;
+            __syncthreads();  // the previous panel's Ys consumed
+            const double *yr = ws_y(w, c, n);
+            for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
+                const long long o = (long long)(e / kPanel) * bsp + j0 + e % kPanel;
+                Ys[e] = make_double2(yr[o], yr[o + (long long)kPanel * bsp]);
+            }
+            __syncthreads();
+            for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
+                const int u = e / kPanel, jj = e % kPanel;
+                double2 a = rows[e];
+                for (int v = 0; v < kPanel; ++v) cfma(a, Xs[(n * kPanel + u) * kPanel + v], Ys[v * kPanel + jj]);
+                rows[e] = a;  // each element is read and written by the same thread
+            }
         }
         __syncthreads();
         for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
@@ -619,8 +761,8 @@ __global__ __launch_bounds__(NT) void k_factor_panel_r(const SubDesc *__restrict
     if (k0 >= bs) return;
     const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
     const double2 *M = chain_M(w, c, q.cur);
-    double *Xr = w.X + (long long)c * 2 * kPanel * bsp, *Xi = Xr + (long long)kPanel * bsp;
-    double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
+    double *Xr = ws_x(w, c, 0), *Xi = Xr + (long long)kPanel * bsp;
+    double *Yr = ws_y(w, c, 0), *Yi = Yr + (long long)kPanel * bsp;
     int *ppos = w.ppos + (long long)c * bsp, *piv = w.piv + (long long)c * bsp;
     const int tid = threadIdx.x;
     const bool own = tid < bs;
@@ -756,26 +898,25 @@ __global__ __launch_bounds__(NT) void k_factor_panel_r(const SubDesc *__restrict
     }
 }
 
-// Update kernel: S <- S + X Y on the block of every active chain (panel
-// columns start from zero; pivot rows of the panel become Y).  Tile 64 x 64,
-// four waves of 32 x 32, each as 2 x 2 MFMA blocks of 16 x 16.  In an MFMA
-// block, the lane holding column q of row group g keeps rows 4 g .. 4 g + 3
-// (accumulator register r holds block row g + 4 r, so the A operand of
-// lane row i reads matrix row 4 (i % 4) + i / 4).
+// Update kernel: the block after the deferred group p0 .. p0 + nd - 1 (one
+// panel when nd = 1: S <- S + X Y, panel columns starting from zero and
+// pivot rows becoming Y), T_{p0+nd} of the formula above, on the block of
+// every active chain.  Tile 64 x 64, four waves of 32 x 32, each as 2 x 2
+// MFMA blocks of 16 x 16.
 __global__ __launch_bounds__(kUThreads) void k_factor_update(const SubDesc *__restrict__ subs, FactWs w, int s,
-                                                             int p, int mid, int tpd) {
+                                                             int p0, int nd, int mid, int tpd) {
     const int ntile = tpd * tpd;
     const int c = blockIdx.x / ntile, tile = blockIdx.x % ntile;
     const ChainPos q = chain_pos(subs, c, s, mid != 0);
     if (!q.active) return;
-    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
-    if (k0 >= bs) return;
-    const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
+    const int bs = q.bs, bsp = w.bsp, kd = p0 * kPanel;
+    if (kd >= bs) return;
+    const int npb = (bs + kPanel - 1) / kPanel;  // panels of this block
+    const int ne = nd < npb - p0 ? nd : npb - p0;  // deferred panels this block has
+    const int ke = (p0 + ne) * kPanel;           // end of the group's columns
     const int i0 = (tile % tpd) * kUTile, j0 = (tile / tpd) * kUTile;
     if (i0 >= bs || j0 >= bs) return;
     double2 *M = chain_M(w, c, q.cur);
-    const double *Xr = w.X + (long long)c * 2 * kPanel * bsp, *Xi = Xr + (long long)kPanel * bsp;
-    const double *Yr = w.Y + (long long)c * 2 * kPanel * bsp, *Yi = Yr + (long long)kPanel * bsp;
     const int *ppos = w.ppos + (long long)c * bsp;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int g = lane >> 4, qq = lane & 15;
@@ -786,65 +927,81 @@ __global__ __launch_bounds__(kUThreads) void k_factor_update(const SubDesc *__re
     // lane qq + 16 g, register r holds S(i, j) with i = rw + 16 bi + qq and
     // j = cw + 16 bj + g + 4 r, so every load and store instruction covers 16
     // consecutive rows (256 bytes) of 4 columns.
+    int lo[2];  // first deferred slot whose product reaches row rw + 16 bi + qq
     dbl4 re[2][2], im[2][2];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < 2; ++bi) {
+        const int i = rw + 16 * bi + qq;
+        const int pp = i < bs ? ppos[i] : -1;
+        const int pn = (pp >= kd && pp < ke) ? pp / kPanel : -1;  // deferred panel the row is a pivot row of
+        lo[bi] = pn >= 0 ? pn - p0 + 1 : 0;
+        const double *yb = pn >= 0 ? ws_y(w, c, pn - p0) + (long long)(pp - pn * kPanel) * bsp : nullptr;
+        const int ymask = pn >= 0 ? (pn + 1) * kPanel : kd;  // base kept in columns j < ymask or j >= ke
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            const int i = rw + 16 * bi + qq;
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = cw + 16 * bj + g + 4 * r;
-                const bool keep = j < bs && !(j >= k0 && j < k0 + bw);  // panel columns start from zero
-                const double2 v = (keep && i < bs) ? M[(long long)j * bs + i] : make_double2(0, 0);
+                const bool keep = j < bs && i < bs && (j < ymask || j >= ke);
+                double2 v = make_double2(0, 0);
+                if (keep) v = pn >= 0 ? make_double2(yb[j], yb[j + (long long)kPanel * bsp]) : M[(long long)j * bs + i];
                 re[bi][bj][r] = v.x;
                 im[bi][bj][r] = v.y;
             }
-        }
-    const int kend = (bw + 3) & ~3;
-    for (int t0 = 0; t0 < kend; t0 += 4) {
-        const long long ko = (long long)(t0 + g) * bsp;
-        double xr[2], xi[2], yr[2], yi[2];
+    }
+    for (int n = 0; n < ne; ++n) {
+        const double *Xr = ws_x(w, c, n), *Xi = Xr + (long long)kPanel * bsp;
+        const double *Yr = ws_y(w, c, n), *Yi = Yr + (long long)kPanel * bsp;
+        const int kn = (p0 + n) * kPanel;
+        const int bwn = bs - kn < kPanel ? bs - kn : kPanel;
+        const int kend = (bwn + 3) & ~3;
+        // panel n's product: rows from slot lo on, columns outside the later panels of the group
+        bool xs[2], ys[2];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            xr[b] = Xr[ko + rw + 16 * b + qq];  // B operand: X^T(t, i) at lane i + 16 t
-            xi[b] = Xi[ko + rw + 16 * b + qq];
-            yr[b] = Yr[ko + cw + 16 * b + qq];  // A operand: Y^T(j, t) at lane j + 16 t
-            yi[b] = Yi[ko + cw + 16 * b + qq];
+            xs[b] = n >= lo[b];
+            const int j = cw + 16 * b + qq;
+            ys[b] = j < kn + kPanel || j >= ke;
         }
+        for (int t0 = 0; t0 < kend; t0 += 4) {
+            const long long ko = (long long)(t0 + g) * bsp;
+            double xr[2], xi[2], yr[2], yi[2];
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xr[bi], re[bi][bj], 0, 0, 0);
-                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], xr[bi], im[bi][bj], 0, 0, 0);
+            for (int b = 0; b < 2; ++b) {
+                const double ar = Xr[ko + rw + 16 * b + qq], ai = Xi[ko + rw + 16 * b + qq];
+                const double br = Yr[ko + cw + 16 * b + qq], bi_ = Yi[ko + cw + 16 * b + qq];
+                xr[b] = xs[b] ? ar : 0.0;  // B operand: X^T(t, i) at lane i + 16 t
+                xi[b] = xs[b] ? ai : 0.0;
+                yr[b] = ys[b] ? br : 0.0;  // A operand: Y^T(j, t) at lane j + 16 t
+                yi[b] = ys[b] ? bi_ : 0.0;
             }
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+            for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], -xi[bi], re[bi][bj], 0, 0, 0);
-                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xi[bi], im[bi][bj], 0, 0, 0);
-            }
+                for (int bj = 0; bj < 2; ++bj) {
+                    re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xr[bi], re[bi][bj], 0, 0, 0);
+                    im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], xr[bi], im[bi][bj], 0, 0, 0);
+                }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], -xi[bi], re[bi][bj], 0, 0, 0);
+                    im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xi[bi], im[bi][bj], 0, 0, 0);
+                }
+        }
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
         const int i = rw + 16 * bi + qq;
         if (i >= bs) continue;
-        const int pr = ppos[i];
-        const bool pivot_row = pr >= k0 && pr < k0 + bw;  // pivot rows become Y
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = cw + 16 * bj + g + 4 * r;
                 if (j >= bs) continue;
-                double2 v = make_double2(re[bi][bj][r], im[bi][bj][r]);
-                if (pivot_row) {
-                    const long long yo = (long long)(pr - k0) * bsp + j;
-                    v = make_double2(Yr[yo], Yi[yo]);
-                }
-                M[(long long)j * bs + i] = v;
+                M[(long long)j * bs + i] = make_double2(re[bi][bj][r], im[bi][bj][r]);
             }
     }
 }
@@ -944,7 +1101,12 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
     if (use_ll) {
         e = hipFuncSetAttribute((const void *)k_factor_panel_ll, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_ll);
         if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void *)k_factor_formy, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)formy_lds_bytes(w.slots - 1));
+        if (e != hipSuccess) return e;
     }
+    // panels per deferred group (the left-looking path only)
+    const int D = use_ll ? w.slots : 1;
     e = launch_fill_zero(w.mxb, (long long)2 * nc * sizeof(unsigned long long), h->stream);
     if (e != hipSuccess) return e;
     e = launch_fill_zero(h->d_flags, (long long)3 * P.nsub * sizeof(int), h->stream);
@@ -956,20 +1118,28 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
             k_factor_formmid<<<P.nsub * groups, kEThreads, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, w,
                                                                           groups);
         const int ss = mid ? 0 : s;
-        for (int p = 0; p < npan; ++p) {
-            if (panel_kind == 0)
-                k_factor_panel_r<256><<<nc, 256, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
-            else if (panel_kind == 1)
-                k_factor_panel_r<512><<<nc, 512, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
-            else if (use_ll)
-                k_factor_panel_ll<<<nc, kPThreads, lds_ll, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
-            else if (pw_in_lds)
-                k_factor_panel<true><<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
-            else
-                k_factor_panel<false><<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags,
-                                                                         P.nsub);
-            if (use_ll) k_factor_formy<<<nc * kYGroups, kYThreads, 0, h->stream>>>(h->d_subs, w, ss, p, mid);
-            k_factor_update<<<nc * tpd * tpd, kUThreads, 0, h->stream>>>(h->d_subs, w, ss, p, mid, tpd);
+        for (int p0 = 0; p0 < npan; p0 += D) {
+            const int nd = npan - p0 < D ? npan - p0 : D;
+            for (int p = p0; p < p0 + nd; ++p) {
+                if (panel_kind == 0)
+                    k_factor_panel_r<256><<<nc, 256, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
+                else if (panel_kind == 1)
+                    k_factor_panel_r<512><<<nc, 512, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
+                else if (use_ll) {
+                    if (p > p0)
+                        k_factor_colupd<<<nc * (w.bsp / 64), kCThreads, 0, h->stream>>>(h->d_subs, w, ss, p, p0, mid);
+                    k_factor_panel_ll<<<nc, kPThreads, lds_ll, h->stream>>>(h->d_subs, w, ss, p, p0, mid, h->d_flags,
+                                                                             P.nsub);
+                    k_factor_formy<<<nc * kYGroups, kYThreads, formy_lds_bytes(p - p0), h->stream>>>(h->d_subs, w, ss,
+                                                                                                  p, p0, mid);
+                } else if (pw_in_lds)
+                    k_factor_panel<true><<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags,
+                                                                            P.nsub);
+                else
+                    k_factor_panel<false><<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags,
+                                                                             P.nsub);
+            }
+            k_factor_update<<<nc * tpd * tpd, kUThreads, 0, h->stream>>>(h->d_subs, w, ss, p0, nd, mid, tpd);
         }
         k_factor_store<T><<<nc * groups, kEThreads, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, A, w, ss, mid,
                                                                     groups, P.mma ? 1 : 0, (T *)h->d_W);

@@ -389,6 +389,36 @@ def test_3d_planes_above_512(M):
         g.close()
 
 
+def test_3d_uneven_planes_deferred_groups():
+    """Plane blocks of 560, 595 and 630 unknowns in one handle (3x1x3
+    subdomains of a 30^3 grid): 18, 19 and 20 panels, so with groups of four
+    deferred panels the smaller blocks end their last group early (two and
+    three panels) and every block ends on a partial panel.  Local solves vs
+    the oracle's, and their residuals under the oracle's subdomain
+    operators."""
+    w = di.small_3d(M=30, N=(3, 1, 3), n_pml=3, n_ov=2, nrhs=2, seed=6)
+    o = Oracle(w.dim, w.M, w.h, w.n_pml, w.sigma0, w.N, w.n_ov, w.k2)
+    bs = set()
+    for a in range(o.nsub):
+        d = o.subdomain(a)
+        bs.add((d["ext_hi"][0] - d["ext_lo"][0] + 1) * (d["ext_hi"][1] - d["ext_lo"][1] + 1))
+    assert bs == {560, 595, 630}
+    gin = di.random_field((2, o.etot), seed=83)
+    xo = o.local_solve(gin)
+    for mixed, tol in ((False, 1e-10), (True, 5e-5)):
+        g = ddm.HelmholtzDDM(ddm.Problem.from_workload(w, mixed=mixed), _t(w.k2.reshape(-1)), 2)
+        xg = _n(g.local_solve(_t(gin)))
+        assert relerr(xg, xo, axis=1) < tol, mixed
+        if not mixed:
+            for a in range(o.nsub):
+                d = o.subdomain(a)
+                sl = slice(d["off"], d["off"] + d["n"])
+                for q in range(2):
+                    r = o.apply_local(a, xg[q, sl]) - gin[q, sl]
+                    assert np.linalg.norm(r) < 1e-12 * np.linalg.norm(gin[q, sl]), (a, q)
+        g.close()
+
+
 @pytest.mark.parametrize("case,mixed", [("2d-3x3-layered", False), ("2d-3x3-layered", True), ("3d-2x2x2", False)])
 def test_step_graph_replays_match_eager(case, mixed):
     """The stationary solve replays captured step graphs (one per ring
