@@ -82,7 +82,7 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int, slots: int = 16, poll_steps: int = 1,
                  device: str = "cuda:0", clock: Callable[[], float] = time.perf_counter,
-                 plans=None, async_build: bool = True):
+                 plans=None, async_build: bool = True, plan_scope: str = ""):
         self.budget = int(hbm_budget_bytes)
         self.slots = int(slots)
         self.poll_steps = int(poll_steps)
@@ -90,6 +90,7 @@ class Server:
         self._clock = clock
         self._t0 = clock()
         self.plans = plans              # tuning.PlanCache or None
+        self.plan_scope = plan_scope    # cache scope the plans were tuned in (tuning.scope_of)
         self.cache: "collections.OrderedDict[Tuple, _Entry]" = collections.OrderedDict()
         self.pending: Dict[Tuple, collections.deque] = collections.defaultdict(collections.deque)
         self.building: Dict[Tuple, Tuple[concurrent.futures.Future, int, float]] = {}
@@ -138,7 +139,7 @@ class Server:
             applied = False
             if self.plans is not None:
                 from .tuning import apply_plan, plan_key
-                plan = self.plans.get(plan_key(solver, self.slots))
+                plan = self.plans.get(plan_key(solver, self.slots, self.plan_scope))
                 if plan is not None:
                     apply_plan(solver, plan)
                     applied = True

@@ -43,12 +43,16 @@ def _shape(s: HelmholtzDDM) -> Tuple[int, int]:
     return bs_max, nb_max
 
 
-def plan_key(s: HelmholtzDDM, nrhs: int) -> str:
+def plan_key(s: HelmholtzDDM, nrhs: int, scope: str = "") -> str:
+    """Cache key of a shape; scope names a restricted search (e.g. "onedir")."""
     props = torch.cuda.get_device_properties(s.device)
     arch = getattr(props, "gcnArchName", None) or props.name
     bs_max, nb_max = _shape(s)
-    return "|".join([str(arch).split(":")[0], "dim%d" % s.problem.dim, "bs%d" % bs_max, "nb%d" % nb_max,
-                     "nsub%d" % s.nsub, "nrhs%d" % nrhs, "mixed" if s.problem.mixed else "fp64"])
+    parts = [str(arch).split(":")[0], "dim%d" % s.problem.dim, "bs%d" % bs_max, "nb%d" % nb_max,
+             "nsub%d" % s.nsub, "nrhs%d" % nrhs, "mixed" if s.problem.mixed else "fp64"]
+    if scope:
+        parts.append(scope)
+    return "|".join(parts)
 
 
 class PlanCache:
@@ -82,6 +86,12 @@ class PlanCache:
             os.replace(tmp, self.path)
 
 
+def scope_of(layouts: Tuple[bool, ...]) -> str:
+    """Cache scope of a layout restriction ("" for the full search)."""
+    t = tuple(sorted(set(bool(x) for x in layouts)))
+    return {(False, True): "", (False,): "onedir", (True,): "twisted"}[t]
+
+
 def apply_plan(s: HelmholtzDDM, plan: dict):
     """Put the handle in the plan's configuration and factorise it once in
     that configuration (the layout and the order of the stored inverses
@@ -93,13 +103,19 @@ def apply_plan(s: HelmholtzDDM, plan: dict):
 
 
 def tune(s: HelmholtzDDM, nrhs: Optional[int] = None, reps: int = 3, cache: Optional[PlanCache] = None,
-         force: bool = False) -> dict:
+         force: bool = False, layouts: Tuple[bool, ...] = (True, False)) -> dict:
     """Time every admissible (layout, variant, tile) on this handle, apply the
     fastest and record it.  With a cache hit (and not force) the cached plan
-    is applied without timing.  Returns the plan: twisted, variant,
-    chain_tile, ms (its time per local solve) and the table of all timings."""
+    is applied without timing.  layouts restricts the factor layouts tried
+    (True = two-ended, False = one-directional): the two-ended substitution
+    waits between the two chains of a subdomain and is launched
+    cooperatively, and a cooperative launch does not run beside kernels of
+    other streams, so a caller that runs many handles at once may want
+    (False,) only.  Returns the plan: twisted, variant, chain_tile, ms (its
+    time per local solve) and the table of all timings."""
     nrhs = int(nrhs or s.nrhs_max)
-    key = plan_key(s, nrhs)
+    layouts = tuple(bool(t) for t in layouts)
+    key = plan_key(s, nrhs, scope_of(layouts))
     if cache is not None and not force:
         plan = cache.get(key)
         if plan is not None:
@@ -107,7 +123,7 @@ def tune(s: HelmholtzDDM, nrhs: Optional[int] = None, reps: int = 3, cache: Opti
             plan["cached"] = True
             return plan
     table: List[dict] = []
-    for twisted in (True, False):
+    for twisted in layouts:
         try:
             s.set_factor_layout(twisted)
         except DDMError:
