@@ -14,7 +14,7 @@
 // pivoting:
 //   * panels of kPanel columns; a panel kernel (one workgroup per chain)
 //     picks the panel's pivot rows by unblocked elimination of a copy of the
-//     panel (left-looking for blocks above 512 rows), inverts the kPanel x
+//     panel (by sub-panels for blocks above 512 rows), inverts the kPanel x
 //     kPanel pivot block A11 and forms
 //     Y = A11^{-1} [pivot rows of S] and X = -[panel columns of S], pivot rows
 //     zeroed;
@@ -142,11 +142,11 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // panel's columns and pivot rows brought up to date by narrow products), then
 // one update of rank kDefer * kPanel applies all of them.
 constexpr int kDefer = 4;
-constexpr int kLLRows = 8;  // rows per thread of the left-looking panel kernel
+constexpr int kSPRows = 4096;  // largest block of the sub-panel kernel
 
-// deferral goes with the left-looking panel (blocks of 513 .. kLLRows * kPThreads rows)
+// deferral goes with the sub-panel kernel (blocks of 513 .. kSPRows rows)
 static int defer_slots(const Plan &P) {
-    return P.bs_max > 512 && P.bs_max <= kLLRows * kPThreads ? kDefer : 1;
+    return P.bs_max > 512 && P.bs_max <= kSPRows ? kDefer : 1;
 }
 
 // Per-chain factor workspace (chain c = 2 * subdomain + direction).
@@ -422,155 +422,6 @@ __global__ __launch_bounds__(kPThreads) void k_factor_panel(const SubDesc *__res
     }
 }
 
-// Left-looking panel kernel for blocks of more than 512 rows (kLLRows rows
-// per thread at most).  The right-looking elimination above rewrites the
-// whole bs x kPanel working panel at every pivot step; here column t of the
-// eliminated panel is formed only when it becomes the pivot column, from the
-// stored multipliers F (the panel's L, in the workspace) and the pivot rows'
-// eliminated values U (in LDS):
-//   col_t(i) = S(i, k0 + t) - sum_{u < t} F_u(i) U(u, t),   F_t(i) = col_t(i) / U(t, t),
-//   U(t, t') = col_t'(r_t) (the same sum for the pivot row, t' >= t).
-// The pivots are those of partial pivoting on the panel.  A11^{-1} is the
-// in-place Gauss-Jordan inverse (pivots on the diagonal, in pivot order) of
-// the panel's original pivot rows; Y and X are formed as above.
-
-__global__ __launch_bounds__(kPThreads) void k_factor_panel_ll(const SubDesc *__restrict__ subs, FactWs w, int s,
-                                                                int p, int p0, int mid, int *__restrict__ flags,
-                                                                int nsub) {
-    extern __shared__ double2 lds[];
-    __shared__ double sv[kPWaves];
-    __shared__ int si[kPWaves];
-    const int c = blockIdx.x;
-    const ChainPos q = chain_pos(subs, c, s, mid != 0);
-    if (!q.active) return;
-    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
-    if (k0 >= bs) return;
-    const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
-    // the panel's columns: the block itself for the first panel of a
-    // deferred group, else the columns k_factor_colupd brought up to date
-    const int slot = p - p0;
-    const double2 *src = slot == 0 ? chain_M(w, c, q.cur) + (long long)k0 * bs : w.C + (long long)c * kPanel * bsp;
-    const long long sld = slot == 0 ? bs : bsp;
-    double *Xr = ws_x(w, c, slot), *Xi = Xr + (long long)kPanel * bsp;
-    int *ppos = w.ppos + (long long)c * bsp, *piv = w.piv + (long long)c * bsp;
-    double2 *Ainv = lds;                      // [kPanel][kPanel]
-    double2 *U = Ainv + kPanel * kPanel;      // [kPanel][kPanel] pivot rows of the eliminated panel
-    int *R1 = (int *)(U + kPanel * kPanel);   // [kPanel]
-    int *ppos_s = R1 + kPanel;                // [bsp]
-    double2 *F = w.Pw + (long long)c * kPanel * bsp;  // [kPanel][bsp] multipliers
-    const int tid = threadIdx.x;
-    const double mx = slot_read(w.mxb + 2 * c + q.cur);
-    if (p == 0) {
-        for (int i = tid; i < bsp; i += kPThreads) ppos_s[i] = -1;
-        if (tid == 0) w.mxb[2 * c + (q.cur ^ 1)] = 0ull;  // the store of this step fills it
-    } else {
-        for (int i = tid; i < bsp; i += kPThreads) ppos_s[i] = ppos[i];
-    }
-    // X = -panel
-    for (int e = tid; e < kPanel * bsp; e += kPThreads) {
-        const int t = e / bsp, i = e % bsp;
-        const double2 v = (t < bw && i < bs) ? src[(long long)t * sld + i] : make_double2(0, 0);
-        Xr[e] = -v.x;
-        Xi[e] = -v.y;
-    }
-    __syncthreads();
-    double tiny2 = (double)bs * DBL_EPSILON;
-    tiny2 = tiny2 * tiny2 * mx;
-    int status = 0;
-    for (int t = 0; t < bw; ++t) {
-        // column t at this thread's candidate rows, and the best of them
-        double2 cv[kLLRows];
-        double best = -1.0;
-        int bi = bs;
-#pragma unroll
-        for (int k = 0; k < kLLRows; ++k) {
-            const int i = tid + k * kPThreads;
-            cv[k] = make_double2(0, 0);
-            if (i < bs && ppos_s[i] < 0) {
-                double2 v = src[(long long)t * sld + i];
-                for (int u = 0; u < t; ++u) v = csub(v, cmul(F[(long long)u * bsp + i], U[u * kPanel + t]));
-                cv[k] = v;
-                const double a2 = cabs2(v);
-                if (a2 > best) { best = a2; bi = i; }
-            }
-        }
-        block_argmax_n<kPWaves>(best, bi, sv, si);
-        const int r = bi < bs ? bi : bs - 1;  // no finite candidate: flagged below, indices stay in range
-        if (!(best > tiny2) && status == 0) status = 1 + q.l * bs + k0 + t;
-        // the pivot row's eliminated values in columns t .. bw-1
-        if (tid >= t && tid < bw) {
-            double2 v = src[(long long)tid * sld + r];
-            for (int u = 0; u < t; ++u) v = csub(v, cmul(F[(long long)u * bsp + r], U[u * kPanel + tid]));
-            U[t * kPanel + tid] = v;
-        }
-        if (tid == 0) {
-            ppos_s[r] = k0 + t;
-            R1[t] = r;
-        }
-        __syncthreads();
-        // multipliers of the remaining candidates
-        const double2 pinv = cinv(U[t * kPanel + t]);
-#pragma unroll
-        for (int k = 0; k < kLLRows; ++k) {
-            const int i = tid + k * kPThreads;
-            if (i < bs && ppos_s[i] < 0) F[(long long)t * bsp + i] = cmul(cv[k], pinv);
-        }
-        __syncthreads();
-    }
-    // A11 (original pivot rows, pivot order) and its in-place inverse by one wave
-    for (int e = tid; e < bw * bw; e += kPThreads) {
-        const int t = e / bw, u = e % bw;
-        Ainv[t * kPanel + u] = src[(long long)u * sld + R1[t]];
-    }
-    __syncthreads();
-    if (tid < 64) {
-        constexpr int kE = kPanel * kPanel / 64;  // elements per lane
-        for (int t = 0; t < bw; ++t) {
-            const double2 pi = cinv(Ainv[t * kPanel + t]);
-            double2 nv[kE];
-#pragma unroll
-            for (int k = 0; k < kE; ++k) {
-                const int e = tid + 64 * k, i = e / kPanel, u = e % kPanel;
-                nv[k] = make_double2(0, 0);
-                if (i < bw && u < bw) {
-                    const double2 rt = u == t ? pi : cmul(Ainv[t * kPanel + u], pi);  // new row t
-                    if (i == t) {
-                        nv[k] = rt;
-                    } else {
-                        const double2 f = Ainv[i * kPanel + t];
-                        nv[k] = u == t ? make_double2(-(f.x * pi.x - f.y * pi.y), -(f.x * pi.y + f.y * pi.x))
-                                       : csub(Ainv[i * kPanel + u], cmul(f, rt));
-                    }
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int k = 0; k < kE; ++k) {
-                const int e = tid + 64 * k, i = e / kPanel, u = e % kPanel;
-                if (i < bw && u < bw) Ainv[i * kPanel + u] = nv[k];
-            }
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS writes are done
-            __builtin_amdgcn_wave_barrier();
-        }
-    }
-    __syncthreads();
-    // A11^{-1} to the workspace (the multipliers are done): Y is formed by
-    // k_factor_formy over several workgroups per chain
-    for (int e = tid; e < kPanel * kPanel; e += kPThreads) F[e] = Ainv[e];
-    // pivot rows take no part in X
-    for (int e = tid; e < bw * kPanel; e += kPThreads) {
-        const int t = e / kPanel, u = e % kPanel;
-        Xr[(long long)u * bsp + R1[t]] = 0.0;
-        Xi[(long long)u * bsp + R1[t]] = 0.0;
-    }
-    for (int i = tid; i < bsp; i += kPThreads) ppos[i] = ppos_s[i];
-    if (tid < bw) piv[k0 + tid] = R1[tid];
-    if (tid == 0 && status) {
-        int *fl = flags + (mid ? 2 * nsub + q.a : c);
-        if (*fl == 0) *fl = status;
-    }
-}
-
 // Deferred groups.  Panels p0 .. p0 + nd - 1 of a block are factored against
 // the block S as it stood before panel p0; with X_n, Y_n the operands of
 // panel n, the block after panels p0 .. m - 1 is
@@ -598,11 +449,19 @@ __global__ __launch_bounds__(kCThreads) void k_factor_colupd(const SubDesc *__re
     if (k0 >= bs || rb * 64 >= bs) return;
     const int nd = p - p0;
     const int tid = threadIdx.x;
-    for (int e = tid; e < nd * kPanel * kPanel; e += kCThreads) {
-        const int n = e / (kPanel * kPanel), v = (e / kPanel) % kPanel, t = e % kPanel;
+    for (int n = 0; n < nd; ++n) {
+        // constant trip count: the loads issued before their LDS stores
+        constexpr int kY = kPanel * kPanel / kCThreads;
         const double *yr = ws_y(w, c, n);
-        const long long o = (long long)v * bsp + k0 + t;  // k0 + t < bsp
-        Ys[e] = make_double2(yr[o], yr[o + (long long)kPanel * bsp]);
+        double2 sy[kY];
+#pragma unroll
+        for (int m = 0; m < kY; ++m) {
+            const int e = tid + m * kCThreads, v = e / kPanel, t = e % kPanel;
+            const long long o = (long long)v * bsp + k0 + t;  // k0 + t < bsp
+            sy[m] = make_double2(yr[o], yr[o + (long long)kPanel * bsp]);
+        }
+#pragma unroll
+        for (int m = 0; m < kY; ++m) Ys[n * kPanel * kPanel + tid + m * kCThreads] = sy[m];
     }
     __syncthreads();
     const int i = rb * 64 + (tid & 63), tg = tid >> 6;
@@ -617,19 +476,28 @@ __global__ __launch_bounds__(kCThreads) void k_factor_colupd(const SubDesc *__re
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[k] = make_double2(yr[o + k], yr[o + k + (long long)kPanel * bsp]);
     } else {
+        // unconditional loads (clamped columns), zeroed past the block
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int j = k0 + 8 * tg + k;
-            acc[k] = j < bs ? M[(long long)j * bs + i] : make_double2(0, 0);
+            acc[k] = M[(long long)(j < bs ? j : bs - 1) * bs + i];
         }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k0 + 8 * tg + k >= bs) acc[k] = make_double2(0, 0);
     }
     for (int n = pn >= 0 ? pn - p0 + 1 : 0; n < nd; ++n) {
         const double *xr = ws_x(w, c, n), *xi = xr + (long long)kPanel * bsp;
         const double2 *Yn = Ys + n * kPanel * kPanel + 8 * tg;
-        for (int v = 0; v < kPanel; ++v) {
-            const double2 x = make_double2(xr[(long long)v * bsp + i], xi[(long long)v * bsp + i]);
+        for (int v0 = 0; v0 < kPanel; v0 += 8) {
+            double2 x[8];  // one batch of loads in flight together
 #pragma unroll
-            for (int k = 0; k < 8; ++k) cfma(acc[k], x, Yn[v * kPanel + k]);
+            for (int vv = 0; vv < 8; ++vv)
+                x[vv] = make_double2(xr[(long long)(v0 + vv) * bsp + i], xi[(long long)(v0 + vv) * bsp + i]);
+#pragma unroll
+            for (int vv = 0; vv < 8; ++vv)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) cfma(acc[k], x[vv], Yn[(v0 + vv) * kPanel + k]);
         }
     }
     double2 *C = w.C + (long long)c * kPanel * bsp;
@@ -638,82 +506,114 @@ __global__ __launch_bounds__(kCThreads) void k_factor_colupd(const SubDesc *__re
 }
 
 // Y_p = A11^{-1} [pivot rows of T_p] (kPanel x bsp, zero outside bw x bs,
-// A11^{-1} itself in the panel columns) for the left-looking panel, over
-// kYGroups workgroups per chain: the pivot rows of S are gathered (one
-// element per row and column of the column-major block) in chunks of 32
-// columns through LDS, and the products of the deferred panels p0 .. p - 1
-// added to them.
-constexpr int kYGroups = 8;
+// A11^{-1} itself in the panel columns) for the sub-panel kernel: one
+// workgroup per chain and 64 columns (two chunks of 32).  The pivot rows of
+// S are gathered (one element per row and column of the column-major block)
+// into registers, the products of the deferred panels p0 .. p - 1 added to
+// them (each panel's X at the pivot rows and its Y in these columns staged
+// in LDS), and the rows multiplied by A11^{-1}.
 constexpr int kYThreads = 256;
-
-static size_t formy_lds_bytes(int nd) {
-    return (size_t)(3 + nd) * kPanel * kPanel * sizeof(double2) + kPanel * sizeof(int);
-}
+constexpr size_t kFormyLds = 4 * kPanel * kPanel * sizeof(double2) + kPanel * sizeof(int);
 
 __global__ __launch_bounds__(kYThreads) void k_factor_formy(const SubDesc *__restrict__ subs, FactWs w, int s, int p,
                                                              int p0, int mid) {
     extern __shared__ double2 lds[];
-    const int nd = p - p0;
     double2 *Ai = lds;                      // [t][u]
-    double2 *rows = Ai + kPanel * kPanel;   // [u][jj]
-    double2 *Ys = rows + kPanel * kPanel;   // [v][jj] a chunk of one deferred panel's Y
-    double2 *Xs = Ys + kPanel * kPanel;     // [n][u][v] deferred panels' X at the pivot rows
-    int *R1 = (int *)(Xs + nd * kPanel * kPanel);
-    const int c = blockIdx.x / kYGroups, grp = blockIdx.x % kYGroups;
+    double2 *Xs = Ai + kPanel * kPanel;     // [u][v] one deferred panel's X at the pivot rows
+    double2 *Ys = Xs + kPanel * kPanel;     // [2][v][jj] its Y in the two chunks; then the rows [2][u][jj]
+    int *R1 = (int *)(Ys + 2 * kPanel * kPanel);
+    const int nfg = w.bsp / 64;
+    const int c = blockIdx.x / nfg, j0 = (blockIdx.x % nfg) * 64;
     const ChainPos q = chain_pos(subs, c, s, mid != 0);
     if (!q.active) return;
-    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel, kd = p0 * kPanel;
+    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
     if (k0 >= bs) return;
     const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
+    const int nd = p - p0;
     const double2 *M = chain_M(w, c, q.cur);
     const double2 *Ainv = w.Pw + (long long)c * kPanel * bsp;
     const int *piv = w.piv + (long long)c * bsp;
     double *Yr = ws_y(w, c, nd), *Yi = Yr + (long long)kPanel * bsp;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < kPanel * kPanel; e += kYThreads) Ai[e] = Ainv[e];
+    const int tid = threadIdx.x, jj = tid % kPanel;
+    {
+        constexpr int kA = kPanel * kPanel / kYThreads;
+        double2 sa[kA];
+#pragma unroll
+        for (int m = 0; m < kA; ++m) sa[m] = Ainv[tid + m * kYThreads];
+#pragma unroll
+        for (int m = 0; m < kA; ++m) Ai[tid + m * kYThreads] = sa[m];
+    }
     if (tid < kPanel) R1[tid] = tid < bw ? piv[k0 + tid] : 0;
     __syncthreads();
-    for (int e = tid; e < nd * kPanel * kPanel; e += kYThreads) {
-        const int n = e / (kPanel * kPanel), u = (e / kPanel) % kPanel, v = e % kPanel;
-        const double *xr = ws_x(w, c, n);
-        const long long o = (long long)v * bsp + R1[u];
-        Xs[e] = make_double2(xr[o], xr[o + (long long)kPanel * bsp]);
+    // thread elements: rows u = tid / 32 + 8 k of the two chunks, column jj
+    double2 acc[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int pc = j0 / kPanel + h;                 // the panel whose columns the chunk holds
+        const bool cleared = pc >= p0 && pc < p;        // an earlier deferred panel's columns
+        const int j = j0 + kPanel * h + jj;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int u = tid / kPanel + 8 * k;
+            acc[h][k] = (u < bw && j < bs && !cleared) ? M[(long long)j * bs + R1[u]] : make_double2(0, 0);
+        }
     }
-    const int nch = bsp / kPanel;  // 32-column chunks (bsp is a multiple of 64), chunk ch = panel ch's columns
-    for (int ch = grp; ch < nch; ch += kYGroups) {
-        const int j0 = ch * kPanel;
-        __syncthreads();  // Ai / R1 / Xs loaded; the previous chunk's rows consumed
-        const bool in_group = j0 >= kd && j0 < k0;  // columns of a deferred panel: S's entries are cleared
-        for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
-            const int u = e / kPanel, jj = e % kPanel, j = j0 + jj;
-            rows[e] = (u < bw && j < bs && !in_group) ? M[(long long)j * bs + R1[u]] : make_double2(0, 0);
+    for (int n = 0; n < nd; ++n) {
+        __syncthreads();  // the previous panel's Xs / Ys consumed
+        const double *xr = ws_x(w, c, n), *yr = ws_y(w, c, n);
+        // constant trip counts: every load of the staging issued before its LDS stores
+        constexpr int kXs = kPanel * kPanel / kYThreads, kYs = 2 * kPanel * kPanel / kYThreads;
+        double2 sx[kXs], sy[kYs];
+#pragma unroll
+        for (int m = 0; m < kXs; ++m) {
+            const int e = tid + m * kYThreads;
+            const long long o = (long long)(e % kPanel) * bsp + R1[e / kPanel];
+            sx[m] = make_double2(xr[o], xr[o + (long long)kPanel * bsp]);
         }
-        for (int n = 0; n < nd; ++n) {
-            // panel p0 + n's product stands in chunk ch unless p0 + n < ch < p
-            if (ch > p0 + n && ch < p) continue;
-            __syncthreads();  // the previous panel's Ys consumed
-            const double *yr = ws_y(w, c, n);
-            for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
-                const long long o = (long long)(e / kPanel) * bsp + j0 + e % kPanel;
-                Ys[e] = make_double2(yr[o], yr[o + (long long)kPanel * bsp]);
-            }
-            __syncthreads();
-            for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
-                const int u = e / kPanel, jj = e % kPanel;
-                double2 a = rows[e];
-                for (int v = 0; v < kPanel; ++v) cfma(a, Xs[(n * kPanel + u) * kPanel + v], Ys[v * kPanel + jj]);
-                rows[e] = a;  // each element is read and written by the same thread
-            }
+#pragma unroll
+        for (int m = 0; m < kYs; ++m) {
+            const int e = tid + m * kYThreads;
+            const int h = e / (kPanel * kPanel), v = (e / kPanel) % kPanel;
+            const long long o = (long long)v * bsp + j0 + kPanel * h + e % kPanel;  // < kPanel * bsp
+            sy[m] = make_double2(yr[o], yr[o + (long long)kPanel * bsp]);
         }
+#pragma unroll
+        for (int m = 0; m < kXs; ++m) Xs[tid + m * kYThreads] = sx[m];
+#pragma unroll
+        for (int m = 0; m < kYs; ++m) Ys[tid + m * kYThreads] = sy[m];
         __syncthreads();
-        for (int e = tid; e < kPanel * kPanel; e += kYThreads) {
-            const int t = e / kPanel, jj = e % kPanel, j = j0 + jj;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // panel p0 + n's product stands in chunk pc unless p0 + n < pc < p
+            const int pc = j0 / kPanel + h;
+            if (pc > p0 + n && pc < p) continue;
+            const double2 *yh = Ys + h * kPanel * kPanel + jj;
+            for (int v = 0; v < kPanel; ++v) {
+                const double2 yv = yh[v * kPanel];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) cfma(acc[h][k], Xs[(tid / kPanel + 8 * k) * kPanel + v], yv);
+            }
+        }
+    }
+    __syncthreads();  // Ys free: the rows go there
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Ys[(h * kPanel + tid / kPanel + 8 * k) * kPanel + jj] = acc[h][k];
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int j = j0 + kPanel * h + jj;
+        const double2 *rows = Ys + h * kPanel * kPanel + jj;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int t = tid / kPanel + 8 * k;
             double2 y = make_double2(0, 0);
             if (t < bw && j < bs) {
                 if (j >= k0 && j < k0 + bw) {
                     y = Ai[t * kPanel + (j - k0)];
                 } else {
-                    for (int u = 0; u < bw; ++u) cfma(y, Ai[t * kPanel + u], rows[u * kPanel + jj]);
+                    for (int u = 0; u < bw; ++u) cfma(y, Ai[t * kPanel + u], rows[u * kPanel]);
                 }
             }
             Yr[(long long)t * bsp + j] = y.x;
@@ -728,6 +628,13 @@ __global__ __launch_bounds__(kYThreads) void k_factor_formy(const SubDesc *__res
 __device__ inline unsigned pivot_key(double v2, int row) {
     return (__float_as_uint((float)v2) & ~1023u) | (unsigned)(1023 - row);
 }
+
+// Workgroup barrier that orders LDS only: this wave's LDS accesses are done,
+// then every wave of the group is here.  Global accesses in flight (the
+// multipliers stored at a pivot step) are not waited for, unlike
+// __syncthreads(); the "memory" clobber keeps the compiler from moving
+// memory accesses across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Max of a 32-bit value over the wave (DPP within rows of 16 lanes, then the
 // four row results), returned to every lane.
@@ -898,6 +805,252 @@ __global__ __launch_bounds__(NT) void k_factor_panel_r(const SubDesc *__restrict
     }
 }
 
+// Panel kernel for blocks of 513 .. 4096 rows by sub-panels of SW columns:
+// thread tid owns rows tid + NT k (k < NK) and keeps their values in
+// the current sub-panel's columns in registers.  A sub-panel's columns are
+// formed left-looking from the multipliers F of the earlier sub-panels (in
+// the workspace, one batch of loads per UB of them) and the pivot rows'
+// eliminated values U (LDS),
+//   v(i, c) = S(i, c) - sum_{u < c0} F_u(i) U(u, c),
+// then eliminated right-looking, one pivot step after another: a wave-level
+// max of the candidates' pivot keys, each wave's best row staged in LDS, one
+// barrier, every thread takes the best of the waves' candidates and updates
+// its rows.  At the end of a sub-panel the pivot rows it chose get their U
+// in the later columns, U(t, c) = S(r_t, c) - sum_{u < t} F_u(r_t) U(u, c).
+// The pivots are those of partial pivoting on the panel (magnitudes compared
+// to 2^-12 relative, ties to the smaller row).  A11^{-1}, X and the
+// workspace outputs: X = -(the panel's columns) with its pivot rows zero,
+// A11^{-1} (A11 = the panel's pivot rows in pivot order, inverted by
+// Gauss-Jordan with all threads) at the start of the multiplier area for
+// k_factor_formy, the pivot steps of the rows and the rows of the steps.
+template <int NT, int NK, int SW, int UB>
+__global__ __launch_bounds__(NT) void k_factor_panel_sp(const SubDesc *__restrict__ subs, FactWs w, int s,
+                                                                int p, int p0, int mid, int *__restrict__ flags,
+                                                                int nsub) {
+    static_assert(NK * NT <= 4096, "pivot keys hold row indices below 4096");
+    constexpr int NW = NT / 64;
+    static_assert(kPanel % SW == 0 && SW % 2 == 0, "sub-panels tile the panel");
+    __shared__ double2 Ainv[kPanel * kPanel];  // also Lp[t][u] = F_u(r_t) while the sub-panels run
+    __shared__ double2 U[kPanel * kPanel];     // [t][c] pivot row t's eliminated values
+    __shared__ double2 Gbuf[kPanel * kPanel];  // second buffer of the A11 inverse
+    __shared__ double2 rowc[2][NW][SW];
+    __shared__ unsigned wkey[2][NW];
+    __shared__ int R1[kPanel];
+    const int c = blockIdx.x;
+    const ChainPos q = chain_pos(subs, c, s, mid != 0);
+    if (!q.active) return;
+    const int bs = q.bs, bsp = w.bsp, k0 = p * kPanel;
+    if (k0 >= bs) return;
+    const int bw = bs - k0 < kPanel ? bs - k0 : kPanel;
+    const int slot = p - p0;
+    const double2 *src = slot == 0 ? chain_M(w, c, q.cur) + (long long)k0 * bs : w.C + (long long)c * kPanel * bsp;
+    const long long sld = slot == 0 ? bs : bsp;
+    double *Xr = ws_x(w, c, slot), *Xi = Xr + (long long)kPanel * bsp;
+    double2 *F = w.Pw + (long long)c * kPanel * bsp;  // [kPanel][bsp] multipliers
+    int *ppos = w.ppos + (long long)c * bsp, *piv = w.piv + (long long)c * bsp;
+    double2 *Lp = Ainv;
+    const int tid = threadIdx.x, wv = tid >> 6;
+    const double mx = slot_read(w.mxb + 2 * c + q.cur);
+    if (p == 0 && tid == 0) w.mxb[2 * c + (q.cur ^ 1)] = 0ull;  // the store of this step fills it
+    // state of the thread's rows: -2 not a candidate (outside the block or an
+    // earlier panel's pivot), -1 candidate, t >= 0 pivot row of step t
+    int tp[NK], ic[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int i = tid + k * NT;
+        ic[k] = i < bs ? i : bs - 1;  // clamped row for unconditional loads
+        tp[k] = (i < bs && (p == 0 || ppos[i] < 0)) ? -1 : -2;
+    }
+    double tiny2 = (double)bs * DBL_EPSILON;
+    tiny2 = tiny2 * tiny2 * mx;
+    int status = 0;
+    for (int c0 = 0; c0 < bw; c0 += SW) {
+        __syncthreads();  // U of the earlier sub-panels complete
+        // this sub-panel's columns of the thread's rows; X = -S there (all rows below bsp)
+        // (all loads issued before the first store: a store under its branch
+        // right after a load would wait for that load alone, one at a time)
+        double2 v[NK][SW];
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+#pragma unroll
+            for (int cc = 0; cc < SW; ++cc) {
+                const int cl = c0 + cc < bw ? c0 + cc : bw - 1;
+                v[k][cc] = src[(long long)cl * sld + ic[k]];
+            }
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int i = tid + k * NT;
+#pragma unroll
+            for (int cc = 0; cc < SW; ++cc)
+                if (!(i < bs && c0 + cc < bw)) v[k][cc] = make_double2(0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int i = tid + k * NT;
+            if (i < bsp) {
+#pragma unroll
+                for (int cc = 0; cc < SW; ++cc) {
+                    Xr[(long long)(c0 + cc) * bsp + i] = -v[k][cc].x;
+                    Xi[(long long)(c0 + cc) * bsp + i] = -v[k][cc].y;
+                }
+            }
+        }
+        // row by row, UB multipliers per batch (all loads of a batch in flight together)
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+#pragma unroll 1
+            for (int u0 = 0; u0 < c0; u0 += UB) {
+                double2 f[UB];
+#pragma unroll
+                for (int uu = 0; uu < UB; ++uu) f[uu] = F[(long long)(u0 + uu) * bsp + ic[k]];
+#pragma unroll
+                for (int uu = 0; uu < UB; ++uu)
+#pragma unroll
+                    for (int cc = 0; cc < SW; ++cc)
+                        v[k][cc] = csub(v[k][cc], cmul(f[uu], U[(u0 + uu) * kPanel + c0 + cc]));
+            }
+        }
+        // pivot steps of this sub-panel
+#pragma unroll
+        for (int cc = 0; cc < SW; ++cc) {
+            const int t = c0 + cc;
+            if (t < bw) {
+                const int b = t & 1;
+                unsigned key = 0u;
+                int kb = 0;
+#pragma unroll
+                for (int k = 0; k < NK; ++k) {
+                    const unsigned kk = tp[k] == -1 ? ((__float_as_uint((float)cabs2(v[k][cc])) & ~4095u) |
+                                                       (unsigned)(4095 - (tid + k * NT)))
+                                                    : 0u;
+                    if (kk > key) { key = kk; kb = k; }
+                }
+                const unsigned wmax = wave_max_u32(key);
+                if (key != 0u && key == wmax) {  // keys are unique: one lane per wave
+#pragma unroll
+                    for (int k = 0; k < NK; ++k)
+                        if (k == kb)
+#pragma unroll
+                            for (int c2 = 0; c2 < SW; ++c2) rowc[b][wv][c2] = v[k][c2];
+                }
+                if ((tid & 63) == 0) wkey[b][wv] = wmax;
+                lds_barrier();  // rowc / wkey[b] are next written two steps later
+                unsigned best = wkey[b][0];
+                int wb = 0;
+#pragma unroll
+                for (int k = 1; k < NW; ++k)
+                    if (wkey[b][k] > best) { best = wkey[b][k]; wb = k; }
+                int r = 4095 - (int)(best & 4095u);
+                r = r < 0 ? 0 : (r >= bs ? bs - 1 : r);
+                const double2 *prow = rowc[b][wb];
+                const double2 piv_v = prow[cc];
+                if (!(cabs2(piv_v) > tiny2) && status == 0) status = 1 + q.l * bs + k0 + t;
+                const double2 inv = cinv(piv_v);
+                if (tid == 0) R1[t] = r;
+                if (tid >= cc && tid < SW) U[t * kPanel + c0 + tid] = prow[tid];  // the pivot row in this sub-panel
+#pragma unroll
+                for (int k = 0; k < NK; ++k) {
+                    if (tp[k] != -1) continue;
+                    const int i = tid + k * NT;
+                    if (i == r) {
+                        tp[k] = t;
+                        continue;
+                    }
+                    const double2 fm = cmul(v[k][cc], inv);
+                    F[(long long)t * bsp + i] = fm;
+#pragma unroll
+                    for (int c2 = cc + 1; c2 < SW; ++c2) v[k][c2] = csub(v[k][c2], cmul(fm, prow[c2]));
+                }
+            }
+        }
+        const int cn = c0 + SW;  // first column of the next sub-panel
+        if (cn < bw) {
+            __syncthreads();  // R1 of this sub-panel, its multipliers stored
+            const int te = cn < bw ? cn : bw;
+            for (int e = tid; e < SW * kPanel; e += NT) {
+                const int tt = c0 + e / kPanel, u = e % kPanel;
+                if (tt < te) {
+                    Lp[tt * kPanel + u] = u < tt ? F[(long long)u * bsp + R1[tt]] : make_double2(0, 0);
+                    if (u >= cn && u < bw) U[tt * kPanel + u] = src[(long long)u * sld + R1[tt]];
+                }
+            }
+            __syncthreads();
+            // the earlier sub-panels' pivots, in parallel over (row, column)
+            for (int e = tid; e < SW * kPanel; e += NT) {
+                const int tt = c0 + e / kPanel, cl = e % kPanel;
+                if (tt < te && cl >= cn && cl < bw) {
+                    double2 a = U[tt * kPanel + cl];
+                    for (int u = 0; u < c0; ++u) a = csub(a, cmul(Lp[tt * kPanel + u], U[u * kPanel + cl]));
+                    U[tt * kPanel + cl] = a;
+                }
+            }
+            __syncthreads();
+            // this sub-panel's pivots in order, one thread per later column
+            if (tid >= cn && tid < bw) {
+                for (int tt = c0; tt < te; ++tt) {
+                    double2 a = U[tt * kPanel + tid];
+                    for (int u = c0; u < tt; ++u) a = csub(a, cmul(Lp[tt * kPanel + u], U[u * kPanel + tid]));
+                    U[tt * kPanel + tid] = a;
+                }
+            }
+        }
+    }
+    __syncthreads();  // R1 complete; Lp no longer read
+    // A11 (original pivot rows, pivot order) and its inverse by Gauss-Jordan
+    // with the pivots on the diagonal: every thread, the matrix double-buffered
+    // in LDS, one barrier per step
+    for (int e = tid; e < kPanel * kPanel; e += NT) {
+        const int t = e / kPanel, u = e % kPanel;
+        Ainv[e] = (t < bw && u < bw) ? src[(long long)u * sld + R1[t]] : make_double2(0, 0);
+    }
+    __syncthreads();
+    for (int t = 0; t < bw; ++t) {
+        const double2 *Gi = (t & 1) ? Gbuf : Ainv;
+        double2 *Go = (t & 1) ? Ainv : Gbuf;
+        const double2 pi = cinv(Gi[t * kPanel + t]);
+        for (int e = tid; e < kPanel * kPanel; e += NT) {
+            const int i = e / kPanel, u = e % kPanel;
+            double2 nv = make_double2(0, 0);
+            if (i < bw && u < bw) {
+                const double2 rt = u == t ? pi : cmul(Gi[t * kPanel + u], pi);  // new row t
+                if (i == t) {
+                    nv = rt;
+                } else {
+                    const double2 fa = Gi[i * kPanel + t];
+                    nv = u == t ? make_double2(-(fa.x * pi.x - fa.y * pi.y), -(fa.x * pi.y + fa.y * pi.x))
+                                : csub(Gi[i * kPanel + u], cmul(fa, rt));
+                }
+            }
+            Go[e] = nv;
+        }
+        lds_barrier();
+    }
+    const double2 *Ares = (bw & 1) ? Gbuf : Ainv;  // the buffer the last step wrote
+    // A11^{-1} to the workspace (the multipliers are done): Y is formed by
+    // k_factor_formy over several workgroups per chain
+    for (int e = tid; e < kPanel * kPanel; e += NT) F[e] = Ares[e];
+    // pivot rows take no part in X; pivot steps of the rows
+    for (int e = tid; e < bw * kPanel; e += NT) {
+        const int t = e / kPanel, u = e % kPanel;
+        Xr[(long long)u * bsp + R1[t]] = 0.0;
+        Xi[(long long)u * bsp + R1[t]] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int i = tid + k * NT;
+        if (i >= bsp) continue;
+        if (tp[k] >= 0) ppos[i] = k0 + tp[k];
+        else if (p == 0) ppos[i] = -1;
+    }
+    for (int i = tid + NK * NT; i < bsp; i += NT)
+        if (p == 0) ppos[i] = -1;
+    if (tid < bw) piv[k0 + tid] = R1[tid];
+    if (tid == 0 && status) {
+        int *fl = flags + (mid ? 2 * nsub + q.a : c);
+        if (*fl == 0) *fl = status;
+    }
+}
+
 // Update kernel: the block after the deferred group p0 .. p0 + nd - 1 (one
 // panel when nd = 1: S <- S + X Y, panel columns starting from zero and
 // pivot rows becoming Y), T_{p0+nd} of the formula above, on the block of
@@ -949,46 +1102,68 @@ __global__ __launch_bounds__(kUThreads) void k_factor_update(const SubDesc *__re
                 im[bi][bj][r] = v.y;
             }
     }
-    for (int n = 0; n < ne; ++n) {
+    // operands of chunk (slot n, panel columns t0 .. t0 + 3): panel n's product
+    // reaches rows from slot lo on and columns outside the group's later panels
+    auto kend_of = [&](int n) {
+        const int kn = (p0 + n) * kPanel;
+        return ((bs - kn < kPanel ? bs - kn : kPanel) + 3) & ~3;
+    };
+    auto load_chunk = [&](int n, int t0, double (&xr)[2], double (&xi)[2], double (&yr)[2], double (&yi)[2]) {
         const double *Xr = ws_x(w, c, n), *Xi = Xr + (long long)kPanel * bsp;
         const double *Yr = ws_y(w, c, n), *Yi = Yr + (long long)kPanel * bsp;
         const int kn = (p0 + n) * kPanel;
-        const int bwn = bs - kn < kPanel ? bs - kn : kPanel;
-        const int kend = (bwn + 3) & ~3;
-        // panel n's product: rows from slot lo on, columns outside the later panels of the group
-        bool xs[2], ys[2];
+        const long long ko = (long long)(t0 + g) * bsp;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            xs[b] = n >= lo[b];
+            const double ar = Xr[ko + rw + 16 * b + qq], ai = Xi[ko + rw + 16 * b + qq];
+            const double br = Yr[ko + cw + 16 * b + qq], bi_ = Yi[ko + cw + 16 * b + qq];
+            const bool xs = n >= lo[b];
             const int j = cw + 16 * b + qq;
-            ys[b] = j < kn + kPanel || j >= ke;
+            const bool ys = j < kn + kPanel || j >= ke;
+            xr[b] = xs ? ar : 0.0;  // B operand: X^T(t, i) at lane i + 16 t
+            xi[b] = xs ? ai : 0.0;
+            yr[b] = ys ? br : 0.0;  // A operand: Y^T(j, t) at lane j + 16 t
+            yi[b] = ys ? bi_ : 0.0;
         }
-        for (int t0 = 0; t0 < kend; t0 += 4) {
-            const long long ko = (long long)(t0 + g) * bsp;
-            double xr[2], xi[2], yr[2], yi[2];
+    };
+    // chunks in order, the next chunk's operands loaded before this chunk's
+    // products (loads issued unconditionally: past the last chunk the last
+    // one is loaded again)
+    int n = 0, t0 = 0;
+    double xr[2], xi[2], yr[2], yi[2];
+    load_chunk(0, 0, xr, xi, yr, yi);
+    for (;;) {
+        int n2 = n, t2 = t0 + 4;
+        if (t2 >= kend_of(n)) {
+            n2 = n + 1;
+            t2 = 0;
+        }
+        const bool more = n2 < ne;
+        double nxr[2], nxi[2], nyr[2], nyi[2];
+        load_chunk(more ? n2 : n, more ? t2 : t0, nxr, nxi, nyr, nyi);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const double ar = Xr[ko + rw + 16 * b + qq], ai = Xi[ko + rw + 16 * b + qq];
-                const double br = Yr[ko + cw + 16 * b + qq], bi_ = Yi[ko + cw + 16 * b + qq];
-                xr[b] = xs[b] ? ar : 0.0;  // B operand: X^T(t, i) at lane i + 16 t
-                xi[b] = xs[b] ? ai : 0.0;
-                yr[b] = ys[b] ? br : 0.0;  // A operand: Y^T(j, t) at lane j + 16 t
-                yi[b] = ys[b] ? bi_ : 0.0;
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xr[bi], re[bi][bj], 0, 0, 0);
+                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], xr[bi], im[bi][bj], 0, 0, 0);
             }
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xr[bi], re[bi][bj], 0, 0, 0);
-                    im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], xr[bi], im[bi][bj], 0, 0, 0);
-                }
+            for (int bj = 0; bj < 2; ++bj) {
+                re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], -xi[bi], re[bi][bj], 0, 0, 0);
+                im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xi[bi], im[bi][bj], 0, 0, 0);
+            }
+        if (!more) break;
+        n = n2;
+        t0 = t2;
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[bj], -xi[bi], re[bi][bj], 0, 0, 0);
-                    im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[bj], xi[bi], im[bi][bj], 0, 0, 0);
-                }
+        for (int b = 0; b < 2; ++b) {
+            xr[b] = nxr[b];
+            xi[b] = nxi[b];
+            yr[b] = nyr[b];
+            yi[b] = nyi[b];
         }
     }
 #pragma unroll
@@ -1064,6 +1239,28 @@ static int groups_for(long long n2) {
     return (int)(g < kEGroups ? g : kEGroups);
 }
 
+// Workgroup size, rows per thread and sub-panel width by block size (the
+// registers of v[NK][SW] and of the multiplier batch within the VGPR budget
+// of NT threads per CU).
+static hipError_t launch_panel_sp(int bs_max, int nc, hipStream_t st, const SubDesc *subs, FactWs w, int s, int p,
+                                  int p0, int mid, int *flags, int nsub) {
+    if (bs_max <= 1024)
+        k_factor_panel_sp<512, 2, 8, 8><<<nc, 512, 0, st>>>(subs, w, s, p, p0, mid, flags, nsub);
+    else if (bs_max <= 1536)
+        k_factor_panel_sp<512, 3, 8, 8><<<nc, 512, 0, st>>>(subs, w, s, p, p0, mid, flags, nsub);
+    else if (bs_max <= 2048)
+        k_factor_panel_sp<512, 4, 8, 8><<<nc, 512, 0, st>>>(subs, w, s, p, p0, mid, flags, nsub);
+    else if (bs_max <= 2304)
+        k_factor_panel_sp<768, 3, 8, 4><<<nc, 768, 0, st>>>(subs, w, s, p, p0, mid, flags, nsub);
+    else if (bs_max <= 3072)
+        k_factor_panel_sp<1024, 3, 4, 4><<<nc, 1024, 0, st>>>(subs, w, s, p, p0, mid, flags, nsub);
+    else if (bs_max <= 4096)
+        k_factor_panel_sp<1024, 4, 4, 2><<<nc, 1024, 0, st>>>(subs, w, s, p, p0, mid, flags, nsub);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_factor(ddm_handle *h, void *ws_base) {
     const Plan &P = h->plan;
@@ -1095,18 +1292,15 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
     hipError_t e = hipFuncSetAttribute(pw_in_lds ? (const void *)k_factor_panel<true> : (const void *)k_factor_panel<false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    // blocks above 512 rows: the left-looking panel (up to kLLRows rows per thread)
-    const bool use_ll = panel_kind == 2 && P.bs_max <= kLLRows * kPThreads;
-    const size_t lds_ll = (size_t)2 * kPanel * kPanel * sizeof(double2) + kPanel * sizeof(int) + (size_t)w.bsp * sizeof(int);
-    if (use_ll) {
-        e = hipFuncSetAttribute((const void *)k_factor_panel_ll, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_ll);
-        if (e != hipSuccess) return e;
+    // blocks of 513 .. 4096 rows: the sub-panel kernel and deferred groups
+    const bool use_sp = panel_kind == 2 && P.bs_max <= kSPRows;
+    if (use_sp) {
         e = hipFuncSetAttribute((const void *)k_factor_formy, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)formy_lds_bytes(w.slots - 1));
+                                (int)kFormyLds);
         if (e != hipSuccess) return e;
     }
-    // panels per deferred group (the left-looking path only)
-    const int D = use_ll ? w.slots : 1;
+    // panels per deferred group (the sub-panel path only)
+    const int D = use_sp ? w.slots : 1;
     e = launch_fill_zero(w.mxb, (long long)2 * nc * sizeof(unsigned long long), h->stream);
     if (e != hipSuccess) return e;
     e = launch_fill_zero(h->d_flags, (long long)3 * P.nsub * sizeof(int), h->stream);
@@ -1125,13 +1319,13 @@ hipError_t launch_factor(ddm_handle *h, void *ws_base) {
                     k_factor_panel_r<256><<<nc, 256, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
                 else if (panel_kind == 1)
                     k_factor_panel_r<512><<<nc, 512, 0, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags, P.nsub);
-                else if (use_ll) {
+                else if (use_sp) {
                     if (p > p0)
                         k_factor_colupd<<<nc * (w.bsp / 64), kCThreads, 0, h->stream>>>(h->d_subs, w, ss, p, p0, mid);
-                    k_factor_panel_ll<<<nc, kPThreads, lds_ll, h->stream>>>(h->d_subs, w, ss, p, p0, mid, h->d_flags,
-                                                                             P.nsub);
-                    k_factor_formy<<<nc * kYGroups, kYThreads, formy_lds_bytes(p - p0), h->stream>>>(h->d_subs, w, ss,
-                                                                                                  p, p0, mid);
+                    e = launch_panel_sp(P.bs_max, nc, h->stream, h->d_subs, w, ss, p, p0, mid, h->d_flags, P.nsub);
+                    if (e != hipSuccess) return e;
+                    k_factor_formy<<<nc * (w.bsp / 64), kYThreads, kFormyLds, h->stream>>>(h->d_subs, w, ss, p, p0,
+                                                                                            mid);
                 } else if (pw_in_lds)
                     k_factor_panel<true><<<nc, kPThreads, lds, h->stream>>>(h->d_subs, w, ss, p, mid, h->d_flags,
                                                                             P.nsub);
