@@ -245,12 +245,37 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const SubDesc *__restrict__
 // host accepts the Phi form only for one-axis layouts.  Its terms are
 // O(v |grad beta| / h) with no cancellation of O(v / h^2) terms.
 // ---------------------------------------------------------------------------
-__device__ inline bool in_box(const SubDesc &b, int q0, int q1, int q2) {
+// The box fields of a descriptor the transfer uses, copied to registers with
+// all loads issued together (read field by field where they are used, each
+// load would be waited for alone inside its branch).
+struct BoxR {
+    int lo[3], hi[3], clo[3], chi[3], n[3];
+    long long off;
+};
+
+__device__ inline BoxR box_of(const SubDesc *__restrict__ subs, int i) {
+    const SubDesc &d = subs[i];
+    BoxR b;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        b.lo[k] = d.lo[k];
+        b.hi[k] = d.hi[k];
+        b.clo[k] = d.clo[k];
+        b.chi[k] = d.chi[k];
+        b.n[k] = d.n[k];
+    }
+    b.off = d.off;
+    return b;
+}
+
+template <typename B>
+__device__ inline bool in_box(const B &b, int q0, int q1, int q2) {
     return q0 >= b.lo[0] && q0 <= b.hi[0] && q1 >= b.lo[1] && q1 <= b.hi[1] && q2 >= b.lo[2] && q2 <= b.hi[2];
 }
 
 // beta_{b->a}(q): b's side factors facing a on every axis where they differ
-__device__ inline double beta_ba(const SubDesc &b, const int *dd, const double *__restrict__ btab, int n_ov, int q0,
+template <typename B>
+__device__ inline double beta_ba(const B &b, const int *dd, const double *__restrict__ btab, int n_ov, int q0,
                                  int q1, int q2) {
     int q[3] = {q0, q1, q2};
     double beta = 1.0;
@@ -292,7 +317,17 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
     const int2 se = strip[t];
     const int a = se.x;
     const long long e = se.y;
-    const SubDesc &s = subs[a];
+    // a's box, coefficient offsets and neighbour table in registers
+    constexpr int NS0 = DIM3 ? 0 : 9, NS = DIM3 ? 26 : 8;  // 2D: only the dz = 0 slots 9 .. 16
+    const BoxR s = box_of(subs, a);
+    int scoff[3], snbr[NS], slag[NS];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) scoff[d] = subs[a].coff[d];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        snbr[k] = subs[a].nbr[NS0 + k];
+        slag[k] = subs[a].lag[NS0 + k];
+    }
     const int lx = (int)(e % s.n[0]), ly = (int)((e / s.n[0]) % s.n[1]), lz = (int)(e / ((long long)s.n[0] * s.n[1]));
     int p[3] = {s.lo[0] + lx, s.lo[1] + ly, s.lo[2] + lz};
     int l[3] = {lx, ly, lz};
@@ -309,22 +344,28 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
     const bool corrected = rcorr && p[0] >= s.clo[0] && p[0] <= s.chi[0] && p[1] >= s.clo[1] &&
                            p[1] <= s.chi[1] && p[2] >= s.clo[2] && p[2] <= s.chi[2];
     const long long gi = glob_index(A, p[0], p[1], p[2]);
+    // loads are issued unconditionally (clamped RHS / node indices, the value
+    // masked afterwards) so that a term's loads for every RHS of the tile are
+    // in flight together; under a branch each load would be waited for alone
 #pragma unroll
-    for (int q = 0; q < RQ; ++q)
-        acc[q] = (corrected && q < nr) ? rcorr[(long long)(r0 + q) * A.nglob + gi] : make_double2(0, 0);
+    for (int q = 0; q < RQ; ++q) {
+        const int qc = q < nr ? q : nr - 1;
+        const double2 v = rcorr ? rcorr[(long long)(r0 + qc) * A.nglob + gi] : make_double2(0, 0);
+        acc[q] = (corrected && q < nr) ? v : make_double2(0, 0);
+    }
     const double kk = PHI ? 0.0 : k2[gi];
     Coef cf[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) cf[d] = coef[s.coff[d] + l[d]];
+    for (int d = 0; d < 3; ++d) cf[d] = coef[scoff[d] + l[d]];
     // neighbour slots in (dz, dy, dx) order without (0, 0, 0); in 2D only the
     // dz = 0 slots 9 .. 16 exist
-    int k = DIM3 ? 0 : 9;
+    int k = 0;
     for (int dz = DIM3 ? -1 : 0; dz <= (DIM3 ? 1 : 0); ++dz)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
                 if (dx == 0 && dy == 0 && dz == 0) continue;
-                int slot = k++;
-                int bidx = s.nbr[slot];
+                const int slot = k++;
+                const int bidx = snbr[slot];
                 if (bidx < 0) continue;
                 int dd[3] = {dx, dy, dz};
                 // every differing axis must put p in the strip facing b
@@ -335,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
                     if (dd[d] > 0 && !inhi[d]) ok = false;
                 }
                 if (!ok) continue;
-                int lag = s.lag[slot];
+                const int lag = slag[slot];
                 const TIN *src = lag == 1 ? l1 : (lag == 2 ? l2 : l3);
                 const TIN *src2 = nullptr;
                 if (corrected) {
@@ -346,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
                     src2 = lag == 3 ? l2 : nullptr;
                 }
                 if (!src) continue;
-                const SubDesc &b = subs[bidx];
+                const BoxR b = box_of(subs, bidx);
                 // stencil points: 0 = p, 2d + 1 = p + e_d, 2d + 2 = p - e_d;
                 // weight of the packed value at each (direct: beta, Phi form:
                 // beta - beta(p)), its packed index, -1 outside b's box or
@@ -376,16 +417,49 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
 #pragma unroll
                     for (int j = 1; j < 7; ++j) wt[j] -= b0;
                 }
+                // clamped packed indices: a point outside b's box reads b's
+                // first node and is masked by its zero weight
+                long long lc[7];
+                bool use[7];
 #pragma unroll
-                for (int q = 0; q < RQ; ++q) {
-                    if (q >= nr) continue;
-                    const long long ro = (long long)(r0 + q) * A.etot;
-                    auto val = [&](int j) {
-                        if (li[j] < 0 || wt[j] == 0.0) return make_double2(0, 0);
-                        double2 v = to_d2(src[ro + li[j]]);
-                        if (src2) v = cadd(v, to_d2(src2[ro + li[j]]));
-                        return cscale(v, wt[j]);
-                    };
+                for (int j = 0; j < 7; ++j) {
+                    use[j] = li[j] >= 0 && wt[j] != 0.0;
+                    lc[j] = li[j] >= 0 ? li[j] : b.off;
+                }
+                constexpr int NP = DIM3 ? 7 : 5;  // stencil points
+                // TWO: the sum of two solutions (the corrected form's lag-3 terms)
+                auto term = [&](auto two) {
+                constexpr bool TWO = decltype(two)::value;
+                // RHS whose loads are in flight together (fewer for complex128 and
+                // the 7-point stencil: registers)
+                constexpr int QC0 = (sizeof(TIN) > 8 ? 2 : 4) / (DIM3 ? 2 : 1);
+                constexpr int QC = RQ < QC0 ? RQ : QC0;
+#pragma unroll
+                for (int q0 = 0; q0 < RQ; q0 += QC) {
+                TIN ld[QC][NP], ld2[QC][TWO ? NP : 1];
+#pragma unroll
+                for (int qq = 0; qq < QC; ++qq) {
+                    const int q = q0 + qq, qc = q < nr ? q : nr - 1;
+                    const long long ro = (long long)(r0 + qc) * A.etot;
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) {
+                        ld[qq][j] = src[ro + lc[j]];
+                        if constexpr (TWO) ld2[qq][j] = src2[ro + lc[j]];
+                    }
+                }
+#pragma unroll
+                for (int qq = 0; qq < QC; ++qq) {
+                    const int q = q0 + qq;
+                    double2 pv[7];
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) pv[j] = make_double2(0, 0);
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) {
+                        double2 v = to_d2(ld[qq][j]);
+                        if constexpr (TWO) v = cadd(v, to_d2(ld2[qq][j]));
+                        pv[j] = use[j] ? cscale(v, wt[j]) : make_double2(0, 0);
+                    }
+                    auto val = [&](int j) { return pv[j]; };
                     double2 Lw;
                     if constexpr (PHI) {
                         // commutator: sum_d cp (beta_+ - beta_0) v_+ + cm (beta_- - beta_0) v_-
@@ -408,6 +482,11 @@ __global__ __launch_bounds__(kBlock) void k_transfer(const SubDesc *__restrict__
                     // plain: acc += Psi = -L(beta v); corrected: acc -= Psi
                     acc[q] = corrected ? cadd(acc[q], Lw) : csub(acc[q], Lw);
                 }
+                __builtin_amdgcn_sched_barrier(0);  // one chunk of loads live at a time (registers)
+                }
+                };
+                if (src2) term(std::true_type{});
+                else term(std::false_type{});
             }
 #pragma unroll
     for (int q = 0; q < RQ; ++q)
@@ -535,9 +614,11 @@ hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TI
     }
     const long long ns = (long long)P.strip.size();
     if (ns > 0) {
-        // RHS per thread: 4, or 16 for batches of more than 8 (the geometry of
-        // a node's neighbour terms is then worked out once for 16 RHS:
-        // 1.32 -> 1.21 ms per complex64 transfer on the layered 2048^2 batch)
+        // RHS per thread: 4, or 8 for batches of more than 4 (the geometry of
+        // a node's neighbour terms is worked out once per tile; with the
+        // loads of 4 RHS in flight together, 8-RHS tiles keep the registers
+        // for two waves per SIMD: 0.98 -> 0.54 ms per complex64 transfer on
+        // the layered 2048^2 batch, against 0.70 ms with 16-RHS tiles)
         const bool phi = h->transfer_form == DDM_TRANSFER_PHI, d3 = P.dim == 3;
         auto launch = [&](auto rq) {
             constexpr int RQ = decltype(rq)::value;
@@ -547,7 +628,7 @@ hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TI
             kern<<<grid, kBlock, 0, h->stream>>>(h->d_subs, h->d_coef, h->d_k2, h->d_btab, l1, l2, l3, g, pack_args(P),
                                                  rcorr, h->d_strip, ns, nrhs);
         };
-        if (nrhs > 8) launch(std::integral_constant<int, 16>{});
+        if (nrhs > 4) launch(std::integral_constant<int, 8>{});
         else launch(std::integral_constant<int, 4>{});
     }
     return hipGetLastError();
