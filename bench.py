@@ -964,11 +964,13 @@ def main():
     ap.add_argument("--serve-layouts", choices=["any", "onedir"], default="any",
                     help="serve: factor layouts the tuner may pick (onedir: no cooperative substitution launches, "
                          "so handles' steps can run side by side)")
-    ap.add_argument("--budget-gb", type=float, default=24.0, help="serve: HBM budget for cached problems (GiB)")
+    ap.add_argument("--budget-gb", type=float, default=96.0, help="serve: HBM budget for cached problems (GiB)")
     ap.add_argument("--poll-steps", type=int, default=1,
                     help="serve: DDM steps enqueued per handle between polls (1: a right-hand side leaves at the "
                          "first step that meets the tolerance, as in a batch solve alone)")
-    ap.add_argument("--slots", type=int, default=16, help="serve: RHS slots per cached problem")
+    ap.add_argument("--slots", type=int, default=64,
+                    help="serve: RHS slots per cached problem (the matrix-core substitution runs its 16-RHS "
+                         "tiles side by side)")
     ap.add_argument("--tol", type=float, default=None, help="stationary/FGMRES tolerance (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FGMRES and mixed-precision legs")

@@ -128,7 +128,7 @@ size_t setup_bytes(const Plan &P, bool mixed, int nrhs) {
     if (mixed) b += abytes<double2>((size_t)nrhs * P.etot);         // widening scratch
     b += abytes<double>(part_doubles(P, nrhs, 30));
     b += abytes<double>((size_t)4 * nrhs) + abytes<int>((size_t)nrhs);  // norms, active flags
-    b += abytes<int>((size_t)4 * P.nsub + 1);                       // meeting / read-done / abort flags
+    b += abytes<int>((size_t)4 * P.nsub * sync_tiles_for(nrhs) + 1);  // meeting / read-done / abort flags
     if (chain2_fits(P)) b += abytes<int>((size_t)12 * P.nsub) + abytes<char>(chain2_xbuf_bytes(P));
     b += 2 * abytes<double2>((size_t)nrhs * P.nglob);               // handle-owned f and u (graphs, slots)
     return b;
@@ -1088,8 +1088,9 @@ int ddm_setup(const ddm_problem *p, const double *k2, int nrhs_max, void *stream
         dalloc(h, &h->d_part, h->part_cap);
         dalloc(h, &h->d_norm, (size_t)4 * nrhs_max);
         dalloc(h, &h->d_active, (size_t)nrhs_max);
-        dalloc(h, &h->d_sync, (size_t)4 * P.nsub + 1);
-        HIPCHK(hipMemset(h->d_sync, 0, (4 * P.nsub + 1) * sizeof(int)));
+        h->sync_tiles = sync_tiles_for(nrhs_max);
+        dalloc(h, &h->d_sync, (size_t)4 * P.nsub * h->sync_tiles + 1);
+        HIPCHK(hipMemset(h->d_sync, 0, ((size_t)4 * P.nsub * h->sync_tiles + 1) * sizeof(int)));
         if (chain2_fits(P)) {
             dalloc(h, &h->d_sync2, (size_t)12 * P.nsub);
             dalloc(h, (char **)&h->d_xbuf, chain2_xbuf_bytes(P));

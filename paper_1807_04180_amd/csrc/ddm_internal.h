@@ -144,7 +144,10 @@ struct ddm_handle {
     // substitution kernel variant (autotuned) and persistent-launch sync state
     int solve_variant = 0;
     int chain_tile = 0;             // chain variant, batches of > 4 RHS: RHS tile 4, 8 or 16 (0 = by batch size)
-    int *d_sync = nullptr;          // 2 nsub meeting flags, 2 nsub read-done flags, 1 abort flag
+    int *d_sync = nullptr;          // per parallel RHS tile of the matrix-core substitution: 2 nsub
+                                    // meeting flags and 2 nsub read-done flags (the chain kernels use
+                                    // the first tile's); then 1 abort flag
+    int sync_tiles = 1;             // RHS tiles d_sync has flags for: ceil(nrhs_max / 16)
     int *d_sync2 = nullptr;         // split substitution: 4 nsub meeting, 4 nsub exchange and
                                     // 4 nsub read-done flags
     void *d_xbuf = nullptr;         // split substitution: double-buffered partial-sum exchange
@@ -172,7 +175,10 @@ struct ddm_handle {
 namespace ddm {
 
 // sticky abort flag of the bounded waits in the substitution kernels
-inline int *abort_flag_ptr(ddm_handle *h) { return h->d_sync + 4 * h->plan.nsub; }
+inline int *abort_flag_ptr(ddm_handle *h) { return h->d_sync + (size_t)4 * h->plan.nsub * h->sync_tiles; }
+
+// RHS tiles of 16 whose flags d_sync holds for a handle of nrhs_max RHS
+inline int sync_tiles_for(int nrhs_max) { return nrhs_max > 16 ? (nrhs_max + 15) / 16 : 1; }
 
 // Bracket one launch with a pair of events when profiling is on.
 struct ProfScope {

@@ -29,6 +29,8 @@
 // padding rows are read; columns are padded to a whole group (zeros).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "cplx.h"
 #include "ddm_internal.h"
 #include "ddm_mma.h"
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
                                                     const T2 *__restrict__ W, const T2 *__restrict__ g,
                                                     T2 *__restrict__ x, int nrhs, long long etot, int dim,
                                                     int twisted, int vcap, int *flags, int *rflags, int *abort_flag,
-                                                    int spin_limit) {
+                                                    int spin_limit, int fstride) {
     using M = Mma<T2>;
     using R = typename M::R;
     using LT = typename M::LT;
@@ -93,10 +95,15 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
     // both V buffers start at zero: the padding columns [bs, mpad) stay zero
     for (int e = threadIdx.x; e < 2 * vcap * kMmaRhs; e += blockDim.x) vbuf[e] = czero<T2>();
 
-    for (int r0 = 0; r0 < nrhs; r0 += kMmaRhs) {
+    // RHS tiles blockIdx.y, blockIdx.y + gridDim.y, ...: the workgroups of a
+    // grid row share nothing with other rows; each row has its own meeting
+    // and read-done flags (fstride apart)
+    flags += (size_t)blockIdx.y * fstride;
+    rflags += (size_t)blockIdx.y * fstride;
+    int epoch = 0;  // meeting flags count this row's tiles (never reset inside the launch)
+    for (int r0 = (int)blockIdx.y * kMmaRhs; r0 < nrhs; r0 += (int)gridDim.y * kMmaRhs) {
         const int nr = nrhs - r0 < kMmaRhs ? nrhs - r0 : kMmaRhs;
-        // meeting flags count RHS tiles (never reset inside the launch)
-        const int epoch = r0 / kMmaRhs + 1;
+        ++epoch;
         __syncthreads();  // the previous tile's readers of buffer 0 are done
         for (int e = threadIdx.x; e < bs * kMmaRhs; e += blockDim.x) {
             const int i = e >> 4, q = e & 15;
@@ -287,17 +294,22 @@ hipError_t run_mma(ddm_handle *h, const T2 *g, T2 *x, int nrhs) {
     long long a6 = P.etot;
     int a7 = P.dim, a8 = P.twisted ? 1 : 0, a9 = P.mpad_max;
     int *a10 = h->d_sync, *a11 = h->d_sync + 2 * P.nsub, *a12 = abort_flag_ptr(h);
-    int a13 = h->spin_limit;
+    int a13 = h->spin_limit, a14 = 4 * P.nsub;
+    // RHS tiles side by side (grid rows): as many as there are tiles, flags
+    // for and, in the two-ended layout, room to keep every workgroup
+    // co-resident (one per CU); a row takes the tiles beyond them in turn
+    int rows = std::min(ntile, h->sync_tiles);
+    if (P.twisted) rows = std::max(1, std::min(rows, P.ncu / (2 * P.nsub)));
     if (P.twisted) {
-        // meeting flags and read-done flags (4 nsub) start at zero
-        e = launch_fill_zero(h->d_sync, (long long)(4 * P.nsub) * sizeof(int), h->stream);
+        // meeting flags and read-done flags (4 nsub per row) start at zero
+        e = launch_fill_zero(h->d_sync, (long long)(4 * P.nsub) * rows * sizeof(int), h->stream);
         if (e != hipSuccess) return e;
-        void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11, &a12, &a13};
+        void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11, &a12, &a13, &a14};
         // the two chains of a subdomain meet once: they must be co-resident
-        return hipLaunchCooperativeKernel(kern, dim3(2 * P.nsub), dim3(nt), args, lds, h->stream);
+        return hipLaunchCooperativeKernel(kern, dim3(2 * P.nsub, rows), dim3(nt), args, lds, h->stream);
     }
-    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11, &a12, &a13};
-    return hipLaunchKernel(kern, dim3(P.nsub), dim3(nt), args, lds, h->stream);
+    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8, &a9, &a10, &a11, &a12, &a13, &a14};
+    return hipLaunchKernel(kern, dim3(P.nsub, rows), dim3(nt), args, lds, h->stream);
 }
 
 template hipError_t run_mma<float2>(ddm_handle *, const float2 *, float2 *, int);

@@ -155,6 +155,30 @@ def test_mma_substitution(case, mixed, twisted):
         g.close()
 
 
+@pytest.mark.parametrize("twisted", [True, False])
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("case", ["2d-2x2-small", "3d-2x2x2"])
+def test_mma_parallel_rhs_tiles(case, mixed, twisted):
+    """48 RHS on a 48-RHS handle: three 16-RHS tiles run side by side (grid
+    rows with their own meeting flags), 40 RHS: a ragged third tile.  Each
+    tile gives the same bits as when solved alone, and the oracle's values."""
+    w = MMA_CASES[case](1)
+    o, g = _pair(w, 48, mixed=mixed)
+    tol = 5e-5 if mixed else 1e-10
+    try:
+        g.set_factor_layout(twisted)
+        g.set_solve_variant("mma")
+        for nrhs in (48, 40):
+            gin = di.random_field((nrhs, o.etot), seed=420 + nrhs)
+            xg = _n(g.local_solve(_t(gin)))
+            assert relerr(xg, o.local_solve(gin), axis=1) < tol, nrhs
+            for t0 in range(0, nrhs, 16):
+                part = _n(g.local_solve(_t(gin[t0:t0 + 16])))
+                assert np.array_equal(part, xg[t0:t0 + 16]), (nrhs, t0)
+    finally:
+        g.close()
+
+
 @pytest.mark.parametrize("mixed", [False, True])
 def test_mma_largest_blocks(mixed):
     """Blocks of 255 and 256 unknowns (16 row tiles: 1024-thread workgroups,
