@@ -883,7 +883,14 @@ extern "C" int ddm_slot_admit(ddm_handle *h, int slot, const void *f) {
 template <typename T>
 static void slots_step_impl(ddm_handle *h, int nsteps) {
     const Plan &P = h->plan;
-    const int n = h->nrhs_max;
+    // slots past the highest busy one are left alone: a slot's arithmetic
+    // does not depend on the others, and a slot's state is cleared when it
+    // is admitted.  The source norms stay at offset nrhs_max of d_norm, where
+    // ddm_slots_poll reads them.
+    int n = 0;
+    for (int q = 0; q < h->nrhs_max; ++q)
+        if (h->slot_steps[q] >= 0) n = q + 1;
+    if (n == 0) return;
     const size_t es = sizeof(T);
     const double2 *rcorr = h->mixed ? h->d_r : nullptr;
     for (int k = 0; k < nsteps; ++k) {
@@ -898,7 +905,8 @@ static void slots_step_impl(ddm_handle *h, int nsteps) {
         T *us = (T *)h->d_ring[s % P.ring];
         HIPCHK(launch_local_solve<T>(h, g, us, n));
         HIPCHK(launch_assemble<T>(h, us, h->d_uin, n, true, h->d_active));
-        HIPCHK(launch_residual(h, h->d_fin, h->d_uin, const_cast<double2 *>(rcorr), n, h->d_norm, h->d_norm + n));
+        HIPCHK(launch_residual(h, h->d_fin, h->d_uin, const_cast<double2 *>(rcorr), n, h->d_norm,
+                               h->d_norm + h->nrhs_max));
         for (int q = 0; q < n; ++q)
             if (h->slot_steps[q] >= 0) ++h->slot_steps[q];
     }
