@@ -818,7 +818,8 @@ __global__ __launch_bounds__(NT) void k_factor_panel_r(const SubDesc *__restrict
 // its rows.  At the end of a sub-panel the pivot rows it chose get their U
 // in the later columns, U(t, c) = S(r_t, c) - sum_{u < t} F_u(r_t) U(u, c).
 // The pivots are those of partial pivoting on the panel (magnitudes compared
-// to 2^-12 relative, ties to the smaller row).  A11^{-1}, X and the
+// to 2^-11 relative: 12 of the 23 mantissa bits of |v|^2 as a float hold
+// the row; ties to the smaller row).  A11^{-1}, X and the
 // workspace outputs: X = -(the panel's columns) with its pivot rows zero,
 // A11^{-1} (A11 = the panel's pivot rows in pivot order, inverted by
 // Gauss-Jordan with all threads) at the start of the multiplier area for
