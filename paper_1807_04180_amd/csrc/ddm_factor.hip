@@ -1159,13 +1159,8 @@ __global__ __launch_bounds__(kUThreads) void k_factor_update(const SubDesc *__re
         if (!more) break;
         n = n2;
         t0 = t2;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            xr[b] = nxr[b];
-            xi[b] = nxi[b];
-            yr[b] = nyr[b];
-            yi[b] = nyi[b];
-        }
+        xr[0] = nxr[0], xr[1] = nxr[1], xi[0] = nxi[0], xi[1] = nxi[1];
+        yr[0] = nyr[0], yr[1] = nyr[1], yi[0] = nyi[0], yi[1] = nyi[1];
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {

@@ -178,3 +178,37 @@ def test_alone_vs_mix(mixed, blocks, slots):
         ug = r.u.cpu().numpy()
         err = np.max(np.linalg.norm(ug - uo, axis=1) / np.linalg.norm(uo, axis=1))
         assert err <= 1e-6, (r.rid, err)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mixed", [False, True])
+def test_slot_steps_cover_the_busy_range(mixed):
+    """A 64-slot handle steps only the slots up to the highest busy one; a
+    slot's arithmetic depends neither on that range nor on its position or
+    on when it was admitted: slot 40 admitted first (steps cover 41 slots),
+    slot 5 three steps later, each gives the bits of the same source alone in
+    slot 0 of a fresh handle after the same number of steps."""
+    w = di.small_2d(M=128, N=(2, 2), n_pml=6, n_ov=4, nrhs=2, seed=3)
+    dev = torch.device("cuda:0")
+    k2 = torch.from_numpy(w.k2.reshape(-1)).to(dev)
+    f = torch.from_numpy(w.f.reshape(2, -1)).to(dev)
+    prob = ddm.Problem.from_workload(w, mixed=mixed)
+    s = ddm.HelmholtzDDM(prob, k2, 64)
+    s.slot_admit(40, f[0])
+    s.slots_step(3)
+    s.slot_admit(5, f[1])
+    s.slots_step(6)
+    rel, steps = s.slots_poll()
+    assert steps[40] == 9 and steps[5] == 6 and steps[0] == -1
+    ua, ub = torch.zeros_like(f[0]), torch.zeros_like(f[1])
+    s.slot_retire(40, ua)
+    s.slot_retire(5, ub)
+    s.close()
+    for src, nsteps, got in ((f[0], 9, ua), (f[1], 6, ub)):
+        t = ddm.HelmholtzDDM(prob, k2, 64)
+        t.slot_admit(0, src)
+        t.slots_step(nsteps)
+        u = torch.zeros_like(src)
+        t.slot_retire(0, u)
+        t.close()
+        assert torch.equal(u, got), nsteps
