@@ -191,6 +191,12 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
             const R *vb = (const R *)vcur + boff;
             const char *cur_b = Wt + (long long)l * bstr_b;
             const char *nxt_b = Wt + (long long)(st + 1 < nsteps ? step_l(st + 1) : l) * bstr_b;
+            // The waits for the g / y entries above already leave no load in
+            // flight, so a full wait costs nothing here; it lets the
+            // compiler's counter analysis wait for one ring load per slot
+            // (7 left in flight).  Without it the analysis carries an unknown
+            // older load into the loop and waits for all eight at every turn.
+            __builtin_amdgcn_s_waitcnt(0);
             for (int jb = 0; jb < NGP; jb += kMmaRing) {
                 // the loads of this turn: groups jb + 8 .. of this block, or
                 // the next block's first groups after this block's last turn
