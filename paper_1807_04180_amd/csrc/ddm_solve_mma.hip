@@ -117,27 +117,30 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
             for (int u = 0; u < kMmaRing; ++u) ring[u] = *(const LT *)(b0 + (long long)(u < NG ? u : NG - 1) * grp_b);
         }
 
-        // per lane: its 4 rows x 2 RHS (one per half) of component p of
-        // g_lnv (forward) or of y_l (backward) for step st_, one load per
-        // entry whatever the step (clamped addresses, the value zeroed where
-        // unused).  The y block of the first backward step of the two-ended
-        // layout was stored by this same lane with an atomic store at the
-        // last forward step and has not been read through this CU's cache
-        // since: a plain load returns it.
-        R pre[2][4];
+        // per lane and half: the g_lnv (forward) or y_l (backward) entries
+        // of step st_ that store_half moves for this lane (whole entries, the
+        // same loads whatever the step: rows and RHS clamped, the values
+        // dropped where unused), turned into part p of the lane's 4 rows by
+        // M::pre_parts where they are used.  The y block of the first
+        // backward step of the two-ended layout was stored by this lane pair
+        // with atomic stores at the last forward step and has not been read
+        // through this CU's cache since: a plain load returns it.
+        typename M::PT pre[2][M::NPL];
         unsigned pok = 0;  // bit 4 hf + r: entry (hf, r) used (applied where it is read, so the
                            // loads are not waited for where they are issued)
 #define DDM_MMA_PRE(st_)                                                                                  \
     {                                                                                                     \
         const int kd = (st_) < nf ? 0 : ((st_) == nf ? 1 : 2), lp = step_l(st_), ln = lnv_of(st_);        \
-        const R *psrc = (const R *)(kd == 2 ? x + (long long)lp * bs : g + (long long)(ln >= 0 ? ln : lp) * bs) + p; \
+        const T2 *psrc = (kd == 2 ? x + (long long)lp * bs : g + (long long)(ln >= 0 ? ln : lp) * bs) + off; \
         const bool puse = kd == 2 || (kd == 0 && ln >= 0);                                                \
-        _Pragma("unroll") for (int hf = 0; hf < 2; ++hf) _Pragma("unroll") for (int r = 0; r < 4; ++r) {  \
-            const int i = 16 * wv + M::row(lane, r), q = 8 * hf + qq;                                     \
-            const bool ok = puse && active && i < bs && q < nr;                                           \
-            const int ic = i < bs ? i : bs - 1, qc = q < nr ? q : nr - 1;                                 \
-            pre[hf][r] = psrc[2 * ((long long)(r0 + qc) * etot + off + ic)];                              \
-            pok = ok ? pok | (1u << (4 * hf + r)) : pok & ~(1u << (4 * hf + r));                          \
+        _Pragma("unroll") for (int hf = 0; hf < 2; ++hf) {                                                \
+            const int q = 8 * hf + qq, qc = q < nr ? q : nr - 1;                                          \
+            M::pre_load(pre[hf], psrc + (long long)(r0 + qc) * etot, bs, 16 * wv, lane);                  \
+            _Pragma("unroll") for (int r = 0; r < 4; ++r) {                                               \
+                const int i = 16 * wv + M::row(lane, r);                                                  \
+                const bool ok = puse && active && i < bs && q < nr;                                       \
+                pok = ok ? pok | (1u << (4 * hf + r)) : pok & ~(1u << (4 * hf + r));                      \
+            }                                                                                             \
         }                                                                                                 \
     }
         DDM_MMA_PRE(0)
@@ -178,23 +181,16 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
             // the block index whose V this step forms (none before the
             // two-ended meeting, which forms its own)
             const int lnv = lnv_of(st);
-            // the g / y entries of this step were loaded at the end of the
-            // previous one: make sure they are in before the ring loads of
-            // this step pile up behind them (their wait is then not mixed up
-            // with the ring's)
-#pragma unroll
-            for (int hf = 0; hf < 2; ++hf)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) asm volatile("" ::"v"(pre[hf][r]));
             // ---- D = W_l V on the matrix cores ----
             Acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
             const R *vb = (const R *)vcur + boff;
             const char *cur_b = Wt + (long long)l * bstr_b;
             const char *nxt_b = Wt + (long long)(st + 1 < nsteps ? step_l(st + 1) : l) * bstr_b;
-            // The waits for the g / y entries above already leave no load in
-            // flight, so a full wait costs nothing here; it lets the
+            // Full wait: the g / y entries of this step (loaded at the end of
+            // the previous one, before the barrier) are in, and the first
+            // ring turn, loaded before them, too.  It also lets the
             // compiler's counter analysis wait for one ring load per slot
-            // (7 left in flight).  Without it the analysis carries an unknown
+            // (7 left in flight); without it the analysis carries an unknown
             // older load into the loop and waits for all eight at every turn.
             __builtin_amdgcn_s_waitcnt(0);
             for (int jb = 0; jb < NGP; jb += kMmaRing) {
@@ -227,22 +223,31 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
             // ---- results and the next V ----
             const Coef cn = coef[s.coff[ax] + (lnv >= 0 ? lnv : l)];
             const double2 cf = kind == 0 ? (chain == 0 ? cn.cm : cn.cp) : (chain == 0 ? cn.cp : cn.cm);
+            // the block's results go out through store_half, whole entries
+            // per lane (results stored by one part per lane took 21% of an
+            // FP64 launch and 14% of a complex64 one); the last forward block
+            // of the two-ended layout (read by the partner at the middle)
+            // goes out here, one part per lane with atomic stores, and its
+            // first backward step reads it back in the same lanes
+            const bool store = kind != 1 || chain == 0;  // the middle block's x: chain 0 stores it
+            const bool xchg = twisted && st == nf - 1;
 #pragma unroll
-            for (int hf = 0; hf < 2; ++hf)
+            for (int hf = 0; hf < 2; ++hf) {
+                R resv[4], othv[4], pvv[4];
+                M::pre_parts(pvv, pre[hf], bs, 16 * wv, lane);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = 16 * wv + M::row(lane, r), q = 8 * hf + qq;
                     const R y = hf == 0 ? acc0[r] : acc1[r];
-                    const R pv = (pok >> (4 * hf + r)) & 1u ? pre[hf][r] : R(0);
+                    const R pv = (pok >> (4 * hf + r)) & 1u ? pvv[r] : R(0);
                     const R res = kind == 2 ? pv - y : y;  // forward y_l, middle x_mid, backward x_l
                     const R oth = shfl_xor1(res);                  // the other part of the same entry
+                    resv[r] = res;
+                    othv[r] = oth;
                     if (!(active && i < bs)) continue;
                     const double re = p ? (double)oth : (double)res, im = p ? (double)res : (double)oth;
-                    if (q < nr && (kind != 1 || chain == 0)) {
-                        R *dst = (R *)(x + (long long)(r0 + q) * etot + off + (long long)l * bs + i) + p;
-                        if (twisted && st == nf - 1) xstore_r(dst, res);  // read by the partner at the middle
-                        else *dst = res;
-                    }
+                    if (xchg && store && q < nr)
+                        xstore_r((R *)(x + (long long)(r0 + q) * etot + off + (long long)l * bs + i) + p, res);
                     if (lnv >= 0) {
                         double v = 0.0;
                         if (q < nr) {
@@ -256,6 +261,10 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
                         ((R *)(vnext + i * kMmaRhs + q))[p] = (R)v;
                     }
                 }
+                if (store && !xchg && active)
+                    M::store_half(x + (long long)(r0 + 8 * hf) * etot + off + (long long)l * bs + 16 * wv, etot,
+                                  bs - 16 * wv, nr - 8 * hf, lane, resv, othv);
+            }
             // the next step's g / y entries, in flight over the barrier
             if (st + 1 < nsteps) DDM_MMA_PRE(st + 1)
             __syncthreads();
