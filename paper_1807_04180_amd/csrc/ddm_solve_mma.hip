@@ -114,7 +114,7 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
         {
             const char *b0 = Wt + (long long)step_l(0) * bstr_b;
 #pragma unroll
-            for (int u = 0; u < kMmaRing; ++u) ring[u] = *(const LT *)(b0 + (long long)(u < NG ? u : NG - 1) * grp_b);
+            for (int u = 0; u < kMmaRing; ++u) ring[u] = M::load_op(b0 + (long long)(u < NG ? u : NG - 1) * grp_b);
         }
 
         // per lane and half: the g_lnv (forward) or y_l (backward) entries
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
                     }
                     // refill this ring slot with the item kMmaRing ahead
                     const int gi = g0 + u < NG ? g0 + u : NG - 1;
-                    ring[u] = *(const LT *)(rb + (long long)gi * grp_b);
+                    ring[u] = M::load_op(rb + (long long)gi * grp_b);
                 }
             }
             // the first backward step overwrites the y block the partner read
