@@ -1121,7 +1121,7 @@ def main():
     achieved = sub["bytes"] / (sub["ms"] * 1e-3) / 1e9 if sub["ms"] > 0 else 0.0
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": recorded_traffic(s64.solve_variant(), "2d1024_fp64") if args.workload == "2d-1024" else None,
+                       "traffic": recorded_traffic(s64.solve_variant(), "2d1024") if args.workload == "2d-1024" else None,
                        "kernel": SUBST_KERNELS[s64.solve_variant()] + " (block substitution)",
                        "avg_launch_us": avg_us, "launches": sub["launches"],
                        "bytes_per_launch": sub["bytes"] / max(sub["launches"], 1)}
