@@ -227,8 +227,8 @@ __global__ __launch_bounds__(NTB) void k_solve_mma(const SubDesc *__restrict__ s
             // per lane (results stored by one part per lane took 21% of an
             // FP64 launch and 14% of a complex64 one); the last forward block
             // of the two-ended layout (read by the partner at the middle)
-            // goes out here, one part per lane with atomic stores, and its
-            // first backward step reads it back in the same lanes
+            // goes out here, one part per lane with atomic stores, and the
+            // first backward step reads it back in the same lane pairs
             const bool store = kind != 1 || chain == 0;  // the middle block's x: chain 0 stores it
             const bool xchg = twisted && st == nf - 1;
 #pragma unroll
