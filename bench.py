@@ -953,8 +953,8 @@ def run_study(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["layered-2048", "2d-1024", "2d-80", "2d-2048-layered", "serve", "3d-96"],
                     default="layered-2048",
                     help="layered-2048 (default, the headline): 2D layered 2048^2 16x16, 16 RHS, mixed FGMRES beside "
