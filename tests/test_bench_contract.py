@@ -101,3 +101,17 @@ def test_overlap_report_on_a_synthetic_trace(tmp_path):
     assert abs(rep["overlapped_share_by_class"]["substitution"] - 0.5) < 1e-12
     assert abs(rep["overlapped_share_by_class"]["transfer"] - 0.5) < 1e-12
     assert rep["overlapped_share_by_class"]["residual"] == 0.0
+
+
+def test_traffic_lookups_name_committed_records():
+    """Every traffic record bench.py looks up (the tag of each
+    recorded_traffic call, with the variant its workload runs) is a committed
+    file under profiles/: a lookup under another tag would report no
+    traffic even with the counters taken."""
+    import re
+    with open(os.path.join(ROOT, "bench.py")) as fh:
+        tags = set(re.findall(r'recorded_traffic\([^,]+,\s*"([^"]+)"\)', fh.read()))
+    assert tags == {"layered2048_c64", "2d1024"}
+    for variant, tag in (("mma", "layered2048_c64"), ("chain2", "2d1024")):
+        path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (bench.SUBST_KERNELS[variant], tag))
+        assert os.path.exists(path), path
