@@ -204,24 +204,38 @@ __device__ inline long long glob_index(const PackArgs &A, int px, int py, int pz
 
 // ---------------------------------------------------------------------------
 // Step-1 sources: g_a = f on the core of a, 0 elsewhere.
-// grid: (ceil(max box / 256), nsub, nrhs)
+// grid: (grid rows of the largest box, nsub, RHS tiles of kRestrictRQ): one
+// workgroup per box row and RHS tile, the loads of the tile's RHS in flight
+// together (one workgroup per row and RHS made the launch bound by the
+// workgroup dispatch: 0.65 ms for the 2048^2 batch of 16 RHS)
 // ---------------------------------------------------------------------------
+constexpr int kRestrictRQ = 8;
 template <typename TIN, typename TOUT>
 __global__ __launch_bounds__(kBlock) void k_restrict(const SubDesc *__restrict__ subs, const TIN *__restrict__ f,
-                                                     TOUT *__restrict__ g, PackArgs A) {
-    const int a = blockIdx.y, rhs = blockIdx.z;
+                                                     TOUT *__restrict__ g, PackArgs A, int nrhs) {
+    const int a = blockIdx.y, r0 = blockIdx.z * kRestrictRQ;
+    const int nr = nrhs - r0 < kRestrictRQ ? nrhs - r0 : kRestrictRQ;
     const SubDesc &s = subs[a];
     const int rowi = blockIdx.x;  // ly + n1 * lz
     if (rowi >= s.n[1] * s.n[2]) return;
     const int ly = rowi % s.n[1], lz = rowi / s.n[1];
     const int p1 = s.lo[1] + ly, p2 = s.lo[2] + lz;
     const bool rowcore = p1 >= s.clo[1] && p1 <= s.chi[1] && p2 >= s.clo[2] && p2 <= s.chi[2];
-    TOUT *gr = g + rhs * A.etot + s.off + (long long)rowi * s.n[0];
+    TOUT *gr = g + (long long)r0 * A.etot + s.off + (long long)rowi * s.n[0];
     for (int lx = threadIdx.x; lx < s.n[0]; lx += kBlock) {
         const int p0 = s.lo[0] + lx;
-        double2 v = make_double2(0, 0);
-        if (rowcore && p0 >= s.clo[0] && p0 <= s.chi[0]) v = to_d2(f[rhs * A.nglob + glob_index(A, p0, p1, p2)]);
-        gr[lx] = from_d2<TOUT>(v);
+        const bool core = rowcore && p0 >= s.clo[0] && p0 <= s.chi[0];
+        // nodes outside the core read node 0 (always there) and store 0
+        const long long gi = core ? glob_index(A, p0, p1, p2) : 0;
+        TIN v[kRestrictRQ];
+#pragma unroll
+        for (int q = 0; q < kRestrictRQ; ++q) {
+            const int qc = q < nr ? q : nr - 1;
+            v[q] = f[(long long)(r0 + qc) * A.nglob + gi];
+        }
+#pragma unroll
+        for (int q = 0; q < kRestrictRQ; ++q)
+            if (q < nr) gr[(long long)q * A.etot + lx] = from_d2<TOUT>(core ? to_d2(v[q]) : make_double2(0, 0));
     }
 }
 
@@ -586,8 +600,8 @@ template <typename TIN, typename TOUT>
 hipError_t launch_restrict(ddm_handle *h, const TIN *f, TOUT *g, int nrhs) {
     const Plan &P = h->plan;
     if (in_source_ws(h, g)) h->g_clean_rows = 0;  // cores written
-    dim3 grid((unsigned)max_rows(P), P.nsub, nrhs);
-    k_restrict<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, f, g, pack_args(P));
+    dim3 grid((unsigned)max_rows(P), P.nsub, (nrhs + kRestrictRQ - 1) / kRestrictRQ);
+    k_restrict<TIN, TOUT><<<grid, kBlock, 0, h->stream>>>(h->d_subs, f, g, pack_args(P), nrhs);
     return hipGetLastError();
 }
 
@@ -601,8 +615,8 @@ hipError_t launch_transfer(ddm_handle *h, const TIN *l1, const TIN *l2, const TI
         for (int d = 0; d < P.dim; ++d) strip += 2.0 * (P.n_ov + 1) * (double)sd.nloc / sd.n[d];
     ProfScope ps(h, DDM_K_TRANSFER, (double)nrhs * ((double)P.etot * sizeof(TOUT) + strip * sizeof(TIN)));
     if (rcorr) {
-        dim3 rg((unsigned)max_rows(P), P.nsub, nrhs);
-        k_restrict<double2, TOUT><<<rg, kBlock, 0, h->stream>>>(h->d_subs, rcorr, g, pack_args(P));
+        dim3 rg((unsigned)max_rows(P), P.nsub, (nrhs + kRestrictRQ - 1) / kRestrictRQ);
+        k_restrict<double2, TOUT><<<rg, kBlock, 0, h->stream>>>(h->d_subs, rcorr, g, pack_args(P), nrhs);
         if (in_source_ws(h, g)) h->g_clean_rows = 0;
     } else if (!((void *)g == h->d_g && h->g_clean_rows >= nrhs)) {
         // the strip kernel writes only strip nodes: everything else must be
