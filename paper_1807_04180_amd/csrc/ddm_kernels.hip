@@ -43,30 +43,38 @@ struct GridArgs {
     long long nglob;
 };
 
+// The node's loads are issued together (clamped in-bounds indices; a missing
+// neighbour's value is replaced by 0 afterwards, as if it had not been read),
+// so that they are waited for once per node and not once per axis.
 __device__ inline double2 apply_global_at(const double2 *__restrict__ u, const double *__restrict__ k2,
                                           const Coef *__restrict__ gc, const GridArgs &g, long long idx, int x,
                                           int y, int z) {
-    double2 uc = u[idx];
-    double2 Lu = cscale(uc, k2[idx]);
+    const double2 zero = make_double2(0, 0);
+    const long long s1 = g.G0;
+    const bool xp = x + 1 < g.G0, xm = x > 0;
+    const bool yp = g.dim >= 2 && y + 1 < g.G1, ym = g.dim >= 2 && y > 0;
+    const double2 uc = u[idx];
+    const double kk = k2[idx];
+    const double2 uxp = u[xp ? idx + 1 : idx], uxm = u[xm ? idx - 1 : idx];
+    const double2 uyp = u[yp ? idx + s1 : idx], uym = u[ym ? idx - s1 : idx];
+    const Coef cx = gc[g.c0 + x];
+    const Coef cy = gc[g.dim >= 2 ? g.c1 + y : g.c0];
+    double2 Lu = cscale(uc, kk);
     {
-        Coef c = gc[g.c0 + x];
-        double2 up = x + 1 < g.G0 ? u[idx + 1] : make_double2(0, 0);
-        double2 um = x > 0 ? u[idx - 1] : make_double2(0, 0);
-        Lu = cadd(Lu, csub(cmul(c.cp, csub(up, uc)), cmul(c.cm, csub(uc, um))));
+        const double2 up = xp ? uxp : zero, um = xm ? uxm : zero;
+        Lu = cadd(Lu, csub(cmul(cx.cp, csub(up, uc)), cmul(cx.cm, csub(uc, um))));
     }
     if (g.dim >= 2) {
-        Coef c = gc[g.c1 + y];
-        long long s = g.G0;
-        double2 up = y + 1 < g.G1 ? u[idx + s] : make_double2(0, 0);
-        double2 um = y > 0 ? u[idx - s] : make_double2(0, 0);
-        Lu = cadd(Lu, csub(cmul(c.cp, csub(up, uc)), cmul(c.cm, csub(uc, um))));
+        const double2 up = yp ? uyp : zero, um = ym ? uym : zero;
+        Lu = cadd(Lu, csub(cmul(cy.cp, csub(up, uc)), cmul(cy.cm, csub(uc, um))));
     }
     if (g.dim >= 3) {
-        Coef c = gc[g.c2 + z];
-        long long s = (long long)g.G0 * g.G1;
-        double2 up = z + 1 < g.G2 ? u[idx + s] : make_double2(0, 0);
-        double2 um = z > 0 ? u[idx - s] : make_double2(0, 0);
-        Lu = cadd(Lu, csub(cmul(c.cp, csub(up, uc)), cmul(c.cm, csub(uc, um))));
+        const long long s2 = (long long)g.G0 * g.G1;
+        const bool zp = z + 1 < g.G2, zm = z > 0;
+        const double2 uzp = u[zp ? idx + s2 : idx], uzm = u[zm ? idx - s2 : idx];
+        const Coef cz = gc[g.c2 + z];
+        const double2 up = zp ? uzp : zero, um = zm ? uzm : zero;
+        Lu = cadd(Lu, csub(cmul(cz.cp, csub(up, uc)), cmul(cz.cm, csub(uc, um))));
     }
     return Lu;
 }
@@ -99,9 +107,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const double2 *__restrict__ 
     double rn = 0.0, fn = 0.0;
     for (int x = threadIdx.x; x < g.G0; x += kBlock) {
         const long long idx = row0 + x;
+        // f is loaded with the stencil's values (mode 1 reads u's own entry)
+        const double2 fv = MODE == 0 ? f[rhs * g.nglob + idx] : make_double2(0, 0);
         double2 Lu = apply_global_at(ur, k2, gc, g, idx, x, y, z);
         if (MODE == 0) {
-            double2 fv = f[rhs * g.nglob + idx];
             double2 rv = csub(fv, Lu);
             if (out) out[rhs * g.nglob + idx] = rv;
             rn += cabs2(rv);
