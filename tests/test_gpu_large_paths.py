@@ -103,7 +103,7 @@ def test_fgmres_3d_matches_global_solve(mixed):
 
 
 @pytest.mark.parametrize("mixed", [False, True])
-@pytest.mark.parametrize("K", [1, 2])
+@pytest.mark.parametrize("K", [1, 2, 3])
 def test_fgmres_small_K(K, mixed):
     w = di.small_2d(M=192, N=(3, 3), n_pml=7, n_ov=5, nrhs=3, layered=True, seed=4)
     o, g = _pair(w, w.nrhs, mixed=mixed)
